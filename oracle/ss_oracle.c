@@ -1,0 +1,418 @@
+/*
+ * Oracle (test infrastructure only): plain, slow, sequential FP64 reference
+ * for the sub-structured Conjugate Gradient.  Only tests/, the smoke check and
+ * the bench's CPU-baseline leg may load it.  It shares no code with the HIP
+ * library.  Built with -O2 -ffp-contract=off: every a*b+c below is a rounded
+ * product followed by a rounded sum, in the order written.
+ *
+ * Paper: "Parallel Sub-Structuring Methods for solving Sparse Linear Systems
+ * on a cluster of GPU" (Cheik Ahamed, Magoules).
+ *   - CSR storage: Section 2.2.
+ *   - Sub-structured SpMV = local SpMV in every sub-domain, then assembly of
+ *     the interface contributions (y_3 = y_3^(1) + y_3^(2)): Section 4.4.1.
+ *   - Interface exchange "collect" (Algorithm 4) and "receive and update"
+ *     (Algorithm 5); a node on several interfaces receives every contribution:
+ *     Section 4.4.2.
+ *   - Dot products: weighted local sums then a global sum: Section 4.4.2.
+ *   - CG: Algorithm 3 with M = I.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+enum { ORC_OK = 0, ORC_NOT_CONVERGED = 1, ORC_EINVAL = -1, ORC_ENOMEM = -2, ORC_EBREAKDOWN = -4 };
+
+/* ---------------------------------------------------------------------- */
+/* CSR products (Section 2.2): row i sums a_ik * x_k left to right.        */
+/* ---------------------------------------------------------------------- */
+
+void orc_csr_matvec(int64_t n, const int32_t *rowptr, const int32_t *colidx, const double *val,
+                    const double *x, double *y)
+{
+    for (int64_t i = 0; i < n; ++i) {
+        double s = 0.0;
+        for (int64_t k = rowptr[i]; k < rowptr[i + 1]; ++k)
+            s = s + val[k] * x[colidx[k]];
+        y[i] = s;
+    }
+}
+
+void orc_csr_matvec_f32(int64_t n, const int32_t *rowptr, const int32_t *colidx, const float *val,
+                        const float *x, float *y)
+{
+    for (int64_t i = 0; i < n; ++i) {
+        float s = 0.0f;
+        for (int64_t k = rowptr[i]; k < rowptr[i + 1]; ++k)
+            s = s + val[k] * x[colidx[k]];
+        y[i] = s;
+    }
+}
+
+/* ---------------------------------------------------------------------- */
+/* Interface assembly (Algorithms 4 and 5 on one address space).           */
+/* For every interface node, its copies (one per sub-domain that holds it, */
+/* ascending sub-domain id) are added left to right and the total is       */
+/* written back to every copy, so all copies hold the assembled value.     */
+/* ---------------------------------------------------------------------- */
+
+void orc_iface_sum(int64_t ngamma, const int32_t *copy_ptr, const int32_t *copy_pos, double *q)
+{
+    for (int64_t g = 0; g < ngamma; ++g) {
+        double t = 0.0;
+        for (int64_t c = copy_ptr[g]; c < copy_ptr[g + 1]; ++c)
+            t = t + q[copy_pos[c]];
+        for (int64_t c = copy_ptr[g]; c < copy_ptr[g + 1]; ++c)
+            q[copy_pos[c]] = t;
+    }
+}
+
+void orc_iface_sum_f32(int64_t ngamma, const int32_t *copy_ptr, const int32_t *copy_pos, float *q)
+{
+    for (int64_t g = 0; g < ngamma; ++g) {
+        float t = 0.0f;
+        for (int64_t c = copy_ptr[g]; c < copy_ptr[g + 1]; ++c)
+            t = t + q[copy_pos[c]];
+        for (int64_t c = copy_ptr[g]; c < copy_ptr[g + 1]; ++c)
+            q[copy_pos[c]] = t;
+    }
+}
+
+/* ---------------------------------------------------------------------- */
+/* Dot products                                                            */
+/* ---------------------------------------------------------------------- */
+
+double orc_dot(int64_t n, const double *u, const double *v)
+{
+    double s = 0.0;
+    for (int64_t i = 0; i < n; ++i)
+        s = s + u[i] * v[i];
+    return s;
+}
+
+/* Weighted local dot: every node counts once.  The weights are the 0/1
+ * owner mask: sub-domain s counts its interior and owned-interface
+ * positions [sub_off[s], sub_off[s] + n_int[s] + n_own[s]). */
+double orc_owned_dot(int32_t P, const int32_t *sub_off, const int32_t *n_int, const int32_t *n_own,
+                     const double *u, const double *v)
+{
+    double s = 0.0;
+    for (int32_t p = 0; p < P; ++p)
+        for (int64_t i = sub_off[p]; i < (int64_t)sub_off[p] + n_int[p] + n_own[p]; ++i)
+            s = s + u[i] * v[i];
+    return s;
+}
+
+double orc_owned_dot_f32(int32_t P, const int32_t *sub_off, const int32_t *n_int, const int32_t *n_own,
+                         const float *u, const float *v)
+{
+    double s = 0.0;
+    for (int32_t p = 0; p < P; ++p)
+        for (int64_t i = sub_off[p]; i < (int64_t)sub_off[p] + n_int[p] + n_own[p]; ++i)
+            s = s + (double)u[i] * (double)v[i];
+    return s;
+}
+
+/* ---------------------------------------------------------------------- */
+/* Sub-domain description                                                  */
+/* ---------------------------------------------------------------------- */
+
+typedef struct {
+    int32_t P;
+    int32_t n_loc;
+    const int32_t *sub_off, *n_int, *n_own, *l2g;
+    int32_t ngamma;
+    const int32_t *copy_ptr, *copy_pos;
+    const int32_t *bd_rowptr, *bd_colidx;
+    const double *bd_val;  /* FP64 local values */
+    const float *bd_val32; /* FP32 local values (may be NULL) */
+} orc_sub;
+
+/* Sub-structured SpMV, Section 4.4.1: local products, then interface assembly. */
+void orc_ss_spmv(const orc_sub *S, const double *x, double *q)
+{
+    orc_csr_matvec(S->n_loc, S->bd_rowptr, S->bd_colidx, S->bd_val, x, q);
+    orc_iface_sum(S->ngamma, S->copy_ptr, S->copy_pos, q);
+}
+
+static void ss_spmv_f32(const orc_sub *S, const float *x, float *q)
+{
+    orc_csr_matvec_f32(S->n_loc, S->bd_rowptr, S->bd_colidx, S->bd_val32, x, q);
+    orc_iface_sum_f32(S->ngamma, S->copy_ptr, S->copy_pos, q);
+}
+
+/* ---------------------------------------------------------------------- */
+/* CG, Algorithm 3 with M = I, on an abstract operator                     */
+/* ---------------------------------------------------------------------- */
+
+typedef struct {
+    int64_t n;
+    void (*apply)(const void *ctx, const double *x, double *y);
+    double (*dot)(const void *ctx, const double *u, const double *v);
+    const void *ctx;
+} orc_op;
+
+/*
+ * Stopping rule (not stated in the paper; reading adopted): stop when
+ * ||r||_2 <= tol * ||b||_2.  When the recurrence reports convergence the
+ * residual is recomputed as b - A x (that is also how the first residual
+ * r_1 = f - S x_1 is formed); if the recomputed residual still exceeds the
+ * tolerance, CG restarts from it with p = r.  maxit bounds the total number
+ * of CG iterations.  hist[k] = ||r_k|| / ||b||; when a residual is
+ * recomputed at iteration k it replaces hist[k].
+ */
+static int cg_core(const orc_op *A, const double *b, double *x, double tol, int32_t maxit,
+                   double *hist, int32_t *iters, double *relres)
+{
+    const int64_t n = A->n;
+    double *r = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    double *p = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    double *q = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    int status = ORC_OK;
+    int32_t k = 0;
+    double rr = 0.0;
+    if (!r || !p || !q) { status = ORC_ENOMEM; goto done; }
+
+    const double bb = A->dot(A->ctx, b, b);
+    if (!isfinite(bb)) { status = ORC_EBREAKDOWN; goto done; }
+    if (bb == 0.0) {
+        for (int64_t i = 0; i < n; ++i) x[i] = 0.0;
+        if (hist) hist[0] = 0.0;
+        *relres = 0.0;
+        goto done;
+    }
+    const double stop = tol * sqrt(bb);
+
+    for (;;) {
+        /* r = b - A x, p = r */
+        A->apply(A->ctx, x, q);
+        for (int64_t i = 0; i < n; ++i) r[i] = b[i] - q[i];
+        for (int64_t i = 0; i < n; ++i) p[i] = r[i];
+        rr = A->dot(A->ctx, r, r);
+        if (!isfinite(rr)) { status = ORC_EBREAKDOWN; goto done; }
+        if (hist) hist[k] = sqrt(rr / bb);
+        if (sqrt(rr) <= stop) { status = ORC_OK; break; }
+        if (k >= maxit) { status = ORC_NOT_CONVERGED; break; }
+
+        while (sqrt(rr) > stop && k < maxit) {
+            A->apply(A->ctx, p, q);                         /* S p_k          */
+            const double pq = A->dot(A->ctx, p, q);         /* (S p_k, p_k)   */
+            if (!(pq > 0.0) || !isfinite(pq)) { status = ORC_EBREAKDOWN; goto done; }
+            const double alpha = rr / pq;                   /* alpha_k        */
+            for (int64_t i = 0; i < n; ++i) x[i] = x[i] + alpha * p[i];
+            for (int64_t i = 0; i < n; ++i) r[i] = r[i] - alpha * q[i];
+            const double rr1 = A->dot(A->ctx, r, r);
+            if (!isfinite(rr1)) { status = ORC_EBREAKDOWN; goto done; }
+            const double beta = rr1 / rr;                   /* beta_k         */
+            for (int64_t i = 0; i < n; ++i) p[i] = r[i] + beta * p[i];
+            rr = rr1;
+            ++k;
+            if (hist) hist[k] = sqrt(rr / bb);
+        }
+    }
+    *relres = sqrt(rr / bb);
+done:
+    *iters = k;
+    free(r); free(p); free(q);
+    return status;
+}
+
+/* global operator */
+typedef struct { int64_t n; const int32_t *rowptr, *colidx; const double *val; } csr_ctx;
+
+static void glob_apply(const void *c, const double *x, double *y)
+{
+    const csr_ctx *A = (const csr_ctx *)c;
+    orc_csr_matvec(A->n, A->rowptr, A->colidx, A->val, x, y);
+}
+static double glob_dot(const void *c, const double *u, const double *v)
+{
+    return orc_dot(((const csr_ctx *)c)->n, u, v);
+}
+
+/* sub-structured operator */
+static void ss_apply(const void *c, const double *x, double *y) { orc_ss_spmv((const orc_sub *)c, x, y); }
+static double ss_dot(const void *c, const double *u, const double *v)
+{
+    const orc_sub *S = (const orc_sub *)c;
+    return orc_owned_dot(S->P, S->sub_off, S->n_int, S->n_own, u, v);
+}
+
+static double true_relres(int64_t n, const int32_t *rowptr, const int32_t *colidx, const double *val,
+                          const double *b, const double *x)
+{
+    double *t = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    if (!t) return NAN;
+    orc_csr_matvec(n, rowptr, colidx, val, x, t);
+    for (int64_t i = 0; i < n; ++i) t[i] = b[i] - t[i];
+    const double rr = orc_dot(n, t, t), bb = orc_dot(n, b, b);
+    free(t);
+    return bb == 0.0 ? 0.0 : sqrt(rr) / sqrt(bb);
+}
+
+/* CG on the unsplit global matrix. */
+int orc_cg(int64_t n, const int32_t *rowptr, const int32_t *colidx, const double *val,
+           const double *b, double *x, double tol, int32_t maxit,
+           double *hist, int32_t *iters, double *relres, double *true_rr)
+{
+    csr_ctx c = {n, rowptr, colidx, val};
+    orc_op op = {n, glob_apply, glob_dot, &c};
+    int st = cg_core(&op, b, x, tol, maxit, hist, iters, relres);
+    *true_rr = true_relres(n, rowptr, colidx, val, b, x);
+    return st;
+}
+
+/* Local copies of a global vector: every copy of node i gets v[i]. */
+static void gather(const orc_sub *S, const double *v, double *loc)
+{
+    for (int64_t c = 0; c < S->n_loc; ++c) loc[c] = v[S->l2g[c]];
+}
+
+/* Global vector from the owned positions (each node has exactly one). */
+static void scatter_owned(const orc_sub *S, const double *loc, double *v)
+{
+    for (int32_t p = 0; p < S->P; ++p)
+        for (int64_t c = S->sub_off[p]; c < (int64_t)S->sub_off[p] + S->n_int[p] + S->n_own[p]; ++c)
+            v[S->l2g[c]] = loc[c];
+}
+
+/* Sub-structured CG: Algorithm 3 where every product by S is the
+ * sub-structured SpMV and every dot product the weighted local sum. */
+int orc_ss_cg(const orc_sub *S, int64_t n, const int32_t *rowptr, const int32_t *colidx,
+              const double *val, const double *b, double *x, double tol, int32_t maxit,
+              double *hist, int32_t *iters, double *relres, double *true_rr)
+{
+    double *bl = (double *)malloc(sizeof(double) * (size_t)(S->n_loc > 0 ? S->n_loc : 1));
+    double *xl = (double *)malloc(sizeof(double) * (size_t)(S->n_loc > 0 ? S->n_loc : 1));
+    if (!bl || !xl) { free(bl); free(xl); return ORC_ENOMEM; }
+    gather(S, b, bl);
+    gather(S, x, xl);
+    orc_op op = {S->n_loc, ss_apply, ss_dot, S};
+    int st = cg_core(&op, bl, xl, tol, maxit, hist, iters, relres);
+    scatter_owned(S, xl, x);
+    *true_rr = true_relres(n, rowptr, colidx, val, b, x);
+    free(bl); free(xl);
+    return st;
+}
+
+/* ---------------------------------------------------------------------- */
+/* FP32 values + FP64 iterative refinement (project variant)              */
+/*                                                                         */
+/* Outer: r = b - A x with FP64 values and vectors; stop when ||r|| <=     */
+/* tol ||b||.  Inner: CG on the FP32 copy of the local values with FP32    */
+/* vectors, FP32 products and sums inside the SpMV and the assembly, FP64  */
+/* dot products and scalars; vector updates are evaluated in FP64 and      */
+/* rounded to FP32.  The inner right-hand side is r / ||r||; the inner     */
+/* solve stops at ||r_in|| <= inner_tol ||r_in,0|| or inner_maxit.         */
+/* ---------------------------------------------------------------------- */
+
+int orc_ss_ir(const orc_sub *S, int64_t n, const int32_t *rowptr, const int32_t *colidx,
+              const double *val, const double *b, double *x, double tol, int32_t maxit,
+              double inner_tol, int32_t inner_maxit, int32_t max_outer,
+              int32_t *iters, int32_t *outer, double *relres, double *true_rr)
+{
+    const int64_t m = S->n_loc > 0 ? S->n_loc : 1;
+    double *bl = malloc(sizeof(double) * m), *xl = malloc(sizeof(double) * m), *r = malloc(sizeof(double) * m);
+    float *d = malloc(sizeof(float) * m), *ri = malloc(sizeof(float) * m), *p = malloc(sizeof(float) * m),
+          *q = malloc(sizeof(float) * m);
+    int st = ORC_OK;
+    int32_t k = 0, j = 0;
+    double rr = 0.0;
+    if (!bl || !xl || !r || !d || !ri || !p || !q) { st = ORC_ENOMEM; goto out; }
+    gather(S, b, bl);
+    gather(S, x, xl);
+    const double bb = orc_owned_dot(S->P, S->sub_off, S->n_int, S->n_own, bl, bl);
+    if (!isfinite(bb)) { st = ORC_EBREAKDOWN; goto out; }
+    if (bb == 0.0) { for (int64_t i = 0; i < S->n_loc; ++i) xl[i] = 0.0; *relres = 0.0; goto out; }
+    for (;; ++j) {
+        orc_ss_spmv(S, xl, r);
+        for (int64_t i = 0; i < S->n_loc; ++i) r[i] = bl[i] - r[i];
+        rr = orc_owned_dot(S->P, S->sub_off, S->n_int, S->n_own, r, r);
+        if (!isfinite(rr)) { st = ORC_EBREAKDOWN; goto out; }
+        if (sqrt(rr) <= tol * sqrt(bb)) { st = ORC_OK; break; }
+        if (j >= max_outer || k >= maxit) { st = ORC_NOT_CONVERGED; break; }
+        const double s = sqrt(rr);
+        for (int64_t i = 0; i < S->n_loc; ++i) {
+            ri[i] = (float)(r[i] / s);
+            p[i] = ri[i];
+            d[i] = 0.0f;
+        }
+        double rr_in = orc_owned_dot_f32(S->P, S->sub_off, S->n_int, S->n_own, ri, ri);
+        const double stop_in = inner_tol * sqrt(rr_in);
+        int32_t kin = 0;
+        while (sqrt(rr_in) > stop_in && kin < inner_maxit && k < maxit) {
+            ss_spmv_f32(S, p, q);
+            const double pq = orc_owned_dot_f32(S->P, S->sub_off, S->n_int, S->n_own, p, q);
+            if (!(pq > 0.0) || !isfinite(pq)) { st = ORC_EBREAKDOWN; goto out; }
+            const double alpha = rr_in / pq;
+            for (int64_t i = 0; i < S->n_loc; ++i) {
+                d[i] = (float)((double)d[i] + alpha * (double)p[i]);
+                ri[i] = (float)((double)ri[i] - alpha * (double)q[i]);
+            }
+            const double rr1 = orc_owned_dot_f32(S->P, S->sub_off, S->n_int, S->n_own, ri, ri);
+            if (!isfinite(rr1)) { st = ORC_EBREAKDOWN; goto out; }
+            const double beta = rr1 / rr_in;
+            for (int64_t i = 0; i < S->n_loc; ++i) p[i] = (float)((double)ri[i] + beta * (double)p[i]);
+            rr_in = rr1;
+            ++kin;
+            ++k;
+        }
+        for (int64_t i = 0; i < S->n_loc; ++i) xl[i] = xl[i] + s * (double)d[i];
+    }
+    *relres = sqrt(rr / bb);
+out:
+    if (st != ORC_ENOMEM) {
+        scatter_owned(S, xl, x);
+        *true_rr = true_relres(n, rowptr, colidx, val, b, x);
+    }
+    *iters = k;
+    *outer = j;
+    free(bl); free(xl); free(r); free(d); free(ri); free(p); free(q);
+    return st;
+}
+
+/* ---------------------------------------------------------------------- */
+/* Adjoint gradient on the stored pattern: for x = A^{-1} b and            */
+/* lambda = A^{-1} dL/dx, dL/da_ij = -lambda_i x_j for every stored entry  */
+/* taken as an independent parameter.                                      */
+/* ---------------------------------------------------------------------- */
+
+void orc_grad_vals(int64_t n, const int32_t *rowptr, const int32_t *colidx,
+                   const double *lambda, const double *x, double *dvals)
+{
+    for (int64_t i = 0; i < n; ++i)
+        for (int64_t k = rowptr[i]; k < rowptr[i + 1]; ++k)
+            dvals[k] = -(lambda[i] * x[colidx[k]]);
+}
+
+/* ---------------------------------------------------------------------- */
+/* Dense Cholesky A = L L^T and the two triangular solves (tiny systems).  */
+/* a is n*n row-major and is overwritten by L in its lower triangle.       */
+/* ---------------------------------------------------------------------- */
+
+int orc_chol_solve(int64_t n, double *a, const double *b, double *x)
+{
+    for (int64_t j = 0; j < n; ++j) {
+        double d = a[j * n + j];
+        for (int64_t k = 0; k < j; ++k) d = d - a[j * n + k] * a[j * n + k];
+        if (!(d > 0.0)) return ORC_EBREAKDOWN;
+        const double ljj = sqrt(d);
+        a[j * n + j] = ljj;
+        for (int64_t i = j + 1; i < n; ++i) {
+            double s = a[i * n + j];
+            for (int64_t k = 0; k < j; ++k) s = s - a[i * n + k] * a[j * n + k];
+            a[i * n + j] = s / ljj;
+        }
+    }
+    for (int64_t i = 0; i < n; ++i) { /* L y = b */
+        double s = b[i];
+        for (int64_t k = 0; k < i; ++k) s = s - a[i * n + k] * x[k];
+        x[i] = s / a[i * n + i];
+    }
+    for (int64_t i = n - 1; i >= 0; --i) { /* L^T x = y */
+        double s = x[i];
+        for (int64_t k = i + 1; k < n; ++k) s = s - a[k * n + i] * x[k];
+        x[i] = s / a[i * n + i];
+    }
+    return ORC_OK;
+}
