@@ -1,0 +1,244 @@
+/*
+ * ss.h -- C-ABI of the sub-structured Conjugate Gradient library (libss.so)
+ * for AMD Instinct MI355X (gfx950).
+ *
+ * Method: "Parallel Sub-Structuring Methods for solving Sparse Linear Systems
+ * on a cluster of GPU" (Cheik Ahamed, Magoules).  A sparse symmetric
+ * positive-definite system A x = b stored in CSR (Section 2.2) is split into
+ * sub-domains (sub-structuring splitting, Section 3.4) and solved by CG
+ * (Algorithm 3).  Every product by A is a local SpMV in each sub-domain
+ * followed by the assembly of the interface contributions (Section 4.4.1,
+ * Algorithms 4 and 5); dot products are weighted local sums followed by a
+ * global sum (Section 4.4.2).  All sub-domains of a partition are resident on
+ * one GPU: the interface exchange is an on-device gather-sum and the global
+ * sums are on-device reductions.
+ *
+ * Conventions for every entry point:
+ *  - 0-based int32 indices; FP64 values unless stated.
+ *  - "host" pointers are ordinary CPU memory; "device" pointers are GPU
+ *    memory of the device that was current when the solver was set up.
+ *  - Inputs are borrowed for the duration of the call only; the library
+ *    copies what it keeps.  The caller owns every buffer it passes.
+ *  - Device work is ordered on the HIP stream given to the setup call;
+ *    device input buffers must be ready on that stream, device outputs are
+ *    complete when the call returns (the call synchronises the stream).
+ *  - Handles are not thread-safe; use one handle per host thread / stream.
+ *  - Return value: one of the SS_* status codes below.  On a negative code
+ *    no output is valid unless stated; ss_strerror() gives a message and
+ *    ss_last_error() the detail of the last failure on the calling thread.
+ */
+#ifndef SS_H
+#define SS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---------------------------------------------------------------- status */
+#define SS_OK 0            /* success                                        */
+#define SS_NOT_CONVERGED 1 /* maxit reached; outputs hold the last iterate   */
+#define SS_EINVAL (-1)     /* invalid argument or matrix (see ss_last_error) */
+#define SS_ENOMEM (-2)     /* host or device allocation failed               */
+#define SS_EDEVICE (-3)    /* HIP runtime error                              */
+#define SS_EBREAKDOWN (-4) /* (p, A p) <= 0 or a non-finite scalar: A is not
+                              SPD or the data holds NaN/Inf; x holds the last
+                              finite iterate                                 */
+#define SS_EUNSUPPORTED (-5)
+
+/* ------------------------------------------------------------ matrices */
+/* Global sparse matrix in CSR, host memory: rowptr[n+1] with rowptr[0] = 0
+ * and rowptr[n] = nnz, colidx[nnz] strictly increasing inside each row,
+ * val[nnz].  The paper's IA/JA/AA (Section 2.2), 0-based.  Solver entry
+ * points require a structurally and bitwise-numerically symmetric matrix
+ * (Section 3.4: S is symmetric positive-definite); violations give
+ * SS_EINVAL. */
+typedef struct {
+    int32_t n;
+    int32_t nnz;
+    const int32_t *rowptr;
+    const int32_t *colidx;
+    const double *val;
+} ss_csr;
+
+/* ---------------------------------------------------------- partitions */
+enum {
+    SS_PART_BOX = 0,  /* structured grid cut into boxes                    */
+    SS_PART_RCB = 1,  /* weighted recursive coordinate bisection           */
+    SS_PART_USER = 2  /* node -> sub-domain array given by the caller      */
+};
+
+typedef struct ss_part ss_part;     /* opaque, host memory */
+typedef struct ss_solver ss_solver; /* opaque, owns device buffers */
+
+/*
+ * ss_partition -- pre-processing step, run once per matrix and independent
+ * of the solver (Section 3: data distribution is a separate step; Section
+ * 3.4: sub-structuring splitting).
+ *
+ * 1. Node partition P(i) in [0, nparts):
+ *    BOX : grid[dim] = nodes per axis (node id = x + Mx*(y + My*z), x
+ *          fastest, n must equal the product), boxes[dim] = boxes per axis,
+ *          nparts must equal their product.  Box b along an axis of M nodes
+ *          and B boxes starts at floor(b*M/B).  Part = bx + Bx*(by + By*bz).
+ *    RCB : coords[n*dim] (row-major, host) and weights[nparts] (target
+ *          relative sizes, > 0; NULL = equal).  A node set for the part range
+ *          [lo,hi) is split along its widest axis (ties: lowest axis); nodes
+ *          ordered by (coordinate, id); the first
+ *          floor(|S| * W[lo,mid) / W[lo,hi) + 0.5) go to [lo, mid),
+ *          mid = (lo+hi)/2; weight sums are sequential left to right.
+ *    USER: user_part[n] with values in [0, nparts).
+ *    Unused pointer arguments may be NULL.
+ * 2. Split of the matrix into local matrices A_s (the paper's S_s, whose
+ *    interface block is a partial sum, S_33 = sum_s S_33^(s)): every stored
+ *    entry (i,j) goes to one sub-domain, o(i,j) = P(i) if i == j else
+ *    min(P(i), P(j)), so that sum_s R_s^T A_s R_s == A exactly.
+ *    V_s = {i : P(i) = s} U {i, j : o(i,j) = s}; multiplicity m_i = number
+ *    of sub-domains holding i; interface Gamma = {i : m_i > 1}.
+ * 3. Local numbering, concatenated over sub-domains: sub-domain s occupies
+ *    positions [sub_off[s], sub_off[s+1]) ordered as interior nodes (m = 1),
+ *    then interface nodes it owns (P(i) = s), then the other interface nodes
+ *    it holds, each group ascending by global id.
+ *
+ * Errors: SS_EINVAL for an invalid CSR (see ss_csr), a non-symmetric matrix,
+ * n < 1, nparts outside [1, n], inconsistent grid/boxes, a non-positive or
+ * non-finite weight, a user part out of range.  *out is set only on SS_OK
+ * and is released with ss_part_destroy.
+ */
+int ss_partition(const ss_csr *A, int32_t method, int32_t nparts, int32_t dim, const int32_t *grid,
+                 const int32_t *boxes, const double *coords, const double *weights,
+                 const int32_t *user_part, ss_part **out);
+
+/* Sizes of the maps below (any pointer may be NULL).  n_loc = sum_s |V_s|,
+ * n_copies = sum over interface nodes of m_i, nnz = stored entries (equal
+ * to the sum of the local nnz). */
+int ss_part_sizes(const ss_part *p, int32_t *nparts, int32_t *n, int32_t *n_loc, int32_t *n_gamma,
+                  int32_t *n_copies, int64_t *nnz);
+
+/* Copies the partition maps into caller-provided host arrays (any may be
+ * NULL): part[n], sub_off[nparts+1], n_int[nparts] (interior count),
+ * n_own[nparts] (owned interface count), l2g[n_loc] (global id of each
+ * concatenated position), gamma[n_gamma] (interface nodes ascending),
+ * copy_ptr[n_gamma+1] and copy_pos[n_copies] (positions of the copies of
+ * gamma[g], ascending sub-domain).  These are the lists Algorithms 4 and 5
+ * walk (list_s), flattened for one address space. */
+int ss_part_export(const ss_part *p, int32_t *part, int32_t *sub_off, int32_t *n_int, int32_t *n_own,
+                   int32_t *l2g, int32_t *gamma, int32_t *copy_ptr, int32_t *copy_pos);
+
+/* Copies the block-diagonal CSR of all local matrices (host arrays, any may
+ * be NULL): bd_rowptr[n_loc+1], bd_colidx[nnz] (concatenated positions,
+ * ascending inside each row) and bd_nzmap[nnz] (index of the global stored
+ * entry each local entry takes its value from). */
+int ss_part_export_local(const ss_part *p, int32_t *bd_rowptr, int32_t *bd_colidx, int32_t *bd_nzmap);
+
+void ss_part_destroy(ss_part *p);
+
+/* --------------------------------------------------------------- solver */
+typedef void *(*ss_alloc_fn)(void *ctx, size_t bytes); /* returns device memory or NULL */
+typedef void (*ss_free_fn)(void *ctx, void *ptr);
+
+enum { SS_FP64 = 0, SS_FP32_IR = 1 };
+
+typedef struct {
+    int32_t precision;   /* SS_FP64, or SS_FP32_IR: FP32 values and vectors in
+                            the inner CG, FP64 dots, FP64 residuals and an
+                            outer iterative-refinement loop                    */
+    double inner_tol;    /* IR: inner relative tolerance (<= 0: 1e-5)          */
+    int32_t inner_maxit; /* IR: inner iteration cap (<= 0: unlimited)          */
+    int32_t max_outer;   /* IR: outer iteration cap (<= 0: 50)                 */
+    int32_t check_every; /* CG iterations between host polls (<= 0: 32)        */
+    int32_t use_graph;   /* 1: replay polled chunks as HIP graphs (default);
+                            0: plain launches                                  */
+    int32_t tile_nnz;    /* SpMV tile size in nonzeros: 0 = tuned choice,
+                            else one of 1024, 2048, 4096                      */
+    int32_t fused_reduce; /* 1 (default): the last workgroup of a kernel
+                             finishes its reduction; 0: separate 1-workgroup
+                             kernels                                          */
+    ss_alloc_fn alloc;   /* device allocator; NULL = hipMalloc                 */
+    ss_free_fn free;     /* matching release; NULL = hipFree                   */
+    void *alloc_ctx;
+} ss_opts;
+
+/* Fills *o with the defaults. */
+void ss_opts_default(ss_opts *o);
+
+typedef struct {
+    int32_t status;           /* same as the return value of the solve      */
+    int32_t iterations;       /* CG iterations (IR: inner iterations, total) */
+    int32_t outer_iterations; /* IR outer iterations (0 for SS_FP64)         */
+    int32_t restarts;         /* recomputed-residual restarts               */
+    double relres;            /* ||b - A x|| / ||b|| recomputed at exit      */
+    double true_relres;       /* same quantity, FP64 values and vectors      */
+} ss_result;
+
+/*
+ * ss_cg_setup -- uploads the local matrices, maps and work vectors of
+ * partition p of A to the current HIP device and prepares the kernels.
+ * A must be the matrix p was built from (same n and nnz; values may differ,
+ * the pattern may not).  hip_stream is a hipStream_t (NULL = default
+ * stream).  o may be NULL (defaults).  Device memory comes from o->alloc
+ * when given.  *out is released with ss_cg_destroy.
+ * Errors: SS_EINVAL (A does not match p, bad options), SS_ENOMEM,
+ * SS_EDEVICE.
+ */
+int ss_cg_setup(const ss_csr *A, const ss_part *p, const ss_opts *o, void *hip_stream, ss_solver **out);
+
+/*
+ * ss_cg_solve -- CG (Algorithm 3, M = I) for A x = b.
+ * b_dev[n], x_dev[n]: device, global numbering; x_dev holds the initial
+ * guess x_1 on entry and the solution on return.  Stopping rule (the paper
+ * states none): ||r|| <= tol ||b||, with r recomputed as b - A x whenever the
+ * recurrence reports convergence (restarting CG from it if needed).  At most
+ * maxit CG iterations.  b = 0 returns x = 0 after 0 iterations.
+ * res (host, may be NULL) receives the result; hist_host (host, may be
+ * NULL, capacity maxit+1) receives ||r_k||/||b|| for k = 0..iterations
+ * (at most the first 4194304 entries are recorded).
+ * Returns SS_OK, SS_NOT_CONVERGED, SS_EBREAKDOWN, SS_EINVAL (tol < 0,
+ * maxit < 0), SS_EDEVICE.
+ */
+int ss_cg_solve(ss_solver *s, const double *b_dev, double *x_dev, double tol, int32_t maxit, ss_result *res,
+                double *hist_host);
+
+/* y_dev = A x_dev through the sub-structured path (local SpMV in every
+ * sub-domain, then interface assembly; Section 4.4.1).  Device, global
+ * numbering, length n; y must not alias x. */
+int ss_cg_apply(ss_solver *s, const double *x_dev, double *y_dev);
+
+/* Replaces the matrix values (same pattern): val_dev[nnz], device, global
+ * stored-entry order.  The values must keep A symmetric positive-definite;
+ * symmetry is not re-checked. */
+int ss_cg_set_values(ss_solver *s, const double *val_dev);
+
+/* Adjoint gradient on the stored pattern: with x = A^{-1} b and
+ * lambda = A^{-1} dL/dx (a second solve with the same symmetric A),
+ * dvals_dev[k] = -lambda[row_k] * x[col_k] for every stored entry k, in
+ * global stored-entry order.  lambda_dev[n], x_dev[n], dvals_dev[nnz]:
+ * device.  dL/db equals lambda itself. */
+int ss_cg_grad_vals(ss_solver *s, const double *lambda_dev, const double *x_dev, double *dvals_dev);
+
+/* Average duration in milliseconds of one launch of the local SpMV kernel
+ * (the fused CG-step variant), timed with HIP events around `reps`
+ * back-to-back launches on the solver stream.  Leaves the solver state
+ * unchanged except for scratch vectors.  Also reports the algorithmic bytes
+ * that launch moves (values, column indices, row pointers, one read of the
+ * two input vectors, two output vectors). */
+int ss_cg_time_spmv(ss_solver *s, int32_t reps, double *ms_per_launch, double *bytes_per_launch);
+
+/* Sizes of the device problem (any pointer may be NULL). */
+int ss_cg_info(const ss_solver *s, int32_t *n, int32_t *n_loc, int64_t *nnz, int32_t *ntiles,
+               int32_t *tile_nnz);
+
+void ss_cg_destroy(ss_solver *s);
+
+/* --------------------------------------------------------------- errors */
+const char *ss_strerror(int code);
+const char *ss_last_error(void); /* detail of the last failure on this thread */
+int ss_version(void);            /* 100 * major + minor */
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SS_H */

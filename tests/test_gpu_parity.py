@@ -1,0 +1,276 @@
+"""GPU parity of the FP64 sub-structured CG against the CPU oracle.
+
+Every call goes through libss's C-ABI (via the ctypes binding); the oracle
+runs on the same seeded inputs.  Bars:
+  - sub-structured SpMV + interface assembly: bitwise equal to the oracle
+    (same products, same left-to-right row sums, same ascending assembly);
+  - CG iterates after a fixed number of steps: relative difference <= 1e-12
+    (only the order of the dot-product sums differs);
+  - solves to ||r|| <= 1e-10 ||b||: recomputed residual <= 1e-10 (checked by
+    the oracle's own SpMV), solution within 1e-9 relative of the oracle's,
+    iteration count within 1 of the oracle's.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+import paper_2108_13162_amd as ss
+from workloads import CSR, config, diffusion3d_lognormal, grid_coords, poisson2d, random_spd_csr, uniform_rhs
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+def _t(a):
+    return torch.tensor(np.ascontiguousarray(a, dtype=np.float64), device=DEV)
+
+
+def _np(t):
+    return t.detach().cpu().numpy()
+
+
+def _setup(A, part_ss, **opts):
+    return ss.ss_cg_setup(A, part_ss, ss.default_opts(**opts) if opts else None)
+
+
+def _cases():
+    out = []
+    w = config(1)
+    out.append(("poisson64_box2x2", w.A, ss.partition_workload(w),
+                O.split(w.A.rowptr, w.A.colidx, O.box_partition(w.grid, w.boxes), 4)))
+    A = diffusion3d_lognormal(13, seed=2)
+    out.append(("diff3d13_box3x2x2", A, ss.ss_partition(A, ss.SS_PART_BOX, 12, grid=(13, 13, 13), boxes=(3, 2, 2)),
+                O.split(A.rowptr, A.colidx, O.box_partition((13, 13, 13), (3, 2, 2)), 12)))
+    w3 = config(3, size=11)
+    out.append(("q1hex11_rcb16", w3.A, ss.partition_workload(w3),
+                O.split(w3.A.rowptr, w3.A.colidx, O.rcb_partition(w3.coords, w3.weights), 16)))
+    A = random_spd_csr(777, 9.0, seed=3)
+    part = np.random.default_rng(3).integers(0, 6, A.n).astype(np.int32)
+    out.append(("random777_user6", A, ss.ss_partition(A, ss.SS_PART_USER, 6, user_part=part),
+                O.split(A.rowptr, A.colidx, part, 6)))
+    return out
+
+
+@pytest.fixture(scope="module")
+def cases():
+    return _cases()
+
+
+def test_apply_integer_data_exact(cases):
+    for name, A, p, sd in cases:
+        if not np.all(A.val == np.round(A.val)):
+            continue
+        s = _setup(A, p)
+        x = np.random.default_rng(1).integers(-2**20, 2**20, A.n).astype(np.float64)
+        y = _np(ss.ss_cg_apply(s, _t(x)))
+        exact = (A.to_dense().astype(np.int64) @ x.astype(np.int64)).astype(np.float64)
+        assert np.array_equal(y, exact), name
+
+
+def test_apply_float_data_bitwise_vs_oracle(cases):
+    for name, A, p, sd in cases:
+        s = _setup(A, p)
+        for seed in range(3):
+            x = uniform_rhs(A.n, 1000 + seed)
+            y = _np(ss.ss_cg_apply(s, _t(x)))
+            ref = O.ss_spmv(A, sd, x)
+            assert np.array_equal(y, ref), (name, seed, np.abs(y - ref).max())
+
+
+@pytest.mark.parametrize("tile", [1024, 2048, 4096])
+def test_apply_every_tile_size_and_ragged_tail(tile):
+    # sizes that leave a partly filled last tile and last update block
+    A = diffusion3d_lognormal(17, seed=9)
+    p = ss.ss_partition(A, ss.SS_PART_BOX, 8, grid=(17, 17, 17), boxes=(2, 2, 2))
+    sd = O.split(A.rowptr, A.colidx, O.box_partition((17, 17, 17), (2, 2, 2)), 8)
+    s = _setup(A, p, tile_nnz=tile)
+    x = uniform_rhs(A.n, 5)
+    assert np.array_equal(_np(ss.ss_cg_apply(s, _t(x))), O.ss_spmv(A, sd, x))
+
+
+@pytest.mark.parametrize("k", [1, 7, 50])
+def test_fixed_k_iterates(cases, k):
+    for name, A, p, sd in cases:
+        b = uniform_rhs(A.n, 7)
+        s = _setup(A, p)
+        x = torch.zeros(A.n, dtype=torch.float64, device=DEV)
+        r = ss.ss_cg_solve(s, _t(b), x, tol=0.0, maxit=k, hist=True)
+        xo, ro = O.ss_cg(A, sd, b, tol=0.0, maxit=k)
+        assert r.status == ss.SS_NOT_CONVERGED and r.iterations == k == ro.iterations, name
+        xg = _np(x)
+        assert np.linalg.norm(xg - xo) <= 1e-12 * np.linalg.norm(xo), (name, np.linalg.norm(xg - xo) / np.linalg.norm(xo))
+        assert np.allclose(r.hist, ro.hist, rtol=1e-10, atol=0), name
+
+
+@pytest.mark.parametrize("fused,graph", [(1, 1), (0, 1), (1, 0), (0, 0)])
+def test_solve_to_tolerance(cases, fused, graph):
+    for name, A, p, sd in cases:
+        b = uniform_rhs(A.n, 11)
+        s = _setup(A, p, fused_reduce=fused, use_graph=graph, check_every=8)
+        x = torch.zeros(A.n, dtype=torch.float64, device=DEV)
+        r = ss.ss_cg_solve(s, _t(b), x, tol=1e-10, maxit=5000, hist=True)
+        xo, ro = O.ss_cg(A, sd, b, tol=1e-10, maxit=5000)
+        xg = _np(x)
+        assert r.status == ss.SS_OK, name
+        assert abs(r.iterations - ro.iterations) <= 1, (name, r.iterations, ro.iterations)
+        true = np.linalg.norm(b - O.csr_matvec(A, xg)) / np.linalg.norm(b)
+        assert true <= 1e-10 and r.relres <= 1e-10, (name, true)
+        assert abs(true - r.true_relres) <= 1e-3 * true + 1e-16
+        assert np.linalg.norm(xg - xo) <= 1e-9 * np.linalg.norm(xo), name
+
+
+def test_modes_give_bitwise_identical_results(cases):
+    name, A, p, sd = cases[1]
+    b = _t(uniform_rhs(A.n, 3))
+    outs = []
+    for fused, graph, chk in [(1, 1, 32), (0, 1, 8), (1, 0, 2), (0, 0, 64)]:
+        s = _setup(A, p, fused_reduce=fused, use_graph=graph, check_every=chk)
+        x = torch.zeros(A.n, dtype=torch.float64, device=DEV)
+        r = ss.ss_cg_solve(s, b, x, tol=1e-10, maxit=5000, hist=True)
+        outs.append((_np(x), r.hist, r.iterations))
+    for xo, ho, ko in outs[1:]:
+        assert np.array_equal(xo, outs[0][0]) and np.array_equal(ho, outs[0][1]) and ko == outs[0][2]
+
+
+def test_run_to_run_reproducible(cases):
+    name, A, p, sd = cases[2]
+    s = _setup(A, p)
+    b = _t(uniform_rhs(A.n, 4))
+    res = []
+    for _ in range(3):
+        x = torch.zeros(A.n, dtype=torch.float64, device=DEV)
+        r = ss.ss_cg_solve(s, b, x, tol=1e-10, maxit=5000, hist=True)
+        res.append((_np(x), r.hist))
+    for x, h in res[1:]:
+        assert np.array_equal(x, res[0][0]) and np.array_equal(h, res[0][1])
+
+
+def test_iterations_independent_of_subdomain_count():
+    M = 20
+    A = diffusion3d_lognormal(M, seed=2)
+    b = _t(uniform_rhs(A.n, 102))
+    its = []
+    for boxes in [(1, 1, 1), (2, 1, 1), (2, 2, 2), (4, 4, 2)]:
+        P = int(np.prod(boxes))
+        s = _setup(A, ss.ss_partition(A, ss.SS_PART_BOX, P, grid=(M, M, M), boxes=boxes))
+        x = torch.zeros(A.n, dtype=torch.float64, device=DEV)
+        r = ss.ss_cg_solve(s, b, x, tol=1e-10, maxit=5000)
+        assert r.status == ss.SS_OK
+        its.append(r.iterations)
+    assert max(its) - min(its) <= 2, its
+
+
+def test_edge_cases():
+    A = poisson2d(37)  # ragged: 1369 rows
+    p = ss.ss_partition(A, ss.SS_PART_BOX, 6, grid=(37, 37), boxes=(3, 2))
+    s = _setup(A, p)
+    n = A.n
+    # b = 0 -> x = 0 in zero iterations, whatever x0 was
+    x = torch.ones(n, dtype=torch.float64, device=DEV)
+    r = ss.ss_cg_solve(s, torch.zeros(n, dtype=torch.float64, device=DEV), x, hist=True)
+    assert r.status == ss.SS_OK and r.iterations == 0 and not _np(x).any()
+    # maxit reached
+    x = torch.zeros(n, dtype=torch.float64, device=DEV)
+    r = ss.ss_cg_solve(s, _t(uniform_rhs(n, 1)), x, tol=1e-30, maxit=1)
+    assert r.status == ss.SS_NOT_CONVERGED and r.iterations == 1
+    # maxit = 0: only the initial residual
+    x = torch.zeros(n, dtype=torch.float64, device=DEV)
+    r = ss.ss_cg_solve(s, _t(uniform_rhs(n, 1)), x, tol=1e-10, maxit=0)
+    assert r.status == ss.SS_NOT_CONVERGED and r.iterations == 0 and not _np(x).any()
+    # NaN in b
+    bn = uniform_rhs(n, 2)
+    bn[5] = np.nan
+    x = torch.zeros(n, dtype=torch.float64, device=DEV)
+    r = ss.ss_cg_solve(s, _t(bn), x)
+    assert r.status == ss.SS_EBREAKDOWN
+    # converged initial guess: zero iterations
+    b = uniform_rhs(n, 3)
+    xs, _ = O.cg(A, b, tol=1e-13)
+    x = _t(xs)
+    r = ss.ss_cg_solve(s, _t(b), x, tol=1e-8)
+    assert r.status == ss.SS_OK and r.iterations == 0
+    # invalid arguments
+    with pytest.raises(ss.SSError):
+        ss.ss_cg_solve(s, _t(b), x, tol=-1.0)
+
+
+def test_indefinite_matrix_breaks_down():
+    # symmetric, indefinite: diag(1, -1) coupled -> (p, A p) <= 0 at the start
+    A = CSR(2, np.array([0, 1, 2], np.int32), np.array([0, 1], np.int32), np.array([1.0, -1.0]))
+    p = ss.ss_partition(A, ss.SS_PART_USER, 2, user_part=np.array([0, 1]))
+    s = _setup(A, p)
+    x = torch.zeros(2, dtype=torch.float64, device=DEV)
+    r = ss.ss_cg_solve(s, _t([0.0, 1.0]), x)
+    assert r.status == ss.SS_EBREAKDOWN and r.iterations == 0
+
+
+def test_one_by_one_and_single_subdomain():
+    A = CSR(1, np.array([0, 1], np.int32), np.array([0], np.int32), np.array([4.0]))
+    p = ss.ss_partition(A, ss.SS_PART_USER, 1, user_part=np.zeros(1))
+    s = _setup(A, p)
+    x = torch.zeros(1, dtype=torch.float64, device=DEV)
+    r = ss.ss_cg_solve(s, _t([3.0]), x, tol=1e-14)
+    assert r.status == ss.SS_OK and r.iterations == 1 and _np(x)[0] == 0.75
+
+
+def test_empty_subdomains():
+    A = poisson2d(9)
+    part = np.zeros(A.n, np.int32)
+    part[A.n // 2:] = 4
+    p = ss.ss_partition(A, ss.SS_PART_USER, 5, user_part=part)
+    sd = O.split(A.rowptr, A.colidx, part, 5)
+    s = _setup(A, p)
+    b = uniform_rhs(A.n, 8)
+    x = torch.zeros(A.n, dtype=torch.float64, device=DEV)
+    r = ss.ss_cg_solve(s, _t(b), x, tol=1e-10)
+    xo, ro = O.ss_cg(A, sd, b, tol=1e-10)
+    assert r.status == ss.SS_OK and abs(r.iterations - ro.iterations) <= 1
+    assert np.linalg.norm(_np(x) - xo) <= 1e-9 * np.linalg.norm(xo)
+
+
+def test_set_values_and_gradient_kernel():
+    w = config(5, size=10)
+    A = w.A
+    p = ss.partition_workload(w)
+    sd = O.split(A.rowptr, A.colidx, O.box_partition(w.grid, w.boxes), 8)
+    s = _setup(A, p)
+    # new values on the same pattern (scaled, still SPD)
+    v2 = A.val * 1.5
+    ss.ss_cg_set_values(s, _t(v2))
+    A2 = CSR(A.n, A.rowptr, A.colidx, v2)
+    x = uniform_rhs(A.n, 3)
+    assert np.array_equal(_np(ss.ss_cg_apply(s, _t(x))), O.ss_spmv(A2, sd, x))
+    lam = uniform_rhs(A.n, 4)
+    d = _np(ss.ss_cg_grad_vals(s, _t(lam), _t(x)))
+    assert np.array_equal(d, O.grad_vals(A2, lam, x))
+
+
+def test_full_size_cfg2():
+    # the benchmarked system: 128^3 lognormal diffusion, 8 boxes
+    w = config(2)
+    A = w.A
+    p = ss.partition_workload(w)
+    sd = O.split(A.rowptr, A.colidx, O.box_partition(w.grid, w.boxes), 8)
+    s = _setup(A, p)
+    # SpMV + assembly at full size: bitwise
+    xv = uniform_rhs(A.n, 77)
+    assert np.array_equal(_np(ss.ss_cg_apply(s, _t(xv))), O.ss_spmv(A, sd, xv))
+    # 10 CG steps against the oracle
+    b = w.b
+    x = torch.zeros(A.n, dtype=torch.float64, device=DEV)
+    r = ss.ss_cg_solve(s, _t(b), x, tol=0.0, maxit=10, hist=True)
+    xo, ro = O.ss_cg(A, sd, b, tol=0.0, maxit=10)
+    assert np.linalg.norm(_np(x) - xo) <= 1e-12 * np.linalg.norm(xo)
+    assert np.allclose(r.hist, ro.hist, rtol=1e-10, atol=0)
+    # full solve: the recomputed residual, checked with the oracle's SpMV
+    x = torch.zeros(A.n, dtype=torch.float64, device=DEV)
+    r = ss.ss_cg_solve(s, _t(b), x, tol=1e-10, maxit=20000)
+    xg = _np(x)
+    assert r.status == ss.SS_OK
+    true = np.linalg.norm(b - O.csr_matvec(A, xg)) / np.linalg.norm(b)
+    assert true <= 1e-10, true
+    print(f"cfg2: {r.iterations} iterations, true relres {true:.3e}, restarts {r.restarts}")

@@ -1,0 +1,142 @@
+"""Host side of libss (no GPU needed): exported symbols, struct layout, input
+validation, and the partition / sub-domain maps, which must equal the oracle's
+bit for bit."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle as O
+import paper_2108_13162_amd as ss
+from workloads import CSR, config, diffusion3d_lognormal, grid_coords, poisson2d, random_spd_csr
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_functions():
+    text = open(os.path.join(ROOT, "include", "ss.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\s*\*?\s*(ss_[a-z_0-9]+)\s*\(", text, flags=re.M)
+    return sorted(set(names))
+
+
+def test_library_exports_every_declared_symbol():
+    names = _declared_functions()
+    assert "ss_partition" in names and "ss_cg_solve" in names and "ss_cg_setup" in names
+    L = C.CDLL(ss.LIB_PATH)
+    missing = [n for n in names if not hasattr(L, n)]
+    assert not missing, missing
+
+
+def test_opts_layout_and_defaults():
+    o = ss.default_opts()
+    assert C.sizeof(ss.ss_opts) == 64
+    assert o.precision == ss.SS_FP64 and o.inner_tol == 1e-5 and o.max_outer == 50
+    assert o.check_every == 32 and o.use_graph == 1 and o.fused_reduce == 1 and o.tile_nnz == 0
+    assert ss.lib().ss_version() >= 100
+    assert ss.strerror(ss.SS_EBREAKDOWN).startswith("CG breakdown")
+
+
+def _compare(A, part_ss, part_or):
+    e = part_ss.export()
+    loc = part_ss.export_local()
+    z = part_ss.sizes()
+    assert z["n_loc"] == part_or.n_loc and z["nnz"] == A.nnz
+    assert np.array_equal(e["part"], part_or.part)
+    for k in ("sub_off", "n_int", "n_own", "l2g", "gamma", "copy_ptr", "copy_pos"):
+        assert np.array_equal(e[k], getattr(part_or, k)), k
+    for k in ("bd_rowptr", "bd_colidx", "bd_nzmap"):
+        assert np.array_equal(loc[k], getattr(part_or, k)), k
+
+
+@pytest.mark.parametrize("m,boxes", [(4, (2, 2)), (17, (3, 3)), (64, (2, 2)), (10, (1, 1)), (9, (4, 2))])
+def test_box_2d_maps_bit_exact(m, boxes):
+    A = poisson2d(m)
+    P = boxes[0] * boxes[1]
+    p = ss.ss_partition(A, ss.SS_PART_BOX, P, grid=(m, m), boxes=boxes)
+    ref = O.split(A.rowptr, A.colidx, O.box_partition((m, m), boxes), P)
+    _compare(A, p, ref)
+
+
+@pytest.mark.parametrize("M,boxes", [(8, (2, 2, 2)), (11, (3, 2, 2)), (24, (2, 2, 2))])
+def test_box_3d_maps_bit_exact(M, boxes):
+    A = diffusion3d_lognormal(M, seed=2)
+    P = int(np.prod(boxes))
+    p = ss.ss_partition(A, ss.SS_PART_BOX, P, grid=(M, M, M), boxes=boxes)
+    ref = O.split(A.rowptr, A.colidx, O.box_partition((M, M, M), boxes), P)
+    _compare(A, p, ref)
+
+
+@pytest.mark.parametrize("size,nparts", [(8, 16), (13, 7), (12, 3)])
+def test_rcb_q1hex_maps_bit_exact(size, nparts):
+    w = config(3, size=size)
+    weights = np.random.default_rng(nparts).uniform(0.7, 1.3, nparts)
+    p = ss.ss_partition(w.A, ss.SS_PART_RCB, nparts, coords=w.coords, weights=weights)
+    ref = O.split(w.A.rowptr, w.A.colidx, O.rcb_partition(w.coords, weights), nparts)
+    _compare(w.A, p, ref)
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2, 3])
+def test_user_partition_random_spd_bit_exact(seed):
+    A = random_spd_csr(300, 6.0, seed=seed)
+    P = [1, 5, 13, 300][seed]
+    part = np.random.default_rng(seed).integers(0, P, size=A.n).astype(np.int32)
+    p = ss.ss_partition(A, ss.SS_PART_USER, P, user_part=part)
+    _compare(A, p, O.split(A.rowptr, A.colidx, part, P))
+
+
+def test_full_size_cfg5_maps_bit_exact():
+    w = config(5)
+    p = ss.partition_workload(w)
+    _compare(w.A, p, O.split(w.A.rowptr, w.A.colidx, O.box_partition(w.grid, w.boxes), 8))
+
+
+def test_empty_subdomains_allowed():
+    # a user partition may leave parts empty; their ranges are empty
+    A = poisson2d(5)
+    part = np.zeros(A.n, np.int32)
+    part[A.n // 2:] = 3
+    p = ss.ss_partition(A, ss.SS_PART_USER, 4, user_part=part)
+    ref = O.split(A.rowptr, A.colidx, part, 4)
+    _compare(A, p, ref)
+    assert np.diff(p.export()["sub_off"]).tolist()[1:3] == [0, 0]
+
+
+def _expect_einval(A, **kw):
+    with pytest.raises(ss.SSError) as ei:
+        ss.ss_partition(A, **kw)
+    assert ei.value.code == ss.SS_EINVAL
+    return str(ei.value)
+
+
+def test_invalid_inputs_rejected():
+    A = poisson2d(4)
+    # unsorted columns
+    bad = CSR(A.n, A.rowptr.copy(), A.colidx.copy(), A.val.copy())
+    bad.colidx[0], bad.colidx[1] = bad.colidx[1], bad.colidx[0]
+    assert "strictly increasing" in _expect_einval(bad, method=ss.SS_PART_USER, nparts=1, user_part=np.zeros(A.n))
+    # column out of range
+    bad = CSR(A.n, A.rowptr.copy(), A.colidx.copy(), A.val.copy())
+    bad.colidx[-1] = A.n
+    assert "out of range" in _expect_einval(bad, method=ss.SS_PART_USER, nparts=1, user_part=np.zeros(A.n))
+    # asymmetric values
+    bad = CSR(A.n, A.rowptr.copy(), A.colidx.copy(), A.val.copy())
+    bad.val[1] = -2.0
+    assert "not symmetric" in _expect_einval(bad, method=ss.SS_PART_USER, nparts=1, user_part=np.zeros(A.n))
+    # asymmetric pattern: drop one off-diagonal entry of row 0
+    keep = np.ones(A.nnz, bool)
+    keep[1] = False
+    rp = A.rowptr.copy()
+    rp[1:] -= 1
+    bad = CSR(A.n, rp, A.colidx[keep], A.val[keep])
+    assert "not symmetric" in _expect_einval(bad, method=ss.SS_PART_USER, nparts=1, user_part=np.zeros(A.n))
+    # nparts out of range, bad grids, bad weights, bad user parts
+    _expect_einval(A, method=ss.SS_PART_USER, nparts=0, user_part=np.zeros(A.n))
+    _expect_einval(A, method=ss.SS_PART_USER, nparts=A.n + 1, user_part=np.zeros(A.n))
+    _expect_einval(A, method=ss.SS_PART_BOX, nparts=4, grid=(4, 5), boxes=(2, 2))
+    _expect_einval(A, method=ss.SS_PART_BOX, nparts=6, grid=(4, 4), boxes=(2, 2))
+    _expect_einval(A, method=ss.SS_PART_RCB, nparts=2, coords=grid_coords((4, 4)), weights=[1.0, -1.0])
+    _expect_einval(A, method=ss.SS_PART_USER, nparts=2, user_part=np.full(A.n, 2))
+    _expect_einval(A, method=7, nparts=1)
