@@ -141,6 +141,13 @@ typedef void (*ss_free_fn)(void *ctx, void *ptr);
 
 enum { SS_FP64 = 0, SS_FP32_IR = 1 };
 
+/* Device storage of the block-diagonal matrix of all local matrices. */
+enum {
+    SS_MAT_AUTO = 0, /* SELL-64 unless rows are too uneven, else CSR row tiles */
+    SS_MAT_SELL = 1, /* chunks of 64 rows, one row per lane, column-major      */
+    SS_MAT_CSR = 2   /* CSR cut into row tiles of tile_nnz entries             */
+};
+
 typedef struct {
     int32_t precision;   /* SS_FP64, or SS_FP32_IR: FP32 values and vectors in
                             the inner CG, FP64 dots, FP64 residuals and an
@@ -151,11 +158,10 @@ typedef struct {
     int32_t check_every; /* CG iterations between host polls (<= 0: 32)        */
     int32_t use_graph;   /* 1: replay polled chunks as HIP graphs (default);
                             0: plain launches                                  */
-    int32_t tile_nnz;    /* SpMV tile size in nonzeros: 0 = tuned choice,
-                            else one of 1024, 2048, 4096                      */
-    int32_t fused_reduce; /* 1 (default): the last workgroup of a kernel
-                             finishes its reduction; 0: separate 1-workgroup
-                             kernels                                          */
+    int32_t tile_nnz;    /* CSR tiles: entries per tile, 0 = 2048, else one of
+                            1024, 2048, 4096                                  */
+    int32_t matrix_format; /* SS_MAT_*                                        */
+    int32_t spmv_grid;   /* persistent SpMV workgroups, 0 = tuned default      */
     ss_alloc_fn alloc;   /* device allocator; NULL = hipMalloc                 */
     ss_free_fn free;     /* matching release; NULL = hipFree                   */
     void *alloc_ctx;
@@ -219,16 +225,18 @@ int ss_cg_set_values(ss_solver *s, const double *val_dev);
 int ss_cg_grad_vals(ss_solver *s, const double *lambda_dev, const double *x_dev, double *dvals_dev);
 
 /* Average duration in milliseconds of one launch of the local SpMV kernel
- * (the fused CG-step variant), timed with HIP events around `reps`
+ * (the CG-step variant), timed with one HIP event pair around each of `reps`
  * back-to-back launches on the solver stream.  Leaves the solver state
  * unchanged except for scratch vectors.  Also reports the algorithmic bytes
  * that launch moves (values, column indices, row pointers, one read of the
  * two input vectors, two output vectors). */
 int ss_cg_time_spmv(ss_solver *s, int32_t reps, double *ms_per_launch, double *bytes_per_launch);
 
-/* Sizes of the device problem (any pointer may be NULL). */
-int ss_cg_info(const ss_solver *s, int32_t *n, int32_t *n_loc, int64_t *nnz, int32_t *ntiles,
-               int32_t *tile_nnz);
+/* Sizes of the device problem (any pointer may be NULL): matrix_format is
+ * the SS_MAT_SELL / SS_MAT_CSR storage chosen, stored the entries it holds
+ * (SELL: including the chunk padding). */
+int ss_cg_info(const ss_solver *s, int32_t *n, int32_t *n_loc, int64_t *nnz, int32_t *matrix_format,
+               int64_t *stored);
 
 void ss_cg_destroy(ss_solver *s);
 

@@ -26,6 +26,7 @@ LIB_PATH = os.path.join(HERE, "libss.so")
 SS_OK, SS_NOT_CONVERGED, SS_EINVAL, SS_ENOMEM, SS_EDEVICE, SS_EBREAKDOWN, SS_EUNSUPPORTED = 0, 1, -1, -2, -3, -4, -5
 SS_PART_BOX, SS_PART_RCB, SS_PART_USER = 0, 1, 2
 SS_FP64, SS_FP32_IR = 0, 1
+SS_MAT_AUTO, SS_MAT_SELL, SS_MAT_CSR = 0, 1, 2
 
 _ALLOC_T = C.CFUNCTYPE(C.c_void_p, C.c_void_p, C.c_size_t)
 _FREE_T = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
@@ -39,7 +40,8 @@ class ss_csr(C.Structure):
 class ss_opts(C.Structure):
     _fields_ = [("precision", C.c_int32), ("inner_tol", C.c_double), ("inner_maxit", C.c_int32),
                 ("max_outer", C.c_int32), ("check_every", C.c_int32), ("use_graph", C.c_int32),
-                ("tile_nnz", C.c_int32), ("fused_reduce", C.c_int32), ("alloc", _ALLOC_T), ("free", _FREE_T),
+                ("tile_nnz", C.c_int32), ("matrix_format", C.c_int32), ("spmv_grid", C.c_int32),
+                ("alloc", _ALLOC_T), ("free", _FREE_T),
                 ("alloc_ctx", C.c_void_p)]
 
 
@@ -139,9 +141,9 @@ class Partition:
         self.h = handle
 
     def __del__(self):
-        if getattr(self, "h", None):
-            lib().ss_part_destroy(self.h)
-            self.h = None
+        h, self.h = getattr(self, "h", None), None
+        if h and _lib is not None:
+            _lib.ss_part_destroy(h)
 
     def sizes(self) -> dict:
         return ss_part_sizes(self)
@@ -267,17 +269,17 @@ class Solver:
         self.nnz = nnz
 
     def __del__(self):
-        if getattr(self, "h", None):
-            lib().ss_cg_destroy(self.h)
-            self.h = None
+        h, self.h = getattr(self, "h", None), None
+        if h and _lib is not None:
+            _lib.ss_cg_destroy(h)
 
     def close(self):
         self.__del__()
 
     def info(self) -> dict:
-        v = [C.c_int32(), C.c_int32(), C.c_int64(), C.c_int32(), C.c_int32()]
+        v = [C.c_int32(), C.c_int32(), C.c_int64(), C.c_int32(), C.c_int64()]
         _check(lib().ss_cg_info(self.h, *[C.byref(t) for t in v]), "ss_cg_info")
-        return dict(zip(["n", "n_loc", "nnz", "ntiles", "tile_nnz"], [t.value for t in v]))
+        return dict(zip(["n", "n_loc", "nnz", "matrix_format", "stored"], [t.value for t in v]))
 
 
 def _dev_f64(t, n: int, name: str):

@@ -16,87 +16,125 @@ enum : int32_t {
     ST_ZERO_RHS = 4,
 };
 
-// Scalars of one CG run, kept in device memory so that a whole iteration runs
-// without the host: the kernels read alpha / beta / status from here and the
-// finishing workgroup of every reduction writes them.
+// Scalars of one CG run, in device memory, so that iterations run without
+// the host.  (r, r) and the iteration count live in two slots: the kernel of
+// a step reads slot c and its workgroup 0 writes slot 1 - c, so no workgroup
+// ever reads a value that another workgroup of the same kernel is writing.
+// `status` is accessed with atomic loads / stores inside kernels.
 struct DevState {
-    double rr;        // (r, r) of the current residual (weighted local dot)
-    double bb;        // (b, b)
-    double pAp;       // (p, A p)
-    double alpha;
-    double beta;
-    double tol;       // relative tolerance of the run
-    double stop;      // CG continues while sqrt(rr) > stop
-    double scale;     // IR: norm of the outer residual the inner solve started from
-    int32_t iter;     // iterations done (all runs of this solve)
-    int32_t kmax;     // iteration limit of the current run
-    int32_t status;   // ST_*
-    int32_t hist_cap; // entries of hist
-    double *hist;     // ||r_k|| / ||b||, device, or nullptr
-    uint32_t cnt[4];  // arrival counters of the fused reductions
+    double rr[2];      // (r, r) of the current residual (weighted local dot), by slot
+    int32_t iter[2];   // completed CG iterations, by slot
+    double bb;         // (b, b)
+    double tol;        // relative tolerance of the run
+    double stop;       // CG continues while sqrt(rr) > stop
+    double alpha, beta, pAp;  // last scalars (report only)
+    double rr_last;    // latest (r, r) (report; read by the host and the next residual step)
+    int32_t iter_last; // latest iteration count (same)
+    int32_t kmax;      // iteration limit
+    int32_t status;    // ST_*
+    int32_t hist_cap;  // entries of hist
+    double *hist;      // ||r_k|| / ||b||, device, or nullptr
 };
 
-// One workgroup of the update / residual kernels: `count` consecutive
-// positions starting at `start`, all of one kind: 0 interior (owned, no
-// assembly), 1 owned interface copy, 2 other interface copy.  `ifbase`
-// indexes pos_grp for the first position of an interface block.
-struct UpdBlock {
-    int32_t start, count, kind, ifbase;
-};
-
-constexpr int kBS = 256;     // workgroup size of all streaming kernels
-constexpr int kUI = 4;       // positions per thread in the update kernels
-constexpr int kNumXcd = 8;   // MI355X: workgroups are dealt round-robin to 8 XCDs
+constexpr int kBS = 256;    // workgroup size of every kernel
+constexpr int kUI = 4;      // positions per thread per batch in the update / residual kernels
+constexpr int kSellU = 8;   // entries per lane per batch in the SELL-64 SpMV
+constexpr int kNumXcd = 8;  // MI355X: workgroups are dealt round-robin to 8 XCDs
 
 // Grid size for `work` items remapped so that each XCD gets a contiguous range.
 inline int xcd_grid(int work) { return ((work + kNumXcd - 1) / kNumXcd) * kNumXcd; }
 
-struct Csr {
-    const int32_t *rowptr, *colidx, *tile_row;
-    const void *val;  // double or float
+enum { FMT_SELL = 0, FMT_CSR = 1 };
+
+// The block-diagonal matrix of all local matrices in device position order.
+//  SELL-64: rows in chunks of 64 consecutive positions (one row per lane of a
+//    wave), entry j of the chunk's rows stored contiguously (column-major
+//    inside the chunk), chunk length = longest row of the chunk, padded
+//    entries masked by the row length.  Chunks are stored in processing order
+//    (cpos = first position of each), which spreads the interface chunks
+//    evenly over the persistent workgroups.
+//  CSR tiles: plain CSR cut into row tiles of at most tile_nnz entries.
+struct Mat {
+    int32_t fmt;
+    int32_t nrows;
+    int32_t grid;                 // persistent grid of the SpMV kernels (multiple of 8)
+    const int32_t *col;           // column positions (SELL order or CSR order)
+    const void *val;              // values, double or float, same order
+    // SELL-64
+    int32_t nchunks;
+    const int32_t *cptr;          // [nchunks+1] start of each chunk in col / val
+    const int32_t *cpos;          // [nchunks] first row position of each chunk
+    const uint8_t *clen;          // [nchunks] entries per row slot of the chunk
+    const uint8_t *rlen;          // [nrows] entries of each row (by position)
+    // CSR tiles
+    const int32_t *rowptr;        // [nrows+1]
+    const int32_t *tile_row;      // [ntiles+1]
     int32_t ntiles, tile_nnz;
 };
 
+// Device position order: [0, n_own) owned interface copies, [n_own, n_if)
+// the other interface copies, [n_if, n_loc) the interior positions of every
+// sub-domain.  pos_grp[c] = interface node of copy c (c < n_if).  The update
+// and residual kernels give one batch of kUI * kBS positions to each
+// workgroup, interface batches first.
 struct Iface {
-    const UpdBlock *blk;
-    int32_t nblk;
+    int32_t n_loc, n_own, n_if;
+    int32_t grid;                 // workgroups of the update kernels (multiple of 8)
     const int32_t *pos_grp, *copy_ptr, *copy_pos;
     int32_t ngamma;
 };
 
-// ---- launchers (all asynchronous on `st`) --------------------------------
+// Partial sums of the two reductions of a CG iteration.
+struct Partials {
+    double *a;  // (p, A_s p), one per SpMV workgroup (count = Mat::grid)
+    double *b;  // (r, r), one per update workgroup (count = Iface::grid)
+    int32_t na, nb;
+};
+
+// ---- launchers (all asynchronous on the given stream) ---------------------
 // Local copies of a global vector (each copy gets the node's value).
 template <typename XT>
 void launch_gather(hipStream_t s, int32_t n_loc, const int32_t *l2g, const double *src, XT *dst);
-// Global vector from the owned copies; zero == true writes zeros instead.
+// Global vector from the owned copies; writes zeros if `state` says b = 0.
 template <typename XT>
-void launch_scatter(hipStream_t s, int32_t n, const int32_t *g2own, const XT *src, double *dst, const DevState *dst_state);
+void launch_scatter(hipStream_t s, int32_t n, const int32_t *g2own, const XT *src, double *dst,
+                    const DevState *state);
 
 // q = A_bd x (no assembly).
 template <typename VT, typename XT>
-void launch_spmv(hipStream_t s, const Csr &A, const XT *x, XT *q);
-// CG step: pout = r + beta * pin (beta from state), q = A_bd pout,
-// partial (pout, q) -> alpha.
+void launch_spmv(hipStream_t s, const Mat &A, const XT *x, XT *q);
+// First CG step after a fresh residual: pout = r (p_1 = r_1), q = A_bd pout,
+// partials (pout, q) -> P.a.
 template <typename VT, typename XT>
-void launch_spmv_cg(hipStream_t s, const Csr &A, const XT *pin, const XT *r, XT *pout, XT *q, double *partial,
-                    DevState *state, bool fused);
+void launch_spmv_first(hipStream_t s, const Mat &A, const XT *pin, const XT *r, XT *pout, XT *q, Partials P,
+                       DevState *state);
+// Later CG steps: each workgroup finishes (r, r) from P.b, records the
+// iteration (workgroup 0), tests for convergence, then pout = r + beta pin,
+// q = A_bd pout, partials -> P.a.
+template <typename VT, typename XT>
+void launch_spmv_step(hipStream_t s, const Mat &A, const XT *pin, const XT *r, XT *pout, XT *q, Partials P,
+                      DevState *state, int slot);
 // Interface assembly in place: every copy of an interface node gets the sum of
 // all its copies (ascending sub-domain).
 template <typename XT>
 void launch_iface_sum(hipStream_t s, const Iface &I, XT *q);
-// Assembly + x += alpha p, r -= alpha q, partial (r, r) -> beta, convergence.
+// Each workgroup finishes (p, A p) from P.a -> alpha, then assembly,
+// x += alpha p, r -= alpha q and partials (r, r) -> P.b.
 template <typename XT>
-void launch_update(hipStream_t s, const Iface &I, XT *x, const XT *p, XT *r, const XT *q, double *partial,
-                   DevState *state, bool fused);
-// Fresh residual: r = b - assemble(q), p0 = r, partial (r, r) [and (b, b)].
+void launch_update(hipStream_t s, const Iface &I, XT *x, const XT *p, XT *r, const XT *q, Partials P,
+                   DevState *state, int slot);
+// Fresh residual r = b - assemble(q), p0 = r, then one workgroup finishes
+// (r, r) [and (b, b) when `first`] and sets the status.  partial: 2 * I.grid.
 template <typename XT>
 void launch_residual(hipStream_t s, const Iface &I, const XT *b, const XT *q, XT *r, XT *p0, double *partial,
-                     DevState *state, bool first, bool fused);
+                     DevState *state, bool first);
 
-// Adjoint gradient on the pattern and value updates through the entry map.
-void launch_grad_vals(hipStream_t s, int32_t n_loc, const int32_t *rowptr, const int32_t *colidx, const int32_t *nzmap,
-                      const int32_t *l2g, const double *lambda, const double *x, double *dvals);
-void launch_set_values(hipStream_t s, int64_t nnz, const int32_t *nzmap, const double *val_glob, double *val64,
+// Adjoint gradient on the pattern: dvals[nzmap[k]] = -lambda[row] x[col] for
+// every stored (non-padding) entry k of A in device order.
+void launch_grad_vals(hipStream_t s, const Mat &A, const int32_t *nzmap, const int32_t *l2g, const double *lambda,
+                      const double *x, double *dvals);
+// val64[k] = val_glob[nzmap[k]] (0 for padding, nzmap < 0), val32 its FP32 rounding.
+void launch_set_values(hipStream_t s, int64_t len, const int32_t *nzmap, const double *val_glob, double *val64,
                        float *val32);
 
 }  // namespace ss

@@ -1,19 +1,22 @@
 // HIP kernels of the sub-structured CG for gfx950 (MI355X).
 //
-// Hot path of one CG iteration (Algorithm 3, M = I) with every sub-domain
-// resident on the device, two launches:
-//   k_spmv  (CG mode): p_k = r_k + beta p_{k-1} recomputed on the fly, the
-//           local SpMV of every sub-domain on the block-diagonal CSR
-//           (Section 4.4.1, first step) and the partial (p, A_s p) sums;
-//           the finishing workgroup forms alpha = (r, r) / (p, A p).
-//   k_update: interface assembly (Algorithms 4 and 5: every copy of an
-//           interface node reads all copies and adds them in ascending
-//           sub-domain order), x += alpha p, r -= alpha q and the weighted
-//           local (r, r) (Section 4.4.2); the finishing workgroup forms beta
-//           and the convergence flag.
-// Reductions are fixed-order (per-thread sequential, 64-lane butterfly, then
-// a sequential sum over waves and over workgroup partials), hence bitwise
-// reproducible run to run.  The file is compiled with -ffp-contract=off:
+// One CG iteration (Algorithm 3, M = I) with every sub-domain resident on the
+// device is two launches (the SpMV on a persistent, fixed-size grid):
+//   k_update: finishes (p, A p) -> alpha, assembles the interface values of
+//             q = A_bd p (Algorithms 4 and 5: every copy of an interface node
+//             reads all copies and adds them in ascending sub-domain order),
+//             x += alpha p, r -= alpha q, and writes partials of the weighted
+//             local (r, r) (Section 4.4.2);
+//   k_spmv_*: finishes (r, r) -> beta and the stopping test, p = r + beta p
+//             recomputed on the fly, the local SpMV of every sub-domain on the
+//             block-diagonal matrix (Section 4.4.1, first step) and partials
+//             of (p, A_s p).
+// "Finishes" means: every workgroup adds up the previous kernel's
+// per-workgroup partials itself, in one fixed order, so all workgroups obtain
+// bitwise the same scalar without a grid-wide barrier or a separate launch;
+// those loads are issued after the workgroup's first streaming loads and
+// overlap them.  Workgroup 0 records the scalars.  All sums are fixed-order,
+// hence bitwise reproducible run to run.  Compiled with -ffp-contract=off:
 // products and sums are rounded separately, as the expressions are written.
 #include "kernels.h"
 
@@ -29,6 +32,25 @@ __device__ __forceinline__ int xcd_remap(int b, int grid)
     return (b % kNumXcd) * per + b / kNumXcd;
 }
 
+__device__ __forceinline__ int32_t load_status(const DevState *st)
+{
+    return __hip_atomic_load(&st->status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void store_status(DevState *st, int32_t v)
+{
+    __hip_atomic_store(&st->status, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Status read once per workgroup and shared, so the whole workgroup takes the
+// same branch.
+__device__ __forceinline__ bool running(const DevState *st, int *s_flag)
+{
+    if (threadIdx.x == 0) *s_flag = load_status(st);
+    __syncthreads();
+    return *s_flag == ST_RUNNING;
+}
+
 template <typename T>
 __device__ __forceinline__ T wave_sum(T v)
 {
@@ -37,119 +59,44 @@ __device__ __forceinline__ T wave_sum(T v)
     return v;
 }
 
-// Sum over the workgroup; result valid in thread 0.  ws: kBS/64 slots.
+// Fixed-order sum over the workgroup, returned to every thread.
+// ws: kBS/64 + 1 slots.
 template <typename T>
-__device__ __forceinline__ T block_sum(T v, T *ws)
+__device__ __forceinline__ T block_sum_all(T v, T *ws)
 {
     v = wave_sum(v);
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     if (lane == 0) ws[w] = v;
     __syncthreads();
-    T t = T(0);
     if (threadIdx.x == 0) {
+        T t = T(0);
 #pragma unroll
         for (int i = 0; i < kBS / 64; ++i) t = t + ws[i];
+        ws[kBS / 64] = t;
     }
+    __syncthreads();
+    const T t = ws[kBS / 64];
     __syncthreads();
     return t;
 }
 
-__device__ __forceinline__ double sum_partials(const double *partial, int n, double *ws)
+// Sum of n partials in a fixed order (thread t adds partials t, t+kBS, ...
+// left to right, then the workgroup tree), returned to every thread.  Loads
+// go out 8 at a time before the adds.
+__device__ __forceinline__ double sum_partials_all(const double *__restrict__ partial, int n, double *ws)
 {
     double v = 0.0;
-    for (int i = threadIdx.x; i < n; i += kBS) v = v + partial[i];
-    return block_sum(v, ws);
-}
-
-// Publishes this workgroup's partial(s); true in every thread of the
-// workgroup that arrives last.  Agent-scope fences make the partials of all
-// XCDs visible to it.
-template <int NV>
-__device__ __forceinline__ bool arrive(const double (&v)[NV], double *partial, uint32_t *counter)
-{
-    __shared__ int last;
-    if (threadIdx.x == 0) {
+    for (int base = 0; base < n; base += 8 * kBS) {
+        double t[8];
 #pragma unroll
-        for (int t = 0; t < NV; ++t) partial[t * gridDim.x + blockIdx.x] = v[t];
-        __threadfence();
-        const uint32_t prev = atomicAdd(counter, 1u);
-        last = (prev == gridDim.x - 1) ? 1 : 0;
-    }
-    __syncthreads();
-    const bool is_last = last != 0;
-    if (is_last) {
-        __threadfence();
-        if (threadIdx.x == 0) *counter = 0u;
-    }
-    return is_last;
-}
-
-// ---- finishing steps (one workgroup) ---------------------------------------
-
-__device__ void finish_alpha(DevState *st, const double *partial, int n, double *ws)
-{
-    const double pAp = sum_partials(partial, n, ws);
-    if (threadIdx.x == 0) {
-        st->pAp = pAp;
-        if (!(pAp > 0.0) || !isfinite(pAp))
-            st->status = ST_BREAKDOWN;
-        else
-            st->alpha = st->rr / pAp;
-    }
-}
-
-__device__ void finish_beta(DevState *st, const double *partial, int n, double *ws)
-{
-    const double rr1 = sum_partials(partial, n, ws);
-    if (threadIdx.x == 0) {
-        if (!isfinite(rr1)) {
-            st->status = ST_BREAKDOWN;
-            return;
+        for (int i = 0; i < 8; ++i) {
+            const int idx = base + i * kBS + (int)threadIdx.x;
+            t[i] = idx < n ? partial[idx] : 0.0;
         }
-        st->beta = rr1 / st->rr;
-        st->rr = rr1;
-        const int k = ++st->iter;
-        if (st->hist && k < st->hist_cap) st->hist[k] = sqrt(rr1 / st->bb);
-        if (sqrt(rr1) <= st->stop)
-            st->status = ST_CONVERGED;
-        else if (k >= st->kmax)
-            st->status = ST_MAXIT;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) v = v + t[i];
     }
-}
-
-__device__ void finish_residual(DevState *st, const double *partial, int n, bool first, double *ws)
-{
-    const double rr = sum_partials(partial, n, ws);
-    const double bb = first ? sum_partials(partial + n, n, ws) : 0.0;
-    if (threadIdx.x == 0) {
-        if (first) {
-            st->bb = bb;
-            if (!isfinite(bb)) {
-                st->status = ST_BREAKDOWN;
-                return;
-            }
-            if (bb == 0.0) {
-                st->status = ST_ZERO_RHS;
-                if (st->hist && st->hist_cap > 0) st->hist[0] = 0.0;
-                return;
-            }
-            st->stop = st->tol * sqrt(bb);
-        }
-        if (!isfinite(rr)) {
-            st->status = ST_BREAKDOWN;
-            return;
-        }
-        st->rr = rr;
-        st->beta = 0.0;
-        const int k = st->iter;
-        if (st->hist && k < st->hist_cap) st->hist[k] = sqrt(rr / st->bb);
-        if (sqrt(rr) <= st->stop)
-            st->status = ST_CONVERGED;
-        else if (k >= st->kmax)
-            st->status = ST_MAXIT;
-        else
-            st->status = ST_RUNNING;
-    }
+    return block_sum_all(v, ws);
 }
 
 // p_k = r_k + beta p_{k-1}, evaluated in FP64 and rounded to the vector type.
@@ -159,46 +106,183 @@ __device__ __forceinline__ XT pupd(XT r, XT p, double beta)
     return (XT)((double)r + beta * (double)p);
 }
 
-// ---- local SpMV on the block-diagonal CSR ----------------------------------
-//
-// One workgroup per row tile (consecutive rows holding at most TN nonzeros,
-// or a single longer row).  Stage 1 streams the tile's values and column
-// indices with coalesced non-temporal loads (they are read once per
-// iteration, the vectors should stay in L2 / MALL) and stores the products
-// in LDS; stage 2 gives each row to one thread, which adds its products left
-// to right -- the same order as a sequential CSR row sum.
+enum { SPMV_PLAIN = 0, SPMV_FIRST = 1, SPMV_STEP = 2 };
 
-template <typename VT, typename XT, int TN, bool CG, bool FUSED>
-__global__ __launch_bounds__(kBS) void k_spmv(const int32_t *__restrict__ rowptr, const int32_t *__restrict__ colidx,
-                                              const VT *__restrict__ val, const int32_t *__restrict__ tile_row,
-                                              int32_t ntiles, const XT *__restrict__ pin, const XT *__restrict__ r,
-                                              XT *__restrict__ pout, XT *__restrict__ q, double *__restrict__ partial,
-                                              DevState *__restrict__ st)
+// The CG-step prologue: finish (r, r) of the previous update, record
+// iteration k+1 (workgroup 0), stopping test.  Returns beta, or sets *stop.
+__device__ __forceinline__ double finish_rr(const double *__restrict__ part_b, int nb, int slot, DevState *st,
+                                            double *ws, bool *stop_out)
 {
-    __shared__ XT prod[TN];
-    __shared__ XT wsx[kBS / 64];
-    __shared__ double ws[kBS / 64];
-    if (CG && st->status != ST_RUNNING) return;
-    const double beta = CG ? st->beta : 0.0;
-    const int tile = xcd_remap(blockIdx.x, gridDim.x);
+    const double rr_new = sum_partials_all(part_b, nb, ws);
+    const double rr_cur = st->rr[slot];
+    const int k_new = st->iter[slot] + 1;
+    int stop = ST_RUNNING;
+    if (!isfinite(rr_new))
+        stop = ST_BREAKDOWN;
+    else if (sqrt(rr_new) <= st->stop)
+        stop = ST_CONVERGED;
+    else if (k_new >= st->kmax)
+        stop = ST_MAXIT;
+    const double beta = rr_new / rr_cur;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        if (stop != ST_BREAKDOWN) {
+            st->rr[slot ^ 1] = rr_new;
+            st->iter[slot ^ 1] = k_new;
+            st->rr_last = rr_new;
+            st->iter_last = k_new;
+            st->beta = beta;
+            if (st->hist && k_new < st->hist_cap) st->hist[k_new] = sqrt(rr_new / st->bb);
+        }
+        if (stop != ST_RUNNING) store_status(st, stop);
+    }
+    *stop_out = stop != ST_RUNNING;
+    return beta;
+}
+
+// ---- local SpMV, SELL-64 -----------------------------------------------------
+//
+// A wave owns chunks of 64 rows, one row per lane.  Entry j of the 64 rows is
+// stored contiguously, so the value / column loads are coalesced and, for
+// matrices whose rows of a chunk have similar column offsets (grid
+// numberings), so are the x gathers.  Each lane adds its row's products left
+// to right in stored (column) order -- the order of a sequential CSR row sum.
+// Workgroup w (after the XCD remap) owns the stored chunks [w*cpb, (w+1)*cpb)
+// (cpos maps them to row positions); its 4 waves take every 4th chunk.
+
+template <typename VT, typename XT, int MODE>
+__global__ __launch_bounds__(kBS) void k_spmv_sell(int32_t nrows, int32_t nchunks, const int32_t *__restrict__ cptr,
+                                                   const int32_t *__restrict__ cpos,
+                                                   const uint8_t *__restrict__ clen,
+                                                   const uint8_t *__restrict__ rlen, const int32_t *__restrict__ col,
+                                                   const VT *__restrict__ val, const XT *__restrict__ pin,
+                                                   const XT *__restrict__ r, XT *__restrict__ pout,
+                                                   XT *__restrict__ q, double *__restrict__ part_a,
+                                                   const double *__restrict__ part_b, int32_t nb, int32_t slot,
+                                                   DevState *__restrict__ st)
+{
+    constexpr bool CG = MODE != SPMV_PLAIN;
+    constexpr int U = kSellU;
+    constexpr int W = kBS / 64;
+    __shared__ double ws[kBS / 64 + 1];
+    __shared__ int s_flag;
+    if (CG && !running(st, &s_flag)) return;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int rb = xcd_remap(blockIdx.x, gridDim.x);
+    const int cpb = (nchunks + (int)gridDim.x - 1) / (int)gridDim.x;
+    const int cend = min(rb * cpb + cpb, nchunks);
+    int c = rb * cpb + w;
+
+    // first batch of the first chunk, loaded before beta is known
+    int cc[U];
+    VT vv[U];
+    int base = 0, L = 0;
+    if (c < cend) {
+        base = cptr[c];
+        L = clen[c];
+        if (L > 0) {
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int k = base + min(u, L - 1) * 64 + lane;
+                cc[u] = col[k];
+                vv[u] = val[k];
+            }
+        }
+    }
+    double beta = 0.0;
+    if (MODE == SPMV_STEP) {
+        bool stop;
+        beta = finish_rr(part_b, nb, slot, st, ws, &stop);
+        if (stop) return;
+    }
+
     double acc = 0.0;
-    if (tile < ntiles) {
+    bool have = true;  // cc / vv hold batch 0 of chunk c
+    for (; c < cend; c += W) {
+        if (!have) {
+            base = cptr[c];
+            L = clen[c];
+        }
+        const int row = cpos[c] + lane;
+        const int len = row < nrows ? (int)rlen[row] : 0;
+        XT s = XT(0);
+        for (int j0 = 0; j0 < L; j0 += U) {
+            if (!have) {
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int k = base + min(j0 + u, L - 1) * 64 + lane;
+                    cc[u] = col[k];
+                    vv[u] = val[k];
+                }
+            }
+            have = false;
+            XT xx[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) xx[u] = CG ? pupd(r[cc[u]], pin[cc[u]], beta) : pin[cc[u]];
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (j0 + u < len) s = s + (XT)vv[u] * xx[u];
+        }
+        have = false;
+        if (row < nrows) {
+            q[row] = s;
+            if (CG) {
+                const XT pr = pupd(r[row], pin[row], beta);
+                pout[row] = pr;
+                acc = acc + (double)pr * (double)s;
+            }
+        }
+    }
+    if (CG) {
+        const double part = block_sum_all(acc, ws);
+        if (threadIdx.x == 0) part_a[blockIdx.x] = part;
+    }
+}
+
+// ---- local SpMV, CSR row tiles (rows of very uneven length) -------------------
+//
+// Workgroup w owns tiles [w*tpb, (w+1)*tpb); a tile is consecutive rows with
+// at most TN entries (or one longer row).  Values and columns are streamed
+// with coalesced loads into LDS products; then each row's thread adds its
+// products left to right.
+
+template <typename VT, typename XT, int TN, int MODE>
+__global__ __launch_bounds__(kBS) void k_spmv_csr(const int32_t *__restrict__ rowptr, const int32_t *__restrict__ col,
+                                                  const VT *__restrict__ val, const int32_t *__restrict__ tile_row,
+                                                  int32_t ntiles, const XT *__restrict__ pin,
+                                                  const XT *__restrict__ r, XT *__restrict__ pout,
+                                                  XT *__restrict__ q, double *__restrict__ part_a,
+                                                  const double *__restrict__ part_b, int32_t nb, int32_t slot,
+                                                  DevState *__restrict__ st)
+{
+    constexpr bool CG = MODE != SPMV_PLAIN;
+    constexpr int NI = TN / kBS;
+    __shared__ XT prod[TN];
+    __shared__ XT wsx[kBS / 64 + 1];
+    __shared__ double ws[kBS / 64 + 1];
+    __shared__ int s_flag;
+    if (CG && !running(st, &s_flag)) return;
+    double beta = 0.0;
+    if (MODE == SPMV_STEP) {
+        bool stop;
+        beta = finish_rr(part_b, nb, slot, st, ws, &stop);
+        if (stop) return;
+    }
+    const int rb = xcd_remap(blockIdx.x, gridDim.x);
+    const int tpb = (ntiles + (int)gridDim.x - 1) / (int)gridDim.x;
+    const int tend = min(rb * tpb + tpb, ntiles);
+    double acc = 0.0;
+    for (int tile = rb * tpb; tile < tend; ++tile) {
         const int r0 = tile_row[tile], r1 = tile_row[tile + 1];
         const int k0 = rowptr[r0], k1 = rowptr[r1];
         if (k1 - k0 <= TN) {
             if (k1 > k0) {
-                // Every load uses an index clamped into [k0, k1) so that all
-                // of them are issued back to back; only the stores are masked.
-                constexpr int NI = TN / kBS;
                 int jj[NI];
                 VT vv[NI];
                 XT xx[NI];
 #pragma unroll
-                for (int i = 0; i < NI; ++i)
-                    jj[i] = __builtin_nontemporal_load(colidx + min(k0 + (int)threadIdx.x + i * kBS, k1 - 1));
+                for (int i = 0; i < NI; ++i) jj[i] = col[min(k0 + (int)threadIdx.x + i * kBS, k1 - 1)];
 #pragma unroll
-                for (int i = 0; i < NI; ++i)
-                    vv[i] = __builtin_nontemporal_load(val + min(k0 + (int)threadIdx.x + i * kBS, k1 - 1));
+                for (int i = 0; i < NI; ++i) vv[i] = val[min(k0 + (int)threadIdx.x + i * kBS, k1 - 1)];
 #pragma unroll
                 for (int i = 0; i < NI; ++i) xx[i] = CG ? pupd(r[jj[i]], pin[jj[i]], beta) : pin[jj[i]];
 #pragma unroll
@@ -219,34 +303,29 @@ __global__ __launch_bounds__(kBS) void k_spmv(const int32_t *__restrict__ rowptr
                     acc = acc + (double)pr * (double)s;
                 }
             }
+            __syncthreads();
         } else {
-            // a single row longer than a tile: strided partial sums, then a
-            // fixed-order workgroup sum
+            // one row longer than a tile: strided partial sums, fixed-order tree
             XT s = XT(0);
             for (int k = k0 + (int)threadIdx.x; k < k1; k += kBS) {
-                const int j = colidx[k];
+                const int j = col[k];
                 const XT xj = CG ? pupd(r[j], pin[j], beta) : pin[j];
                 s = s + (XT)val[k] * xj;
             }
-            s = block_sum(s, wsx);
+            s = block_sum_all(s, wsx);
             if (threadIdx.x == 0) {
                 q[r0] = s;
                 if (CG) {
                     const XT pr = pupd(r[r0], pin[r0], beta);
                     pout[r0] = pr;
-                    acc = (double)pr * (double)s;
+                    acc = acc + (double)pr * (double)s;
                 }
             }
         }
     }
     if (CG) {
-        const double part = block_sum(acc, ws);
-        if (FUSED) {
-            const double v[1] = {part};
-            if (arrive(v, partial, &st->cnt[0])) finish_alpha(st, partial, gridDim.x, ws);
-        } else if (threadIdx.x == 0) {
-            partial[blockIdx.x] = part;
-        }
+        const double part = block_sum_all(acc, ws);
+        if (threadIdx.x == 0) part_a[blockIdx.x] = part;
     }
 }
 
@@ -272,132 +351,148 @@ __global__ __launch_bounds__(kBS) void k_iface_sum(int32_t ngamma, const int32_t
     for (int u = copy_ptr[g]; u < copy_ptr[g + 1]; ++u) q[copy_pos[u]] = t;
 }
 
-// ---- fused assembly + x / r update + (r, r) ----------------------------------
+// ---- alpha + assembly + x / r update + (r, r) partials ------------------------
+//
+// Workgroup b (in dispatch order, so the slower interface batches start
+// first) takes positions [b*B, b*B + B), B = kUI * kBS.
 
-template <typename XT, bool FUSED>
-__global__ __launch_bounds__(kBS) void k_update(const UpdBlock *__restrict__ blk, int32_t nblk,
+template <typename XT>
+__global__ __launch_bounds__(kBS) void k_update(int32_t n_loc, int32_t n_own, int32_t n_if,
                                                 const int32_t *__restrict__ pos_grp,
                                                 const int32_t *__restrict__ copy_ptr,
                                                 const int32_t *__restrict__ copy_pos, XT *__restrict__ x,
                                                 const XT *__restrict__ p, XT *__restrict__ r,
-                                                const XT *__restrict__ q, double *__restrict__ partial,
+                                                const XT *__restrict__ q, double *__restrict__ part_b,
+                                                const double *__restrict__ part_a, int32_t na, int32_t slot,
                                                 DevState *__restrict__ st)
 {
-    __shared__ double ws[kBS / 64];
-    if (st->status != ST_RUNNING) return;
-    const int bi = xcd_remap(blockIdx.x, gridDim.x);
+    constexpr int B = kUI * kBS;
+    __shared__ double ws[kBS / 64 + 1];
+    __shared__ int s_flag;
+    if (!running(st, &s_flag)) return;
+    const int b0 = (int)blockIdx.x * B;
+    // a full batch of interior positions: operands loaded before alpha is known
+    const bool plain = b0 >= n_if && b0 + B <= n_loc;
+    XT xv[kUI], pv[kUI], rv[kUI], qv[kUI];
+    if (plain) {
+#pragma unroll
+        for (int i = 0; i < kUI; ++i) {
+            const int c = b0 + (int)threadIdx.x + i * kBS;
+            xv[i] = x[c];
+            pv[i] = p[c];
+            rv[i] = r[c];
+            qv[i] = q[c];
+        }
+    }
+
+    // finish (p, A p): alpha, or a breakdown when it is not positive
+    const double pAp = sum_partials_all(part_a, na, ws);
+    const bool bad = !(pAp > 0.0) || !isfinite(pAp);
+    const double alpha = st->rr[slot] / pAp;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        st->pAp = pAp;
+        st->alpha = alpha;
+        if (bad) store_status(st, ST_BREAKDOWN);
+    }
+    if (bad) return;
+
     double acc = 0.0;
-    if (bi < nblk) {
-        const UpdBlock d = blk[bi];
-        const double alpha = st->alpha;
-        if (d.kind == 0) {
-            // interior positions: no assembly; clamped loads, masked stores
-            XT xv[kUI], pv[kUI], rv[kUI], qv[kUI];
+    if (plain) {
 #pragma unroll
-            for (int i = 0; i < kUI; ++i) {
-                const int c = d.start + min((int)threadIdx.x + i * kBS, d.count - 1);
-                xv[i] = x[c];
-                pv[i] = p[c];
-                rv[i] = r[c];
-                qv[i] = q[c];
-            }
-#pragma unroll
-            for (int i = 0; i < kUI; ++i) {
-                const int o = (int)threadIdx.x + i * kBS;
-                if (o < d.count) {
-                    const int c = d.start + o;
-                    x[c] = (XT)((double)xv[i] + alpha * (double)pv[i]);
-                    const XT rc = (XT)((double)rv[i] - alpha * (double)qv[i]);
-                    r[c] = rc;
-                    acc = acc + (double)rc * (double)rc;
-                }
-            }
-        } else {
-            for (int i = 0; i < kUI; ++i) {
-                const int o = (int)threadIdx.x + i * kBS;
-                if (o < d.count) {
-                    const int c = d.start + o;
-                    const XT qc = assembled(q, pos_grp[d.ifbase + o], copy_ptr, copy_pos);
-                    x[c] = (XT)((double)x[c] + alpha * (double)p[c]);
-                    const XT rc = (XT)((double)r[c] - alpha * (double)qc);
-                    r[c] = rc;
-                    if (d.kind != 2) acc = acc + (double)rc * (double)rc;
-                }
+        for (int i = 0; i < kUI; ++i) {
+            const int c = b0 + (int)threadIdx.x + i * kBS;
+            x[c] = (XT)((double)xv[i] + alpha * (double)pv[i]);
+            const XT rc = (XT)((double)rv[i] - alpha * (double)qv[i]);
+            r[c] = rc;
+            acc = acc + (double)rc * (double)rc;
+        }
+    } else {
+        for (int i = 0; i < kUI; ++i) {
+            const int c = b0 + (int)threadIdx.x + i * kBS;
+            if (c < n_loc) {
+                const XT qc = c >= n_if ? q[c] : assembled(q, pos_grp[c], copy_ptr, copy_pos);
+                x[c] = (XT)((double)x[c] + alpha * (double)p[c]);
+                const XT rc = (XT)((double)r[c] - alpha * (double)qc);
+                r[c] = rc;
+                if (c < n_own || c >= n_if) acc = acc + (double)rc * (double)rc;
             }
         }
     }
-    const double part = block_sum(acc, ws);
-    if (FUSED) {
-        const double v[1] = {part};
-        if (arrive(v, partial, &st->cnt[1])) finish_beta(st, partial, gridDim.x, ws);
-    } else if (threadIdx.x == 0) {
-        partial[blockIdx.x] = part;
-    }
+    const double part = block_sum_all(acc, ws);
+    if (threadIdx.x == 0) part_b[blockIdx.x] = part;
 }
 
 // ---- fresh residual r = b - A x (assembly of q = A_bd x included) -----------
 
-template <typename XT, bool FIRST, bool FUSED>
-__global__ __launch_bounds__(kBS) void k_residual(const UpdBlock *__restrict__ blk, int32_t nblk,
+template <typename XT, bool FIRST>
+__global__ __launch_bounds__(kBS) void k_residual(int32_t n_loc, int32_t n_own, int32_t n_if,
                                                   const int32_t *__restrict__ pos_grp,
                                                   const int32_t *__restrict__ copy_ptr,
                                                   const int32_t *__restrict__ copy_pos, const XT *__restrict__ b,
                                                   const XT *__restrict__ q, XT *__restrict__ r, XT *__restrict__ p0,
-                                                  double *__restrict__ partial, DevState *__restrict__ st)
+                                                  double *__restrict__ partial)
 {
-    __shared__ double ws[kBS / 64];
-    const int bi = xcd_remap(blockIdx.x, gridDim.x);
+    constexpr int B = kUI * kBS;
+    __shared__ double ws[kBS / 64 + 1];
+    const int b0 = (int)blockIdx.x * B;
     double arr = 0.0, abb = 0.0;
-    if (bi < nblk) {
-        const UpdBlock d = blk[bi];
-#pragma unroll
-        for (int i = 0; i < kUI; ++i) {
-            const int o = (int)threadIdx.x + i * kBS;
-            if (o < d.count) {
-                const int c = d.start + o;
-                const XT qc = d.kind == 0 ? q[c] : assembled(q, pos_grp[d.ifbase + o], copy_ptr, copy_pos);
-                const XT bc = b[c];
-                const XT rc = bc - qc;
-                r[c] = rc;
-                p0[c] = rc;
-                if (d.kind != 2) {
-                    arr = arr + (double)rc * (double)rc;
-                    if (FIRST) abb = abb + (double)bc * (double)bc;
-                }
+    for (int i = 0; i < kUI; ++i) {
+        const int c = b0 + (int)threadIdx.x + i * kBS;
+        if (c < n_loc) {
+            const XT qc = c >= n_if ? q[c] : assembled(q, pos_grp[c], copy_ptr, copy_pos);
+            const XT bc = b[c];
+            const XT rc = bc - qc;
+            r[c] = rc;
+            p0[c] = rc;
+            if (c < n_own || c >= n_if) {
+                arr = arr + (double)rc * (double)rc;
+                if (FIRST) abb = abb + (double)bc * (double)bc;
             }
         }
     }
-    const double prr = block_sum(arr, ws);
-    const double pbb = FIRST ? block_sum(abb, ws) : 0.0;
-    if (FUSED) {
-        const double v[2] = {prr, pbb};
-        if (arrive(v, partial, &st->cnt[2])) finish_residual(st, partial, gridDim.x, FIRST, ws);
-    } else if (threadIdx.x == 0) {
+    const double prr = block_sum_all(arr, ws);
+    const double pbb = FIRST ? block_sum_all(abb, ws) : 0.0;
+    if (threadIdx.x == 0) {
         partial[blockIdx.x] = prr;
         partial[gridDim.x + blockIdx.x] = pbb;
     }
 }
 
-// ---- separate finishing kernels (one workgroup) ------------------------------
-
-__global__ __launch_bounds__(kBS) void k_finish_alpha(DevState *st, const double *partial, int n)
-{
-    __shared__ double ws[kBS / 64];
-    if (st->status != ST_RUNNING) return;
-    finish_alpha(st, partial, n, ws);
-}
-
-__global__ __launch_bounds__(kBS) void k_finish_beta(DevState *st, const double *partial, int n)
-{
-    __shared__ double ws[kBS / 64];
-    if (st->status != ST_RUNNING) return;
-    finish_beta(st, partial, n, ws);
-}
-
+// One workgroup: (r, r) [and (b, b)], the stopping test, slot 0 of the state.
 __global__ __launch_bounds__(kBS) void k_finish_residual(DevState *st, const double *partial, int n, int first)
 {
-    __shared__ double ws[kBS / 64];
-    finish_residual(st, partial, n, first != 0, ws);
+    __shared__ double ws[kBS / 64 + 1];
+    const double rr = sum_partials_all(partial, n, ws);
+    const double bb = first ? sum_partials_all(partial + n, n, ws) : 0.0;
+    if (threadIdx.x != 0) return;
+    if (first) {
+        st->bb = bb;
+        if (!isfinite(bb)) {
+            store_status(st, ST_BREAKDOWN);
+            return;
+        }
+        if (bb == 0.0) {
+            if (st->hist && st->hist_cap > 0) st->hist[0] = 0.0;
+            store_status(st, ST_ZERO_RHS);
+            return;
+        }
+        st->stop = st->tol * sqrt(bb);
+    }
+    if (!isfinite(rr)) {
+        store_status(st, ST_BREAKDOWN);
+        return;
+    }
+    const int k = st->iter_last;
+    st->rr[0] = rr;
+    st->iter[0] = k;
+    st->rr_last = rr;
+    if (st->hist && k < st->hist_cap) st->hist[k] = sqrt(rr / st->bb);
+    if (sqrt(rr) <= st->stop)
+        store_status(st, ST_CONVERGED);
+    else if (k >= st->kmax)
+        store_status(st, ST_MAXIT);
+    else
+        store_status(st, ST_RUNNING);
 }
 
 // ---- gathers, scatters, gradient -------------------------------------------
@@ -421,30 +516,67 @@ __global__ __launch_bounds__(kBS) void k_scatter(int32_t n, const int32_t *__res
     dst[i] = zero ? 0.0 : (double)src[g2own[i]];
 }
 
-__global__ __launch_bounds__(kBS) void k_grad_vals(int32_t n_loc, const int32_t *__restrict__ rowptr,
-                                                   const int32_t *__restrict__ colidx,
-                                                   const int32_t *__restrict__ nzmap, const int32_t *__restrict__ l2g,
-                                                   const double *__restrict__ lambda, const double *__restrict__ x,
-                                                   double *__restrict__ dvals)
+// one thread per row: SELL threads walk the stored chunks (lane = row of the
+// chunk), CSR threads the rows
+__global__ __launch_bounds__(kBS) void k_grad_vals(Mat A, const int32_t *__restrict__ nzmap,
+                                                   const int32_t *__restrict__ l2g, const double *__restrict__ lambda,
+                                                   const double *__restrict__ x, double *__restrict__ dvals)
 {
-    const int c = blockIdx.x * kBS + threadIdx.x;
-    if (c >= n_loc) return;
-    const double li = lambda[l2g[c]];
-    for (int e = rowptr[c]; e < rowptr[c + 1]; ++e) dvals[nzmap[e]] = -(li * x[l2g[colidx[e]]]);
+    const int t = blockIdx.x * kBS + threadIdx.x;
+    if (A.fmt == FMT_SELL) {
+        const int c = t >> 6, lane = t & 63;
+        if (c >= A.nchunks) return;
+        const int row = A.cpos[c] + lane;
+        if (row >= A.nrows) return;
+        const double li = lambda[l2g[row]];
+        const int base = A.cptr[c], len = A.rlen[row];
+        for (int j = 0; j < len; ++j) {
+            const int k = base + j * 64 + lane;
+            dvals[nzmap[k]] = -(li * x[l2g[A.col[k]]]);
+        }
+    } else {
+        if (t >= A.nrows) return;
+        const double li = lambda[l2g[t]];
+        for (int k = A.rowptr[t]; k < A.rowptr[t + 1]; ++k) dvals[nzmap[k]] = -(li * x[l2g[A.col[k]]]);
+    }
 }
 
-__global__ __launch_bounds__(kBS) void k_set_values(int64_t nnz, const int32_t *__restrict__ nzmap,
+__global__ __launch_bounds__(kBS) void k_set_values(int64_t len, const int32_t *__restrict__ nzmap,
                                                     const double *__restrict__ src, double *__restrict__ v64,
                                                     float *__restrict__ v32)
 {
     const int64_t e = (int64_t)blockIdx.x * kBS + threadIdx.x;
-    if (e >= nnz) return;
-    const double v = src[nzmap[e]];
+    if (e >= len) return;
+    const int m = nzmap[e];
+    const double v = m >= 0 ? src[m] : 0.0;
     v64[e] = v;
     if (v32) v32[e] = (float)v;
 }
 
 inline int nblocks(int64_t n) { return (int)((n + kBS - 1) / kBS); }
+
+template <typename VT, typename XT, int MODE>
+void spmv_dispatch(hipStream_t s, const Mat &A, const XT *pin, const XT *r, XT *pout, XT *q, Partials P,
+                   DevState *st, int slot)
+{
+    if (A.nrows == 0) return;
+    const dim3 grid(A.grid), block(kBS);
+    if (A.fmt == FMT_SELL) {
+        hipLaunchKernelGGL((k_spmv_sell<VT, XT, MODE>), grid, block, 0, s, A.nrows, A.nchunks, A.cptr, A.cpos, A.clen,
+                           A.rlen,
+                           A.col, (const VT *)A.val, pin, r, pout, q, P.a, (const double *)P.b, P.nb, slot, st);
+        return;
+    }
+#define SS_SPMV(TN)                                                                                              \
+    hipLaunchKernelGGL((k_spmv_csr<VT, XT, TN, MODE>), grid, block, 0, s, A.rowptr, A.col, (const VT *)A.val,    \
+                       A.tile_row, A.ntiles, pin, r, pout, q, P.a, (const double *)P.b, P.nb, slot, st)
+    switch (A.tile_nnz) {
+    case 1024: SS_SPMV(1024); break;
+    case 4096: SS_SPMV(4096); break;
+    default: SS_SPMV(2048); break;
+    }
+#undef SS_SPMV
+}
 
 }  // namespace
 
@@ -462,42 +594,24 @@ void launch_scatter(hipStream_t s, int32_t n, const int32_t *g2own, const XT *sr
     if (n > 0) hipLaunchKernelGGL(k_scatter<XT>, dim3(nblocks(n)), dim3(kBS), 0, s, n, g2own, src, dst, st);
 }
 
-template <typename VT, typename XT, int TN, bool CG, bool FUSED>
-static void spmv_tn(hipStream_t s, const Csr &A, const XT *pin, const XT *r, XT *pout, XT *q, double *partial,
-                    DevState *st)
+template <typename VT, typename XT>
+void launch_spmv(hipStream_t s, const Mat &A, const XT *x, XT *q)
 {
-    hipLaunchKernelGGL((k_spmv<VT, XT, TN, CG, FUSED>), dim3(xcd_grid(A.ntiles)), dim3(kBS), 0, s, A.rowptr, A.colidx,
-                       (const VT *)A.val, A.tile_row, A.ntiles, pin, r, pout, q, partial, st);
-}
-
-template <typename VT, typename XT, bool CG, bool FUSED>
-static void spmv_dispatch(hipStream_t s, const Csr &A, const XT *pin, const XT *r, XT *pout, XT *q, double *partial,
-                          DevState *st)
-{
-    if (A.ntiles == 0) return;
-    switch (A.tile_nnz) {
-    case 1024: spmv_tn<VT, XT, 1024, CG, FUSED>(s, A, pin, r, pout, q, partial, st); break;
-    case 4096: spmv_tn<VT, XT, 4096, CG, FUSED>(s, A, pin, r, pout, q, partial, st); break;
-    default: spmv_tn<VT, XT, 2048, CG, FUSED>(s, A, pin, r, pout, q, partial, st); break;
-    }
+    spmv_dispatch<VT, XT, SPMV_PLAIN>(s, A, x, nullptr, nullptr, q, Partials{nullptr, nullptr, 0, 0}, nullptr, 0);
 }
 
 template <typename VT, typename XT>
-void launch_spmv(hipStream_t s, const Csr &A, const XT *x, XT *q)
+void launch_spmv_first(hipStream_t s, const Mat &A, const XT *pin, const XT *r, XT *pout, XT *q, Partials P,
+                       DevState *st)
 {
-    spmv_dispatch<VT, XT, false, false>(s, A, x, nullptr, nullptr, q, nullptr, nullptr);
+    spmv_dispatch<VT, XT, SPMV_FIRST>(s, A, pin, r, pout, q, P, st, 0);
 }
 
 template <typename VT, typename XT>
-void launch_spmv_cg(hipStream_t s, const Csr &A, const XT *pin, const XT *r, XT *pout, XT *q, double *partial,
-                    DevState *st, bool fused)
+void launch_spmv_step(hipStream_t s, const Mat &A, const XT *pin, const XT *r, XT *pout, XT *q, Partials P,
+                      DevState *st, int slot)
 {
-    if (fused) {
-        spmv_dispatch<VT, XT, true, true>(s, A, pin, r, pout, q, partial, st);
-    } else {
-        spmv_dispatch<VT, XT, true, false>(s, A, pin, r, pout, q, partial, st);
-        hipLaunchKernelGGL(k_finish_alpha, dim3(1), dim3(kBS), 0, s, st, partial, xcd_grid(A.ntiles));
-    }
+    spmv_dispatch<VT, XT, SPMV_STEP>(s, A, pin, r, pout, q, P, st, slot);
 }
 
 template <typename XT>
@@ -509,74 +623,57 @@ void launch_iface_sum(hipStream_t s, const Iface &I, XT *q)
 }
 
 template <typename XT>
-void launch_update(hipStream_t s, const Iface &I, XT *x, const XT *p, XT *r, const XT *q, double *partial,
-                   DevState *st, bool fused)
+void launch_update(hipStream_t s, const Iface &I, XT *x, const XT *p, XT *r, const XT *q, Partials P, DevState *st,
+                   int slot)
 {
-    const int grid = xcd_grid(I.nblk);
-    if (fused) {
-        hipLaunchKernelGGL((k_update<XT, true>), dim3(grid), dim3(kBS), 0, s, I.blk, I.nblk, I.pos_grp, I.copy_ptr,
-                           I.copy_pos, x, p, r, q, partial, st);
-    } else {
-        hipLaunchKernelGGL((k_update<XT, false>), dim3(grid), dim3(kBS), 0, s, I.blk, I.nblk, I.pos_grp, I.copy_ptr,
-                           I.copy_pos, x, p, r, q, partial, st);
-        hipLaunchKernelGGL(k_finish_beta, dim3(1), dim3(kBS), 0, s, st, partial, grid);
-    }
+    hipLaunchKernelGGL(k_update<XT>, dim3(I.grid), dim3(kBS), 0, s, I.n_loc, I.n_own, I.n_if, I.pos_grp,
+                       I.copy_ptr, I.copy_pos, x, p, r, q, P.b, (const double *)P.a, P.na, slot, st);
 }
 
 template <typename XT>
 void launch_residual(hipStream_t s, const Iface &I, const XT *b, const XT *q, XT *r, XT *p0, double *partial,
-                     DevState *st, bool first, bool fused)
+                     DevState *st, bool first)
 {
-    const int grid = xcd_grid(I.nblk);
-#define SS_RES(F, U)                                                                                              \
-    hipLaunchKernelGGL((k_residual<XT, F, U>), dim3(grid), dim3(kBS), 0, s, I.blk, I.nblk, I.pos_grp, I.copy_ptr, \
-                       I.copy_pos, b, q, r, p0, partial, st)
-    if (fused) {
-        if (first) SS_RES(true, true);
-        else SS_RES(false, true);
-    } else {
-        if (first) SS_RES(true, false);
-        else SS_RES(false, false);
-        hipLaunchKernelGGL(k_finish_residual, dim3(1), dim3(kBS), 0, s, st, partial, grid, first ? 1 : 0);
-    }
-#undef SS_RES
+    if (first)
+        hipLaunchKernelGGL((k_residual<XT, true>), dim3(I.grid), dim3(kBS), 0, s, I.n_loc, I.n_own, I.n_if,
+                           I.pos_grp, I.copy_ptr, I.copy_pos, b, q, r, p0, partial);
+    else
+        hipLaunchKernelGGL((k_residual<XT, false>), dim3(I.grid), dim3(kBS), 0, s, I.n_loc, I.n_own, I.n_if,
+                           I.pos_grp, I.copy_ptr, I.copy_pos, b, q, r, p0, partial);
+    hipLaunchKernelGGL(k_finish_residual, dim3(1), dim3(kBS), 0, s, st, partial, I.grid, first ? 1 : 0);
 }
 
-void launch_grad_vals(hipStream_t s, int32_t n_loc, const int32_t *rowptr, const int32_t *colidx, const int32_t *nzmap,
-                      const int32_t *l2g, const double *lambda, const double *x, double *dvals)
+void launch_grad_vals(hipStream_t s, const Mat &A, const int32_t *nzmap, const int32_t *l2g, const double *lambda,
+                      const double *x, double *dvals)
 {
-    if (n_loc > 0)
-        hipLaunchKernelGGL(k_grad_vals, dim3(nblocks(n_loc)), dim3(kBS), 0, s, n_loc, rowptr, colidx, nzmap, l2g,
-                           lambda, x, dvals);
+    const int64_t threads = A.fmt == FMT_SELL ? (int64_t)A.nchunks * 64 : A.nrows;
+    if (threads > 0)
+        hipLaunchKernelGGL(k_grad_vals, dim3(nblocks(threads)), dim3(kBS), 0, s, A, nzmap, l2g, lambda, x, dvals);
 }
 
-void launch_set_values(hipStream_t s, int64_t nnz, const int32_t *nzmap, const double *val_glob, double *val64,
+void launch_set_values(hipStream_t s, int64_t len, const int32_t *nzmap, const double *val_glob, double *val64,
                        float *val32)
 {
-    if (nnz > 0)
-        hipLaunchKernelGGL(k_set_values, dim3(nblocks(nnz)), dim3(kBS), 0, s, nnz, nzmap, val_glob, val64, val32);
+    if (len > 0)
+        hipLaunchKernelGGL(k_set_values, dim3(nblocks(len)), dim3(kBS), 0, s, len, nzmap, val_glob, val64, val32);
 }
 
 // explicit instantiations
-template void launch_gather<double>(hipStream_t, int32_t, const int32_t *, const double *, double *);
-template void launch_gather<float>(hipStream_t, int32_t, const int32_t *, const double *, float *);
-template void launch_scatter<double>(hipStream_t, int32_t, const int32_t *, const double *, double *, const DevState *);
-template void launch_scatter<float>(hipStream_t, int32_t, const int32_t *, const float *, double *, const DevState *);
-template void launch_spmv<double, double>(hipStream_t, const Csr &, const double *, double *);
-template void launch_spmv<float, float>(hipStream_t, const Csr &, const float *, float *);
-template void launch_spmv_cg<double, double>(hipStream_t, const Csr &, const double *, const double *, double *,
-                                             double *, double *, DevState *, bool);
-template void launch_spmv_cg<float, float>(hipStream_t, const Csr &, const float *, const float *, float *, float *,
-                                           double *, DevState *, bool);
-template void launch_iface_sum<double>(hipStream_t, const Iface &, double *);
-template void launch_iface_sum<float>(hipStream_t, const Iface &, float *);
-template void launch_update<double>(hipStream_t, const Iface &, double *, const double *, double *, const double *,
-                                    double *, DevState *, bool);
-template void launch_update<float>(hipStream_t, const Iface &, float *, const float *, float *, const float *,
-                                   double *, DevState *, bool);
-template void launch_residual<double>(hipStream_t, const Iface &, const double *, const double *, double *, double *,
-                                      double *, DevState *, bool, bool);
-template void launch_residual<float>(hipStream_t, const Iface &, const float *, const float *, float *, float *,
-                                     double *, DevState *, bool, bool);
+#define SS_INST(XT)                                                                                                  \
+    template void launch_gather<XT>(hipStream_t, int32_t, const int32_t *, const double *, XT *);                    \
+    template void launch_scatter<XT>(hipStream_t, int32_t, const int32_t *, const XT *, double *, const DevState *); \
+    template void launch_spmv<XT, XT>(hipStream_t, const Mat &, const XT *, XT *);                                   \
+    template void launch_spmv_first<XT, XT>(hipStream_t, const Mat &, const XT *, const XT *, XT *, XT *, Partials,  \
+                                            DevState *);                                                             \
+    template void launch_spmv_step<XT, XT>(hipStream_t, const Mat &, const XT *, const XT *, XT *, XT *, Partials,   \
+                                           DevState *, int);                                                         \
+    template void launch_iface_sum<XT>(hipStream_t, const Iface &, XT *);                                            \
+    template void launch_update<XT>(hipStream_t, const Iface &, XT *, const XT *, XT *, const XT *, Partials,        \
+                                    DevState *, int);                                                                \
+    template void launch_residual<XT>(hipStream_t, const Iface &, const XT *, const XT *, XT *, XT *, double *,      \
+                                      DevState *, bool);
+SS_INST(double)
+SS_INST(float)
+#undef SS_INST
 
 }  // namespace ss

@@ -1,6 +1,6 @@
-// Solver driver: device setup, the CG loop of Algorithm 3 with device-resident
-// scalars, HIP-graph replay of polled iteration chunks, and the remaining
-// C-ABI entry points of ss.h.
+// Solver driver: device layout and setup, the CG loop of Algorithm 3 with
+// device-resident scalars, HIP-graph replay of polled iteration chunks, and
+// the solver entry points of ss.h.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -19,6 +19,8 @@ namespace {
 
 constexpr int kDefaultCheck = 32;
 constexpr int32_t kHistMax = 1 << 22;  // residual history entries kept on the device
+constexpr int kSpmvGridMax = 1024;      // persistent SpMV workgroups (4 per CU)
+constexpr int kGridLimit = 65536;       // upper bound accepted for a requested grid
 
 struct DeviceMem {
     ss_alloc_fn alloc = nullptr;
@@ -62,11 +64,170 @@ struct DeviceMem {
     }
 };
 
-#define SS_HIP(call)                                                                         \
-    do {                                                                                     \
-        hipError_t e_ = (call);                                                              \
+#define SS_HIP(call)                                                                                         \
+    do {                                                                                                     \
+        hipError_t e_ = (call);                                                                              \
         if (e_ != hipSuccess) return fail(SS_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
     } while (0)
+
+// Host image of the device data of one partition.
+struct Layout {
+    // device position of every concatenated local position
+    std::vector<int32_t> dev_pos;
+    int32_t n_own = 0, n_if = 0;
+    std::vector<int32_t> l2g, g2own, copy_pos, pos_grp;
+    // matrix in device order
+    int fmt = FMT_SELL;
+    std::vector<int32_t> col, nzmap;  // storage order (SELL padded: nzmap = -1)
+    std::vector<int32_t> cptr, cpos, rowptr, tile_row;
+    std::vector<uint8_t> clen, rlen;
+    int32_t nchunks = 0, ntiles = 0, tile_nnz = 2048;
+    int64_t stored = 0;  // entries incl. padding
+};
+
+// Device order: all owned interface copies (sub-domain by sub-domain), then
+// all other interface copies, then every sub-domain's interior positions, the
+// local order kept inside each group.  Within one local row all columns
+// belong to the same sub-domain and keep their relative order, so row sums
+// are unchanged.  Interface positions come first so that their (slower,
+// gathering) update batches are dispatched first.
+void build_order(const ss_part *p, Layout &L)
+{
+    const int32_t P = p->P, nl = p->n_loc();
+    L.dev_pos.assign(nl, -1);
+    int32_t tot_int = 0, tot_own = 0;
+    for (int32_t s = 0; s < P; ++s) {
+        tot_int += p->n_int[s];
+        tot_own += p->n_own[s];
+    }
+    const int32_t tot_if = nl - tot_int;
+    int32_t a = tot_if, b = 0, c = tot_own;
+    for (int32_t s = 0; s < P; ++s) {
+        const int32_t o = p->sub_off[s], i1 = o + p->n_int[s], i2 = i1 + p->n_own[s], e = p->sub_off[s + 1];
+        for (int32_t u = o; u < i1; ++u) L.dev_pos[u] = a++;
+        for (int32_t u = i1; u < i2; ++u) L.dev_pos[u] = b++;
+        for (int32_t u = i2; u < e; ++u) L.dev_pos[u] = c++;
+    }
+    L.n_own = tot_own;
+    L.n_if = tot_if;
+    L.l2g.assign(nl, 0);
+    for (int32_t u = 0; u < nl; ++u) L.l2g[L.dev_pos[u]] = p->l2g[u];
+    L.g2own.resize(p->n);
+    for (int32_t i = 0; i < p->n; ++i) L.g2own[i] = L.dev_pos[p->g2own[i]];
+    L.copy_pos.resize(p->copy_pos.size());
+    for (size_t u = 0; u < p->copy_pos.size(); ++u) L.copy_pos[u] = L.dev_pos[p->copy_pos[u]];
+    L.pos_grp.assign((size_t)tot_if, -1);
+    for (size_t g = 0; g + 1 < p->copy_ptr.size(); ++g)
+        for (int32_t u = p->copy_ptr[g]; u < p->copy_ptr[g + 1]; ++u) L.pos_grp[L.copy_pos[u]] = (int32_t)g;
+}
+
+// Matrix storage.  SELL-64 unless a row is longer than 255 entries or the
+// chunk padding would add more than a quarter to the stored entries; then
+// CSR row tiles.  `force` = SS_MAT_* selection from the options.
+void build_matrix(const ss_part *p, Layout &L, int32_t tile_nnz, int32_t force)
+{
+    const int32_t nl = p->n_loc();
+    // rows in device order
+    std::vector<int32_t> src_row(nl);
+    for (int32_t u = 0; u < nl; ++u) src_row[L.dev_pos[u]] = u;
+    auto row_len = [&](int32_t t) { return p->bd_rowptr[src_row[t] + 1] - p->bd_rowptr[src_row[t]]; };
+    int32_t maxlen = 0;
+    for (int32_t t = 0; t < nl; ++t) maxlen = std::max(maxlen, row_len(t));
+    const int32_t nch = (nl + 63) / 64;
+    int64_t padded = 0;
+    for (int32_t c = 0; c < nch; ++c) {
+        int32_t m = 0;
+        for (int32_t t = c * 64; t < std::min(nl, c * 64 + 64); ++t) m = std::max(m, row_len(t));
+        padded += 64 * (int64_t)m;
+    }
+    const bool sell_ok = maxlen <= 255 && padded < INT32_MAX;
+    bool sell = sell_ok && padded <= p->nnz + p->nnz / 4;
+    if (force == SS_MAT_SELL && sell_ok) sell = true;
+    if (force == SS_MAT_CSR) sell = false;
+    L.tile_nnz = tile_nnz;
+    if (sell) {
+        L.fmt = FMT_SELL;
+        L.nchunks = nch;
+        L.rlen.assign(nl, 0);
+        for (int32_t t = 0; t < nl; ++t) L.rlen[t] = (uint8_t)row_len(t);
+        // processing order: the chunks holding interface rows (positions
+        // [0, n_if)) are spread evenly among the interior chunks
+        const int32_t nif_ch = (L.n_if + 63) / 64;
+        std::vector<int32_t> order;
+        order.reserve(nch);
+        int64_t placed_if = 0;
+        int32_t next_if = 0, next_in = nif_ch;
+        for (int32_t i = 0; i < nch; ++i) {
+            const bool take_if = next_if < nif_ch &&
+                                 (next_in >= nch || (int64_t)(i + 1) * nif_ch > placed_if * nch);
+            if (take_if) {
+                order.push_back(next_if++);
+                ++placed_if;
+            } else {
+                order.push_back(next_in++);
+            }
+        }
+        L.cptr.assign(nch + 1, 0);
+        L.cpos.assign(nch, 0);
+        L.clen.assign(nch, 0);
+        for (int32_t i = 0; i < nch; ++i) {
+            const int32_t id = order[i];
+            int32_t m = 0;
+            for (int32_t t = id * 64; t < std::min(nl, id * 64 + 64); ++t) m = std::max(m, (int32_t)L.rlen[t]);
+            L.cpos[i] = id * 64;
+            L.clen[i] = (uint8_t)m;
+            L.cptr[i + 1] = L.cptr[i] + 64 * m;
+        }
+        L.stored = L.cptr[nch];
+        // padding points at a valid position (the row itself, or 0 past the
+        // last row) and is masked out by the row length
+        L.col.assign((size_t)L.stored, 0);
+        L.nzmap.assign((size_t)L.stored, -1);
+        for (int32_t i = 0; i < nch; ++i)
+            for (int32_t lane = 0; lane < 64; ++lane) {
+                const int32_t t = L.cpos[i] + lane;
+                const int32_t len = t < nl ? L.rlen[t] : 0;
+                for (int32_t j = 0; j < L.clen[i]; ++j) {
+                    const int64_t k = L.cptr[i] + (int64_t)j * 64 + lane;
+                    if (j < len) {
+                        const int32_t e = p->bd_rowptr[src_row[t]] + j;
+                        L.col[k] = L.dev_pos[p->bd_colidx[e]];
+                        L.nzmap[k] = p->bd_nzmap[e];
+                    } else {
+                        L.col[k] = t < nl ? t : 0;
+                    }
+                }
+            }
+    } else {
+        L.fmt = FMT_CSR;
+        L.rowptr.assign(nl + 1, 0);
+        for (int32_t t = 0; t < nl; ++t) L.rowptr[t + 1] = L.rowptr[t] + row_len(t);
+        L.stored = L.rowptr[nl];
+        L.col.resize((size_t)L.stored);
+        L.nzmap.resize((size_t)L.stored);
+        for (int32_t t = 0; t < nl; ++t) {
+            const int32_t u = src_row[t];
+            for (int32_t e = p->bd_rowptr[u], k = L.rowptr[t]; e < p->bd_rowptr[u + 1]; ++e, ++k) {
+                L.col[k] = L.dev_pos[p->bd_colidx[e]];
+                L.nzmap[k] = p->bd_nzmap[e];
+            }
+        }
+        // row tiles: at most tile_nnz entries and 4 * workgroup rows; a longer
+        // row is a tile of its own
+        L.tile_row.assign(1, 0);
+        int32_t r0 = 0;
+        while (r0 < nl) {
+            int32_t r = r0;
+            if (L.rowptr[r0 + 1] - L.rowptr[r0] > tile_nnz)
+                r = r0 + 1;
+            else
+                while (r < nl && r - r0 < 4 * kBS && L.rowptr[r + 1] - L.rowptr[r0] <= tile_nnz) ++r;
+            L.tile_row.push_back(r);
+            r0 = r;
+        }
+        L.ntiles = (int32_t)L.tile_row.size() - 1;
+    }
+}
 
 }  // namespace
 
@@ -77,94 +238,42 @@ struct ss_solver {
     ss_opts opts{};
     DeviceMem mem;
 
-    int32_t n = 0, n_loc = 0, P = 0, ngamma = 0, ncopies = 0;
+    int32_t n = 0, n_loc = 0, P = 0, ngamma = 0;
     int64_t nnz = 0;
 
-    // matrix and maps
-    int32_t *rowptr = nullptr, *colidx = nullptr, *tile_row = nullptr, *nzmap = nullptr;
+    Mat mat{};
+    Iface ifc{};
+    int32_t *nzmap = nullptr;  // storage order -> global stored entry (-1: padding)
     double *val = nullptr;
-    float *val32 = nullptr;
-    int32_t *l2g = nullptr, *g2own = nullptr, *copy_ptr = nullptr, *copy_pos = nullptr, *pos_grp = nullptr;
-    UpdBlock *ublk = nullptr;
-    int32_t ntiles = 0, nublk = 0, tile_nnz = 2048;
+    int32_t *l2g = nullptr, *g2own = nullptr;
+    int64_t stored = 0;
 
-    // FP64 work vectors (concatenated local numbering)
+    // FP64 work vectors (device position order)
     double *b = nullptr, *x = nullptr, *r = nullptr, *p0 = nullptr, *p1 = nullptr, *q = nullptr;
-    double *partial = nullptr;
-    size_t partial_len = 0;
+    double *part_a = nullptr, *part_b = nullptr, *part_r = nullptr;  // SpMV, update, residual partials
     DevState *st = nullptr;
     double *hist = nullptr;
     int32_t hist_cap = 0;
 
     // host side
-    DevState *st_pinned = nullptr;     // readback of the state
-    int32_t *flag_pinned = nullptr;    // two status slots for pipelined polling
+    DevState *st_pinned = nullptr;   // readback of the state
+    int32_t *flag_pinned = nullptr;  // two status slots for pipelined polling
     hipEvent_t ev[2] = {nullptr, nullptr};
-    hipEvent_t t0 = nullptr, t1 = nullptr;
 
     // graph of one polled chunk
     hipGraphExec_t chunk_exec = nullptr;
     hipGraph_t chunk_graph = nullptr;
     int32_t chunk_iters = 0;
 
-    Csr csr64() const { return Csr{rowptr, colidx, tile_row, val, ntiles, tile_nnz}; }
-    Iface iface() const { return Iface{ublk, nublk, pos_grp, copy_ptr, copy_pos, ngamma}; }
+    Partials partials() const { return Partials{part_a, part_b, mat.grid, ifc.grid}; }
 };
 
 namespace {
 
-// Row tiles: consecutive rows with at most tile_nnz stored entries (and at
-// most 4 * workgroup rows); a longer row forms a tile of its own.
-std::vector<int32_t> build_tiles(const std::vector<int32_t> &rowptr, int32_t tile_nnz)
-{
-    const int32_t nrows = (int32_t)rowptr.size() - 1;
-    const int32_t rmax = 4 * kBS;
-    std::vector<int32_t> t;
-    t.push_back(0);
-    int32_t r0 = 0;
-    while (r0 < nrows) {
-        int32_t r = r0;
-        if (rowptr[r0 + 1] - rowptr[r0] > tile_nnz) {
-            r = r0 + 1;
-        } else {
-            while (r < nrows && r - r0 < rmax && rowptr[r + 1] - rowptr[r0] <= tile_nnz) ++r;
-        }
-        t.push_back(r);
-        r0 = r;
-    }
-    return t;
-}
-
-// Workgroups of the update / residual kernels: per sub-domain, the interior,
-// owned-interface and other-interface ranges cut into pieces of kBS * kUI.
-void build_update_blocks(const ss_part *p, std::vector<UpdBlock> &blk, std::vector<int32_t> &pos_grp)
-{
-    const int32_t chunk = kBS * kUI;
-    const int32_t nl = p->n_loc();
-    // interface index of every interface position
-    std::vector<int32_t> ifidx(nl, -1);
-    int32_t nif = 0;
-    for (int32_t s = 0; s < p->P; ++s)
-        for (int32_t c = p->sub_off[s] + p->n_int[s]; c < p->sub_off[s + 1]; ++c) ifidx[c] = nif++;
-    pos_grp.assign(nif, -1);
-    for (size_t g = 0; g + 1 < p->copy_ptr.size(); ++g)
-        for (int32_t u = p->copy_ptr[g]; u < p->copy_ptr[g + 1]; ++u) pos_grp[ifidx[p->copy_pos[u]]] = (int32_t)g;
-    blk.clear();
-    for (int32_t s = 0; s < p->P; ++s) {
-        const int32_t a = p->sub_off[s];
-        const int32_t bounds[4] = {a, a + p->n_int[s], a + p->n_int[s] + p->n_own[s], p->sub_off[s + 1]};
-        for (int kind = 0; kind < 3; ++kind)
-            for (int32_t c = bounds[kind]; c < bounds[kind + 1]; c += chunk) {
-                const int32_t cnt = std::min(chunk, bounds[kind + 1] - c);
-                blk.push_back(UpdBlock{c, cnt, kind, kind == 0 ? -1 : ifidx[c]});
-            }
-    }
-}
-
 template <typename T>
 int upload(ss_solver *s, T **dst, const T *src, size_t count)
 {
-    *dst = (T *)s->mem.get(sizeof(T) * count);
+    *dst = (T *)s->mem.get(sizeof(T) * std::max<size_t>(count, 1));
     if (!*dst) return fail(SS_ENOMEM, "device allocation failed");
     if (count) SS_HIP(hipMemcpyAsync(*dst, src, sizeof(T) * count, hipMemcpyHostToDevice, s->stream));
     return SS_OK;
@@ -173,7 +282,7 @@ int upload(ss_solver *s, T **dst, const T *src, size_t count)
 template <typename T>
 int alloc_dev(ss_solver *s, T **dst, size_t count)
 {
-    *dst = (T *)s->mem.get(sizeof(T) * count);
+    *dst = (T *)s->mem.get(sizeof(T) * std::max<size_t>(count, 1));
     return *dst ? SS_OK : fail(SS_ENOMEM, "device allocation failed");
 }
 
@@ -186,45 +295,47 @@ void destroy_graph(ss_solver *s)
     s->chunk_iters = 0;
 }
 
-// One CG iteration: two launches (plus two finishing launches when the
-// reductions are not fused).  `odd` selects the p ping-pong direction.
-void enqueue_iteration(ss_solver *s, hipStream_t stream, bool odd)
+// Pair j of a chunk: the update of iteration k (alpha, x, r) and the SpMV step
+// of iteration k+1 (beta, p, A p).  The scalar slot and the p ping-pong
+// alternate with j; chunks hold an even number of pairs, so every chunk
+// starts from slot 0 with the current p in p1.
+void enqueue_pair(ss_solver *s, hipStream_t stream, int j)
 {
-    double *pin = odd ? s->p1 : s->p0;
-    double *pout = odd ? s->p0 : s->p1;
-    const bool fused = s->opts.fused_reduce != 0;
-    launch_spmv_cg<double, double>(stream, s->csr64(), pin, s->r, pout, s->q, s->partial, s->st, fused);
-    launch_update<double>(stream, s->iface(), s->x, pout, s->r, s->q, s->partial, s->st, fused);
+    const int slot = j & 1;
+    double *pcur = slot ? s->p0 : s->p1;
+    double *pnext = slot ? s->p1 : s->p0;
+    launch_update<double>(stream, s->ifc, s->x, pcur, s->r, s->q, s->partials(), s->st, slot);
+    launch_spmv_step<double, double>(stream, s->mat, pcur, s->r, pnext, s->q, s->partials(), s->st, slot);
 }
 
-int ensure_chunk_graph(ss_solver *s, int32_t iters)
+int ensure_chunk_graph(ss_solver *s, int32_t pairs)
 {
-    if (s->chunk_exec && s->chunk_iters == iters) return SS_OK;
+    if (s->chunk_exec && s->chunk_iters == pairs) return SS_OK;
     destroy_graph(s);
     SS_HIP(hipStreamBeginCapture(s->cap, hipStreamCaptureModeThreadLocal));
-    for (int32_t k = 0; k < iters; ++k) enqueue_iteration(s, s->cap, (k & 1) != 0);
+    for (int32_t k = 0; k < pairs; ++k) enqueue_pair(s, s->cap, k);
     hipGraph_t g = nullptr;
     SS_HIP(hipStreamEndCapture(s->cap, &g));
     s->chunk_graph = g;
     SS_HIP(hipGraphInstantiate(&s->chunk_exec, g, nullptr, nullptr, 0));
-    s->chunk_iters = iters;
+    s->chunk_iters = pairs;
     return SS_OK;
 }
 
-int enqueue_chunk(ss_solver *s, int32_t iters)
+int enqueue_chunk(ss_solver *s, int32_t pairs)
 {
     if (s->opts.use_graph) {
         SS_HIP(hipGraphLaunch(s->chunk_exec, s->stream));
     } else {
-        for (int32_t k = 0; k < iters; ++k) enqueue_iteration(s, s->stream, (k & 1) != 0);
+        for (int32_t k = 0; k < pairs; ++k) enqueue_pair(s, s->stream, k);
         SS_HIP(hipGetLastError());
     }
     return SS_OK;
 }
 
 // Runs CG iterations until the device status leaves RUNNING.  Chunks of
-// `check_every` iterations (even, so every chunk starts from p0) are queued
-// one ahead of the status poll, so the device never idles on the host.
+// `check_every` iterations (even) are queued one ahead of the status poll, so
+// the device does not wait for the host.
 int iterate(ss_solver *s)
 {
     int32_t chunk = s->opts.check_every > 0 ? s->opts.check_every : kDefaultCheck;
@@ -289,7 +400,7 @@ void ss_opts_default(ss_opts *o)
     o->check_every = kDefaultCheck;
     o->use_graph = 1;
     o->tile_nnz = 0;
-    o->fused_reduce = 1;
+    o->matrix_format = SS_MAT_AUTO;
 }
 
 void ss_cg_destroy(ss_solver *s)
@@ -299,8 +410,6 @@ void ss_cg_destroy(ss_solver *s)
     destroy_graph(s);
     for (auto &e : s->ev)
         if (e) (void)hipEventDestroy(e);
-    if (s->t0) (void)hipEventDestroy(s->t0);
-    if (s->t1) (void)hipEventDestroy(s->t1);
     if (s->st_pinned) (void)hipHostFree(s->st_pinned);
     if (s->flag_pinned) (void)hipHostFree(s->flag_pinned);
     if (s->cap) (void)hipStreamDestroy(s->cap);
@@ -322,8 +431,19 @@ int ss_cg_setup(const ss_csr *A, const ss_part *p, const ss_opts *o, void *hip_s
     if (opts.precision != SS_FP64 && opts.precision != SS_FP32_IR) return fail(SS_EINVAL, "unknown precision");
     if (opts.tile_nnz != 0 && opts.tile_nnz != 1024 && opts.tile_nnz != 2048 && opts.tile_nnz != 4096)
         return fail(SS_EINVAL, "tile_nnz must be 0, 1024, 2048 or 4096");
+    if (opts.matrix_format < SS_MAT_AUTO || opts.matrix_format > SS_MAT_CSR)
+        return fail(SS_EINVAL, "unknown matrix_format");
     if ((opts.alloc == nullptr) != (opts.free == nullptr)) return fail(SS_EINVAL, "alloc and free go together");
+    if (opts.spmv_grid < 0 || opts.spmv_grid > kGridLimit) return fail(SS_EINVAL, "spmv_grid must be in [0, 65536]");
     if (opts.precision == SS_FP32_IR) return fail(SS_EUNSUPPORTED, "FP32 iterative refinement is not built yet");
+
+    Layout L;
+    try {
+        build_order(p, L);
+        build_matrix(p, L, opts.tile_nnz ? opts.tile_nnz : 2048, opts.matrix_format);
+    } catch (const std::bad_alloc &) {
+        return fail(SS_ENOMEM, "host allocation failed");
+    }
 
     ss_solver *s = new (std::nothrow) ss_solver;
     if (!s) return fail(SS_ENOMEM, "host allocation failed");
@@ -342,8 +462,6 @@ int ss_cg_setup(const ss_csr *A, const ss_part *p, const ss_opts *o, void *hip_s
     for (auto &e : s->ev)
         if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess)
             return bail(fail(SS_EDEVICE, "event creation failed"));
-    if (hipEventCreate(&s->t0) != hipSuccess || hipEventCreate(&s->t1) != hipSuccess)
-        return bail(fail(SS_EDEVICE, "event creation failed"));
     if (hipHostMalloc((void **)&s->st_pinned, sizeof(DevState), hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc((void **)&s->flag_pinned, 4 * sizeof(int32_t), hipHostMallocDefault) != hipSuccess)
         return bail(fail(SS_ENOMEM, "pinned host allocation failed"));
@@ -353,35 +471,62 @@ int ss_cg_setup(const ss_csr *A, const ss_part *p, const ss_opts *o, void *hip_s
     s->P = p->P;
     s->nnz = p->nnz;
     s->ngamma = (int32_t)p->gamma.size();
-    s->ncopies = (int32_t)p->copy_pos.size();
-    s->tile_nnz = opts.tile_nnz ? opts.tile_nnz : 2048;
+    s->stored = L.stored;
 
-    std::vector<int32_t> tiles = build_tiles(p->bd_rowptr, s->tile_nnz);
-    s->ntiles = (int32_t)tiles.size() - 1;
-    std::vector<UpdBlock> blk;
-    std::vector<int32_t> pos_grp;
-    build_update_blocks(p, blk, pos_grp);
-    s->nublk = (int32_t)blk.size();
-    std::vector<double> val_bd((size_t)s->nnz);
-    for (int64_t e = 0; e < s->nnz; ++e) val_bd[e] = A->val[p->bd_nzmap[e]];
+    std::vector<double> val_st((size_t)L.stored, 0.0);
+    for (int64_t k = 0; k < L.stored; ++k)
+        if (L.nzmap[k] >= 0) val_st[k] = A->val[L.nzmap[k]];
 
-    const size_t nl = (size_t)std::max(s->n_loc, 1);
-    if ((rc = upload(s, &s->rowptr, p->bd_rowptr.data(), p->bd_rowptr.size())) ||
-        (rc = upload(s, &s->colidx, p->bd_colidx.data(), p->bd_colidx.size())) ||
-        (rc = upload(s, &s->nzmap, p->bd_nzmap.data(), p->bd_nzmap.size())) ||
-        (rc = upload(s, &s->val, val_bd.data(), val_bd.size())) ||
-        (rc = upload(s, &s->tile_row, tiles.data(), tiles.size())) ||
-        (rc = upload(s, &s->l2g, p->l2g.data(), p->l2g.size())) ||
-        (rc = upload(s, &s->g2own, p->g2own.data(), p->g2own.size())) ||
-        (rc = upload(s, &s->copy_ptr, p->copy_ptr.data(), p->copy_ptr.size())) ||
-        (rc = upload(s, &s->copy_pos, p->copy_pos.data(), p->copy_pos.size())) ||
-        (rc = upload(s, &s->pos_grp, pos_grp.data(), pos_grp.size())) ||
-        (rc = upload(s, &s->ublk, blk.data(), blk.size())) || (rc = alloc_dev(s, &s->b, nl)) ||
+    Mat &M = s->mat;
+    M.fmt = L.fmt;
+    M.nrows = s->n_loc;
+    M.nchunks = L.nchunks;
+    M.ntiles = L.ntiles;
+    M.tile_nnz = L.tile_nnz;
+    const int work = L.fmt == FMT_SELL ? (L.nchunks + kBS / 64 - 1) / (kBS / 64) : L.ntiles;
+    M.grid = xcd_grid(std::max(1, std::min(work, opts.spmv_grid ? opts.spmv_grid : kSpmvGridMax)));
+    Iface &I = s->ifc;
+    I.n_loc = s->n_loc;
+    I.n_own = L.n_own;
+    I.n_if = L.n_if;
+    I.ngamma = s->ngamma;
+    I.grid = std::max(1, (s->n_loc + kUI * kBS - 1) / (kUI * kBS));
+
+    int32_t *d_col = nullptr, *d_cptr = nullptr, *d_cpos = nullptr, *d_rowptr = nullptr, *d_tile = nullptr, *d_pos_grp = nullptr,
+            *d_copy_ptr = nullptr, *d_copy_pos = nullptr;
+    uint8_t *d_clen = nullptr, *d_rlen = nullptr;
+    const size_t nl = (size_t)s->n_loc;
+    if ((rc = upload(s, &d_col, L.col.data(), L.col.size())) ||
+        (rc = upload(s, &s->nzmap, L.nzmap.data(), L.nzmap.size())) ||
+        (rc = upload(s, &s->val, val_st.data(), val_st.size())) ||
+        (rc = upload(s, &d_cptr, L.cptr.data(), L.cptr.size())) ||
+        (rc = upload(s, &d_cpos, L.cpos.data(), L.cpos.size())) ||
+        (rc = upload(s, &d_clen, L.clen.data(), L.clen.size())) ||
+        (rc = upload(s, &d_rlen, L.rlen.data(), L.rlen.size())) ||
+        (rc = upload(s, &d_rowptr, L.rowptr.data(), L.rowptr.size())) ||
+        (rc = upload(s, &d_tile, L.tile_row.data(), L.tile_row.size())) ||
+        (rc = upload(s, &s->l2g, L.l2g.data(), L.l2g.size())) ||
+        (rc = upload(s, &s->g2own, L.g2own.data(), L.g2own.size())) ||
+        (rc = upload(s, &d_copy_ptr, p->copy_ptr.data(), p->copy_ptr.size())) ||
+        (rc = upload(s, &d_copy_pos, L.copy_pos.data(), L.copy_pos.size())) ||
+        (rc = upload(s, &d_pos_grp, L.pos_grp.data(), L.pos_grp.size())) || (rc = alloc_dev(s, &s->b, nl)) ||
         (rc = alloc_dev(s, &s->x, nl)) || (rc = alloc_dev(s, &s->r, nl)) || (rc = alloc_dev(s, &s->p0, nl)) ||
-        (rc = alloc_dev(s, &s->p1, nl)) || (rc = alloc_dev(s, &s->q, nl)) || (rc = alloc_dev(s, &s->st, 1)))
+        (rc = alloc_dev(s, &s->p1, nl)) || (rc = alloc_dev(s, &s->q, nl)) || (rc = alloc_dev(s, &s->st, 1)) ||
+        (rc = alloc_dev(s, &s->part_a, (size_t)M.grid)) || (rc = alloc_dev(s, &s->part_b, (size_t)I.grid)) ||
+        (rc = alloc_dev(s, &s->part_r, 2 * (size_t)I.grid)))
         return bail(rc);
-    s->partial_len = 2 * (size_t)std::max(xcd_grid(s->ntiles), xcd_grid(s->nublk)) + 16;
-    if ((rc = alloc_dev(s, &s->partial, s->partial_len))) return bail(rc);
+    M.col = d_col;
+    M.val = s->val;
+    M.cptr = d_cptr;
+    M.cpos = d_cpos;
+    M.clen = d_clen;
+    M.rlen = d_rlen;
+    M.rowptr = d_rowptr;
+    M.tile_row = d_tile;
+    I.pos_grp = d_pos_grp;
+    I.copy_ptr = d_copy_ptr;
+    I.copy_pos = d_copy_pos;
+
     DevState init{};
     std::memcpy(s->st_pinned, &init, sizeof(DevState));
     if (hipMemcpyAsync(s->st, s->st_pinned, sizeof(DevState), hipMemcpyHostToDevice, s->stream) != hipSuccess ||
@@ -391,14 +536,15 @@ int ss_cg_setup(const ss_csr *A, const ss_part *p, const ss_opts *o, void *hip_s
     return SS_OK;
 }
 
-int ss_cg_info(const ss_solver *s, int32_t *n, int32_t *n_loc, int64_t *nnz, int32_t *ntiles, int32_t *tile_nnz)
+int ss_cg_info(const ss_solver *s, int32_t *n, int32_t *n_loc, int64_t *nnz, int32_t *matrix_format,
+               int64_t *stored)
 {
     if (!s) return fail(SS_EINVAL, "solver is NULL");
     if (n) *n = s->n;
     if (n_loc) *n_loc = s->n_loc;
     if (nnz) *nnz = s->nnz;
-    if (ntiles) *ntiles = s->ntiles;
-    if (tile_nnz) *tile_nnz = s->tile_nnz;
+    if (matrix_format) *matrix_format = s->mat.fmt == FMT_SELL ? SS_MAT_SELL : SS_MAT_CSR;
+    if (stored) *stored = s->stored;
     return SS_OK;
 }
 
@@ -410,8 +556,6 @@ int ss_cg_solve(ss_solver *s, const double *b_dev, double *x_dev, double tol, in
     if (!(tol >= 0.0) || maxit < 0) return fail(SS_EINVAL, "need tol >= 0 and maxit >= 0");
     int rc = ensure_hist(s, std::min<int64_t>((int64_t)maxit + 1, kHistMax));
     if (rc != SS_OK) return rc;
-    const bool fused = s->opts.fused_reduce != 0;
-
     DevState init{};
     init.tol = tol;
     init.kmax = maxit;
@@ -428,11 +572,13 @@ int ss_cg_solve(ss_solver *s, const double *b_dev, double *x_dev, double tol, in
     for (bool first = true;; first = false) {
         ++restarts;
         // r = b - A x, p = r (Algorithm 3, first line; also the convergence check)
-        launch_spmv<double, double>(s->stream, s->csr64(), s->x, s->q);
-        launch_residual<double>(s->stream, s->iface(), s->b, s->q, s->r, s->p0, s->partial, s->st, first, fused);
+        launch_spmv<double, double>(s->stream, s->mat, s->x, s->q);
+        launch_residual<double>(s->stream, s->ifc, s->b, s->q, s->r, s->p0, s->part_r, s->st, first);
         SS_HIP(hipGetLastError());
         if ((rc = read_status(s, &status)) != SS_OK) return rc;
         if (status != ST_RUNNING) break;
+        // p_1 = r_1, A p_1, then (update, step) pairs until the status changes
+        launch_spmv_first<double, double>(s->stream, s->mat, s->p0, s->r, s->p1, s->q, s->partials(), s->st);
         if ((rc = iterate(s)) != SS_OK) return rc;
         if ((rc = read_status(s, &status)) != SS_OK) return rc;
         if (status == ST_BREAKDOWN) break;
@@ -449,17 +595,17 @@ int ss_cg_solve(ss_solver *s, const double *b_dev, double *x_dev, double tol, in
     case ST_MAXIT: code = SS_NOT_CONVERGED; break;
     default: code = SS_EBREAKDOWN; break;
     }
-    const double relres = f.status == ST_ZERO_RHS ? 0.0 : std::sqrt(f.rr / f.bb);
+    const double relres = f.status == ST_ZERO_RHS ? 0.0 : std::sqrt(f.rr_last / f.bb);
     if (res) {
         res->status = code;
-        res->iterations = f.iter;
+        res->iterations = f.iter_last;
         res->outer_iterations = 0;
         res->restarts = restarts;
         res->relres = relres;
         res->true_relres = relres;
     }
     if (hist_host) {
-        const int32_t cnt = f.status == ST_ZERO_RHS ? 1 : std::min(f.iter + 1, s->hist_cap);
+        const int32_t cnt = f.status == ST_ZERO_RHS ? 1 : std::min(f.iter_last + 1, s->hist_cap);
         SS_HIP(hipMemcpy(hist_host, s->hist, sizeof(double) * cnt, hipMemcpyDeviceToHost));
     }
     if (code == SS_EBREAKDOWN) fail(SS_EBREAKDOWN, "CG breakdown: (p, A p) <= 0 or non-finite value");
@@ -470,8 +616,8 @@ int ss_cg_apply(ss_solver *s, const double *x_dev, double *y_dev)
 {
     if (!s || !x_dev || !y_dev) return fail(SS_EINVAL, "NULL argument");
     launch_gather<double>(s->stream, s->n_loc, s->l2g, x_dev, s->p0);
-    launch_spmv<double, double>(s->stream, s->csr64(), s->p0, s->q);
-    launch_iface_sum<double>(s->stream, s->iface(), s->q);
+    launch_spmv<double, double>(s->stream, s->mat, s->p0, s->q);
+    launch_iface_sum<double>(s->stream, s->ifc, s->q);
     launch_scatter<double>(s->stream, s->n, s->g2own, s->q, y_dev, nullptr);
     SS_HIP(hipGetLastError());
     SS_HIP(hipStreamSynchronize(s->stream));
@@ -481,7 +627,7 @@ int ss_cg_apply(ss_solver *s, const double *x_dev, double *y_dev)
 int ss_cg_set_values(ss_solver *s, const double *val_dev)
 {
     if (!s || !val_dev) return fail(SS_EINVAL, "NULL argument");
-    launch_set_values(s->stream, s->nnz, s->nzmap, val_dev, s->val, s->val32);
+    launch_set_values(s->stream, s->stored, s->nzmap, val_dev, s->val, nullptr);
     SS_HIP(hipGetLastError());
     SS_HIP(hipStreamSynchronize(s->stream));
     return SS_OK;
@@ -490,7 +636,7 @@ int ss_cg_set_values(ss_solver *s, const double *val_dev)
 int ss_cg_grad_vals(ss_solver *s, const double *lambda_dev, const double *x_dev, double *dvals_dev)
 {
     if (!s || !lambda_dev || !x_dev || !dvals_dev) return fail(SS_EINVAL, "NULL argument");
-    launch_grad_vals(s->stream, s->n_loc, s->rowptr, s->colidx, s->nzmap, s->l2g, lambda_dev, x_dev, dvals_dev);
+    launch_grad_vals(s->stream, s->mat, s->nzmap, s->l2g, lambda_dev, x_dev, dvals_dev);
     SS_HIP(hipGetLastError());
     SS_HIP(hipStreamSynchronize(s->stream));
     return SS_OK;
@@ -499,34 +645,55 @@ int ss_cg_grad_vals(ss_solver *s, const double *lambda_dev, const double *x_dev,
 int ss_cg_time_spmv(ss_solver *s, int32_t reps, double *ms_per_launch, double *bytes_per_launch)
 {
     if (!s || reps < 1 || !ms_per_launch) return fail(SS_EINVAL, "need a solver, reps >= 1 and an output");
-    // keep the run state; time the CG-step kernel with p = r = 1 and beta = 0:
-    // (1, A 1) > 0 for SPD A, so the status stays RUNNING and every launch
-    // does the full work
+    // Keep the run state; time the CG-step SpMV as it runs inside the loop:
+    // p = r = 1, update partials of 1 each, (r, r) slot 0 = 1, no stopping
+    // (stop = 0, unbounded iterations, no history), so every launch finishes
+    // the reduction, reads slot 0, writes slot 1 and does the full work.
     SS_HIP(hipMemcpyAsync(s->st_pinned, s->st, sizeof(DevState), hipMemcpyDeviceToHost, s->stream));
     SS_HIP(hipStreamSynchronize(s->stream));
     const DevState saved = *s->st_pinned;
-    DevState tmp = saved;
+    DevState tmp{};
+    tmp.rr[0] = 1.0;
+    tmp.iter[0] = 0;
+    tmp.bb = 1.0;
+    tmp.stop = 0.0;
+    tmp.kmax = INT32_MAX;
     tmp.status = ST_RUNNING;
-    tmp.beta = 0.0;
-    tmp.rr = 1.0;
     std::memcpy(s->st_pinned, &tmp, sizeof(DevState));
     SS_HIP(hipMemcpyAsync(s->st, s->st_pinned, sizeof(DevState), hipMemcpyHostToDevice, s->stream));
-    std::vector<double> ones((size_t)std::max(s->n_loc, 1), 1.0);
-    SS_HIP(hipMemcpyAsync(s->p0, ones.data(), sizeof(double) * (size_t)s->n_loc, hipMemcpyHostToDevice, s->stream));
+    const Partials P = s->partials();
+    std::vector<double> ones((size_t)std::max({s->n_loc, P.nb, 1}), 1.0);
+    SS_HIP(hipMemcpyAsync(s->p1, ones.data(), sizeof(double) * (size_t)s->n_loc, hipMemcpyHostToDevice, s->stream));
     SS_HIP(hipMemcpyAsync(s->r, ones.data(), sizeof(double) * (size_t)s->n_loc, hipMemcpyHostToDevice, s->stream));
-    const bool fused = s->opts.fused_reduce != 0;
-    launch_spmv_cg<double, double>(s->stream, s->csr64(), s->p0, s->r, s->p1, s->q, s->partial, s->st, fused);
-    SS_HIP(hipEventRecord(s->t0, s->stream));
-    for (int32_t k = 0; k < reps; ++k)
-        launch_spmv_cg<double, double>(s->stream, s->csr64(), s->p0, s->r, s->p1, s->q, s->partial, s->st, fused);
-    SS_HIP(hipEventRecord(s->t1, s->stream));
-    SS_HIP(hipGetLastError());
-    SS_HIP(hipEventSynchronize(s->t1));
-    float ms = 0.0f;
-    SS_HIP(hipEventElapsedTime(&ms, s->t0, s->t1));
-    *ms_per_launch = (double)ms / reps;
-    // values + column indices, row pointers, one read of r and p_{k-1},
-    // writes of p_k and q
+    SS_HIP(hipMemcpyAsync(P.b, ones.data(), sizeof(double) * (size_t)P.nb, hipMemcpyHostToDevice, s->stream));
+    launch_spmv_step<double, double>(s->stream, s->mat, s->p1, s->r, s->p0, s->q, P, s->st, 0);
+    // one event pair around every launch: the sum of the pairs is the kernel
+    // time without the gaps between launches
+    std::vector<hipEvent_t> ev(2 * (size_t)reps, nullptr);
+    for (auto &e : ev)
+        if (hipEventCreate(&e) != hipSuccess) {
+            for (auto &f : ev)
+                if (f) (void)hipEventDestroy(f);
+            return fail(SS_EDEVICE, "event creation failed");
+        }
+    for (int32_t k = 0; k < reps; ++k) {
+        (void)hipEventRecord(ev[2 * k], s->stream);
+        launch_spmv_step<double, double>(s->stream, s->mat, s->p1, s->r, s->p0, s->q, P, s->st, 0);
+        (void)hipEventRecord(ev[2 * k + 1], s->stream);
+    }
+    hipError_t err = hipGetLastError();
+    if (err == hipSuccess) err = hipEventSynchronize(ev.back());
+    double total = 0.0;
+    for (int32_t k = 0; k < reps && err == hipSuccess; ++k) {
+        float ms = 0.0f;
+        err = hipEventElapsedTime(&ms, ev[2 * k], ev[2 * k + 1]);
+        total += ms;
+    }
+    for (auto &e : ev) (void)hipEventDestroy(e);
+    if (err != hipSuccess) return fail(SS_EDEVICE, std::string("SpMV timing: ") + hipGetErrorString(err));
+    *ms_per_launch = total / reps;
+    // values + column indices, row structure (4 B per row), one read of r and
+    // p_{k-1}, writes of p_k and q
     if (bytes_per_launch)
         *bytes_per_launch = 12.0 * (double)s->nnz + 4.0 * (double)(s->n_loc + 1) + 4.0 * 8.0 * (double)s->n_loc;
     std::memcpy(s->st_pinned, &saved, sizeof(DevState));
