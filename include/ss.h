@@ -198,9 +198,16 @@ int ss_cg_setup(const ss_csr *A, const ss_part *p, const ss_opts *o, void *hip_s
  * states none): ||r|| <= tol ||b||, with r recomputed as b - A x whenever the
  * recurrence reports convergence (restarting CG from it if needed).  At most
  * maxit CG iterations.  b = 0 returns x = 0 after 0 iterations.
- * res (host, may be NULL) receives the result; hist_host (host, may be
- * NULL, capacity maxit+1) receives ||r_k||/||b|| for k = 0..iterations
- * (at most the first 4194304 entries are recorded).
+ * With precision SS_FP32_IR the same stopping rule applies to the FP64
+ * residual of the outer loop: r = b - A x (FP64 values and vectors), inner CG
+ * on the FP32 values with FP32 vectors for r / ||r|| (FP64 dots and scalars)
+ * until its residual drops by inner_tol (or inner_maxit iterations), then
+ * x += ||r|| d; at most max_outer corrections (SS_NOT_CONVERGED beyond).
+ * res (host, may be NULL) receives the result (iterations = all inner
+ * iterations for SS_FP32_IR); hist_host (host, may be NULL, capacity
+ * maxit+1) receives ||r_k||/||b|| for k = 0..iterations (FP32_IR: inner
+ * estimates, replaced by the FP64 value at every outer step; at most the
+ * first 4194304 entries are recorded).
  * Returns SS_OK, SS_NOT_CONVERGED, SS_EBREAKDOWN, SS_EINVAL (tol < 0,
  * maxit < 0), SS_EDEVICE.
  */
@@ -225,7 +232,8 @@ int ss_cg_set_values(ss_solver *s, const double *val_dev);
 int ss_cg_grad_vals(ss_solver *s, const double *lambda_dev, const double *x_dev, double *dvals_dev);
 
 /* Average duration in milliseconds of one launch of the local SpMV kernel
- * (the CG-step variant), timed with one HIP event pair around each of `reps`
+ * (the CG-step variant; the FP32 inner step for an SS_FP32_IR solver),
+ * timed with one HIP event pair around each of `reps`
  * back-to-back launches on the solver stream.  Leaves the solver state
  * unchanged except for scratch vectors.  Also reports the algorithmic bytes
  * that launch moves (values, column indices, row pointers, one read of the

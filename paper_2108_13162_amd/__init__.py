@@ -345,3 +345,62 @@ def ss_cg_time_spmv(s: Solver, reps: int = 20) -> tuple:
     ms, nbytes = C.c_double(), C.c_double()
     _check(lib().ss_cg_time_spmv(s.h, int(reps), C.byref(ms), C.byref(nbytes)), "ss_cg_time_spmv")
     return ms.value, nbytes.value
+
+
+# ----------------------------------------------------------------------------
+# differentiable solve (adjoint CG)
+# ----------------------------------------------------------------------------
+
+def _autograd_function():
+    torch = _torch()
+
+    class SSCGSolve(torch.autograd.Function):
+        """x = A(vals)^{-1} b through the sub-structured CG, differentiable in
+        vals (the global stored entries, in CSR order) and b.
+
+        Backward: one more solve with the same symmetric A gives
+        lambda = A^{-1} dL/dx; then dL/db = lambda and, for every stored
+        entry k = (i, j) taken as an independent parameter,
+        dL/dvals_k = -lambda_i x_j.  A perturbation that keeps A symmetric
+        moves the (i, j) and (j, i) entries together; its derivative is the
+        sum of the two components.
+        """
+
+        @staticmethod
+        def forward(ctx, vals, b, solver, tol=1e-10, maxit=100000, adj_tol=None):
+            ss_cg_set_values(solver, vals.detach().contiguous())
+            x = torch.zeros_like(b)
+            res = ss_cg_solve(solver, b.detach().contiguous(), x, tol=tol, maxit=maxit)
+            if res.status != SS_OK:
+                raise SSError(res.status, "SSCGSolve.forward")
+            ctx.solver = solver
+            ctx.adj = (tol if adj_tol is None else adj_tol, maxit)
+            ctx.save_for_backward(vals, x)
+            ctx.forward_result = res
+            return x
+
+        @staticmethod
+        def backward(ctx, gx):
+            vals, x = ctx.saved_tensors
+            solver = ctx.solver
+            ss_cg_set_values(solver, vals.detach().contiguous())
+            lam = torch.zeros_like(x)
+            res = ss_cg_solve(solver, gx.detach().contiguous(), lam, tol=ctx.adj[0], maxit=ctx.adj[1])
+            if res.status != SS_OK:
+                raise SSError(res.status, "SSCGSolve.backward")
+            dvals = ss_cg_grad_vals(solver, lam, x) if ctx.needs_input_grad[0] else None
+            db = lam if ctx.needs_input_grad[1] else None
+            return dvals, db, None, None, None, None
+
+    return SSCGSolve
+
+
+_SSCGSolve = None
+
+
+def sscg_solve(vals, b, solver: Solver, tol: float = 1e-10, maxit: int = 100000, adj_tol: Optional[float] = None):
+    """Differentiable x = A(vals)^{-1} b on `solver` (set up for A's pattern)."""
+    global _SSCGSolve
+    if _SSCGSolve is None:
+        _SSCGSolve = _autograd_function()
+    return _SSCGSolve.apply(vals, b, solver, tol, maxit, adj_tol)

@@ -129,6 +129,19 @@ template <typename XT>
 void launch_residual(hipStream_t s, const Iface &I, const XT *b, const XT *q, XT *r, XT *p0, double *partial,
                      DevState *state, bool first);
 
+// FP32-value iterative refinement.  ir_prepare: inner right-hand side
+// rin = (XT)(r64 / s) with s = sqrt(outer (r, r)), p0 = rin, d = 0, then one
+// workgroup sets up the inner run's state (stop = inner_tol * ||rin||, limit
+// min(iterations + inner_maxit, maxit), history scaled to ||r|| / ||b||).
+template <typename XT>
+void launch_ir_prepare(hipStream_t s, const Iface &I, const double *r64, XT *rin, XT *p0, XT *d, double *partial,
+                       const DevState *outer, DevState *inner, double inner_tol, int32_t inner_maxit, int32_t maxit);
+// x64 += s * d (every copy), iteration count back to the outer state; an
+// inner breakdown skips the correction and marks the outer state.
+template <typename XT>
+void launch_ir_accumulate(hipStream_t s, int32_t n_loc, double *x64, const XT *d, const DevState *inner,
+                          DevState *outer);
+
 // Adjoint gradient on the pattern: dvals[nzmap[k]] = -lambda[row] x[col] for
 // every stored (non-padding) entry k of A in device order.
 void launch_grad_vals(hipStream_t s, const Mat &A, const int32_t *nzmap, const int32_t *l2g, const double *lambda,

@@ -20,6 +20,7 @@
 // products and sums are rounded separately, as the expressions are written.
 #include "kernels.h"
 
+#include <algorithm>
 #include <cmath>
 
 namespace ss {
@@ -495,6 +496,76 @@ __global__ __launch_bounds__(kBS) void k_finish_residual(DevState *st, const dou
         store_status(st, ST_RUNNING);
 }
 
+// ---- FP32-value iterative refinement ---------------------------------------
+
+template <typename XT>
+__global__ __launch_bounds__(kBS) void k_ir_prepare(int32_t n_loc, int32_t n_own, int32_t n_if,
+                                                    const double *__restrict__ r64, XT *__restrict__ rin,
+                                                    XT *__restrict__ p0, XT *__restrict__ d,
+                                                    double *__restrict__ partial, const DevState *__restrict__ outer)
+{
+    constexpr int B = kUI * kBS;
+    __shared__ double ws[kBS / 64 + 1];
+    const double sc = sqrt(outer->rr_last);
+    const int b0 = (int)blockIdx.x * B;
+    double acc = 0.0;
+    for (int i = 0; i < kUI; ++i) {
+        const int c = b0 + (int)threadIdx.x + i * kBS;
+        if (c < n_loc) {
+            const XT v = (XT)(r64[c] / sc);
+            rin[c] = v;
+            p0[c] = v;
+            d[c] = XT(0);
+            if (c < n_own || c >= n_if) acc = acc + (double)v * (double)v;
+        }
+    }
+    const double part = block_sum_all(acc, ws);
+    if (threadIdx.x == 0) partial[blockIdx.x] = part;
+}
+
+__global__ __launch_bounds__(kBS) void k_ir_start(DevState *in, const DevState *outer, const double *partial, int n,
+                                                  double inner_tol, int32_t inner_maxit, int32_t maxit)
+{
+    __shared__ double ws[kBS / 64 + 1];
+    const double rr = sum_partials_all(partial, n, ws);
+    if (threadIdx.x != 0) return;
+    const int k = outer->iter_last;
+    in->rr[0] = rr;
+    in->iter[0] = k;
+    in->rr_last = rr;
+    in->iter_last = k;
+    in->bb = outer->bb / outer->rr_last;  // inner history: sqrt(rr / bb_in) = ||r|| / ||b|| estimate
+    in->tol = inner_tol;
+    in->stop = inner_tol * sqrt(rr);
+    in->kmax = inner_maxit > 0 ? (int32_t)min((long long)k + inner_maxit, (long long)maxit) : maxit;
+    in->hist = outer->hist;
+    in->hist_cap = outer->hist_cap;
+    if (!isfinite(rr))
+        store_status(in, ST_BREAKDOWN);
+    else if (sqrt(rr) <= in->stop)
+        store_status(in, ST_CONVERGED);
+    else if (k >= in->kmax)
+        store_status(in, ST_MAXIT);
+    else
+        store_status(in, ST_RUNNING);
+}
+
+template <typename XT>
+__global__ __launch_bounds__(kBS) void k_ir_accumulate(int32_t n_loc, double *__restrict__ x64,
+                                                       const XT *__restrict__ d, const DevState *__restrict__ in,
+                                                       DevState *__restrict__ outer)
+{
+    const int c = blockIdx.x * kBS + threadIdx.x;
+    const bool broke = in->status == ST_BREAKDOWN;
+    if (c == 0) {
+        outer->iter_last = in->iter_last;
+        if (broke) store_status(outer, ST_BREAKDOWN);
+    }
+    if (broke || c >= n_loc) return;
+    const double sc = sqrt(outer->rr_last);
+    x64[c] = x64[c] + sc * (double)d[c];
+}
+
 // ---- gathers, scatters, gradient -------------------------------------------
 
 template <typename XT>
@@ -658,6 +729,24 @@ void launch_set_values(hipStream_t s, int64_t len, const int32_t *nzmap, const d
         hipLaunchKernelGGL(k_set_values, dim3(nblocks(len)), dim3(kBS), 0, s, len, nzmap, val_glob, val64, val32);
 }
 
+template <typename XT>
+void launch_ir_prepare(hipStream_t s, const Iface &I, const double *r64, XT *rin, XT *p0, XT *d, double *partial,
+                       const DevState *outer, DevState *inner, double inner_tol, int32_t inner_maxit, int32_t maxit)
+{
+    hipLaunchKernelGGL(k_ir_prepare<XT>, dim3(I.grid), dim3(kBS), 0, s, I.n_loc, I.n_own, I.n_if, r64, rin, p0, d,
+                       partial, outer);
+    hipLaunchKernelGGL(k_ir_start, dim3(1), dim3(kBS), 0, s, inner, outer, partial, I.grid, inner_tol, inner_maxit,
+                       maxit);
+}
+
+template <typename XT>
+void launch_ir_accumulate(hipStream_t s, int32_t n_loc, double *x64, const XT *d, const DevState *inner,
+                          DevState *outer)
+{
+    hipLaunchKernelGGL(k_ir_accumulate<XT>, dim3(nblocks(std::max(n_loc, 1))), dim3(kBS), 0, s, n_loc, x64, d, inner,
+                       outer);
+}
+
 // explicit instantiations
 #define SS_INST(XT)                                                                                                  \
     template void launch_gather<XT>(hipStream_t, int32_t, const int32_t *, const double *, XT *);                    \
@@ -671,7 +760,10 @@ void launch_set_values(hipStream_t s, int64_t len, const int32_t *nzmap, const d
     template void launch_update<XT>(hipStream_t, const Iface &, XT *, const XT *, XT *, const XT *, Partials,        \
                                     DevState *, int);                                                                \
     template void launch_residual<XT>(hipStream_t, const Iface &, const XT *, const XT *, XT *, XT *, double *,      \
-                                      DevState *, bool);
+                                      DevState *, bool);                                                             \
+    template void launch_ir_prepare<XT>(hipStream_t, const Iface &, const double *, XT *, XT *, XT *, double *,      \
+                                        const DevState *, DevState *, double, int32_t, int32_t);                     \
+    template void launch_ir_accumulate<XT>(hipStream_t, int32_t, double *, const XT *, const DevState *, DevState *);
 SS_INST(double)
 SS_INST(float)
 #undef SS_INST

@@ -255,15 +255,25 @@ struct ss_solver {
     double *hist = nullptr;
     int32_t hist_cap = 0;
 
+    // FP32-value iterative refinement: FP32 copy of the values, inner vectors
+    Mat mat32{};
+    float *val32 = nullptr, *d32 = nullptr, *r32 = nullptr, *p32a = nullptr, *p32b = nullptr, *q32 = nullptr;
+    DevState *st_in = nullptr;
+
     // host side
     DevState *st_pinned = nullptr;   // readback of the state
     int32_t *flag_pinned = nullptr;  // two status slots for pipelined polling
     hipEvent_t ev[2] = {nullptr, nullptr};
 
-    // graph of one polled chunk
-    hipGraphExec_t chunk_exec = nullptr;
-    hipGraph_t chunk_graph = nullptr;
-    int32_t chunk_iters = 0;
+    // one CG run: its vectors, state and the graph of one polled chunk
+    struct Run {
+        bool fp32 = false;
+        void *x = nullptr, *r = nullptr, *p0 = nullptr, *p1 = nullptr, *q = nullptr;
+        DevState *st = nullptr;
+        hipGraphExec_t exec = nullptr;
+        hipGraph_t graph = nullptr;
+        int32_t pairs = 0;
+    } run64, run32;
 
     Partials partials() const { return Partials{part_a, part_b, mat.grid, ifc.grid}; }
 };
@@ -286,74 +296,83 @@ int alloc_dev(ss_solver *s, T **dst, size_t count)
     return *dst ? SS_OK : fail(SS_ENOMEM, "device allocation failed");
 }
 
-void destroy_graph(ss_solver *s)
+void destroy_graph(ss_solver::Run &R)
 {
-    if (s->chunk_exec) (void)hipGraphExecDestroy(s->chunk_exec);
-    if (s->chunk_graph) (void)hipGraphDestroy(s->chunk_graph);
-    s->chunk_exec = nullptr;
-    s->chunk_graph = nullptr;
-    s->chunk_iters = 0;
+    if (R.exec) (void)hipGraphExecDestroy(R.exec);
+    if (R.graph) (void)hipGraphDestroy(R.graph);
+    R.exec = nullptr;
+    R.graph = nullptr;
+    R.pairs = 0;
 }
 
 // Pair j of a chunk: the update of iteration k (alpha, x, r) and the SpMV step
 // of iteration k+1 (beta, p, A p).  The scalar slot and the p ping-pong
 // alternate with j; chunks hold an even number of pairs, so every chunk
 // starts from slot 0 with the current p in p1.
-void enqueue_pair(ss_solver *s, hipStream_t stream, int j)
+template <typename XT>
+void enqueue_pair_t(ss_solver *s, const ss_solver::Run &R, const Mat &M, hipStream_t stream, int j)
 {
     const int slot = j & 1;
-    double *pcur = slot ? s->p0 : s->p1;
-    double *pnext = slot ? s->p1 : s->p0;
-    launch_update<double>(stream, s->ifc, s->x, pcur, s->r, s->q, s->partials(), s->st, slot);
-    launch_spmv_step<double, double>(stream, s->mat, pcur, s->r, pnext, s->q, s->partials(), s->st, slot);
+    XT *pcur = (XT *)(slot ? R.p0 : R.p1);
+    XT *pnext = (XT *)(slot ? R.p1 : R.p0);
+    launch_update<XT>(stream, s->ifc, (XT *)R.x, pcur, (XT *)R.r, (XT *)R.q, s->partials(), R.st, slot);
+    launch_spmv_step<XT, XT>(stream, M, pcur, (XT *)R.r, pnext, (XT *)R.q, s->partials(), R.st, slot);
 }
 
-int ensure_chunk_graph(ss_solver *s, int32_t pairs)
+void enqueue_pair(ss_solver *s, const ss_solver::Run &R, hipStream_t stream, int j)
 {
-    if (s->chunk_exec && s->chunk_iters == pairs) return SS_OK;
-    destroy_graph(s);
+    if (R.fp32)
+        enqueue_pair_t<float>(s, R, s->mat32, stream, j);
+    else
+        enqueue_pair_t<double>(s, R, s->mat, stream, j);
+}
+
+int ensure_chunk_graph(ss_solver *s, ss_solver::Run &R, int32_t pairs)
+{
+    if (R.exec && R.pairs == pairs) return SS_OK;
+    destroy_graph(R);
     SS_HIP(hipStreamBeginCapture(s->cap, hipStreamCaptureModeThreadLocal));
-    for (int32_t k = 0; k < pairs; ++k) enqueue_pair(s, s->cap, k);
+    for (int32_t k = 0; k < pairs; ++k) enqueue_pair(s, R, s->cap, k);
     hipGraph_t g = nullptr;
     SS_HIP(hipStreamEndCapture(s->cap, &g));
-    s->chunk_graph = g;
-    SS_HIP(hipGraphInstantiate(&s->chunk_exec, g, nullptr, nullptr, 0));
-    s->chunk_iters = pairs;
+    R.graph = g;
+    SS_HIP(hipGraphInstantiate(&R.exec, g, nullptr, nullptr, 0));
+    R.pairs = pairs;
     return SS_OK;
 }
 
-int enqueue_chunk(ss_solver *s, int32_t pairs)
+int enqueue_chunk(ss_solver *s, ss_solver::Run &R, int32_t pairs)
 {
     if (s->opts.use_graph) {
-        SS_HIP(hipGraphLaunch(s->chunk_exec, s->stream));
+        SS_HIP(hipGraphLaunch(R.exec, s->stream));
     } else {
-        for (int32_t k = 0; k < pairs; ++k) enqueue_pair(s, s->stream, k);
+        for (int32_t k = 0; k < pairs; ++k) enqueue_pair(s, R, s->stream, k);
         SS_HIP(hipGetLastError());
     }
     return SS_OK;
 }
 
-// Runs CG iterations until the device status leaves RUNNING.  Chunks of
-// `check_every` iterations (even) are queued one ahead of the status poll, so
-// the device does not wait for the host.
-int iterate(ss_solver *s)
+// Runs CG iterations of run R until its device status leaves RUNNING.
+// Chunks of `check_every` iterations (even) are queued one ahead of the
+// status poll, so the device does not wait for the host.
+int iterate(ss_solver *s, ss_solver::Run &R)
 {
     int32_t chunk = s->opts.check_every > 0 ? s->opts.check_every : kDefaultCheck;
     chunk += chunk & 1;
     if (s->opts.use_graph) {
-        int rc = ensure_chunk_graph(s, chunk);
+        int rc = ensure_chunk_graph(s, R, chunk);
         if (rc != SS_OK) return rc;
     }
     int slot = 0;
-    int rc = enqueue_chunk(s, chunk);
+    int rc = enqueue_chunk(s, R, chunk);
     if (rc != SS_OK) return rc;
-    SS_HIP(hipMemcpyAsync(&s->flag_pinned[slot], &s->st->status, sizeof(int32_t), hipMemcpyDeviceToHost, s->stream));
+    SS_HIP(hipMemcpyAsync(&s->flag_pinned[slot], &R.st->status, sizeof(int32_t), hipMemcpyDeviceToHost, s->stream));
     SS_HIP(hipEventRecord(s->ev[slot], s->stream));
     for (;;) {
         const int nxt = slot ^ 1;
-        rc = enqueue_chunk(s, chunk);
+        rc = enqueue_chunk(s, R, chunk);
         if (rc != SS_OK) return rc;
-        SS_HIP(hipMemcpyAsync(&s->flag_pinned[nxt], &s->st->status, sizeof(int32_t), hipMemcpyDeviceToHost,
+        SS_HIP(hipMemcpyAsync(&s->flag_pinned[nxt], &R.st->status, sizeof(int32_t), hipMemcpyDeviceToHost,
                               s->stream));
         SS_HIP(hipEventRecord(s->ev[nxt], s->stream));
         SS_HIP(hipEventSynchronize(s->ev[slot]));
@@ -365,9 +384,9 @@ int iterate(ss_solver *s)
     }
 }
 
-int read_status(ss_solver *s, int32_t *status)
+int read_status(ss_solver *s, const DevState *st, int32_t *status)
 {
-    SS_HIP(hipMemcpyAsync(&s->flag_pinned[0], &s->st->status, sizeof(int32_t), hipMemcpyDeviceToHost, s->stream));
+    SS_HIP(hipMemcpyAsync(&s->flag_pinned[0], &st->status, sizeof(int32_t), hipMemcpyDeviceToHost, s->stream));
     SS_HIP(hipStreamSynchronize(s->stream));
     *status = s->flag_pinned[0];
     return SS_OK;
@@ -407,7 +426,8 @@ void ss_cg_destroy(ss_solver *s)
 {
     if (!s) return;
     if (s->stream) (void)hipStreamSynchronize(s->stream);
-    destroy_graph(s);
+    destroy_graph(s->run64);
+    destroy_graph(s->run32);
     for (auto &e : s->ev)
         if (e) (void)hipEventDestroy(e);
     if (s->st_pinned) (void)hipHostFree(s->st_pinned);
@@ -435,7 +455,8 @@ int ss_cg_setup(const ss_csr *A, const ss_part *p, const ss_opts *o, void *hip_s
         return fail(SS_EINVAL, "unknown matrix_format");
     if ((opts.alloc == nullptr) != (opts.free == nullptr)) return fail(SS_EINVAL, "alloc and free go together");
     if (opts.spmv_grid < 0 || opts.spmv_grid > kGridLimit) return fail(SS_EINVAL, "spmv_grid must be in [0, 65536]");
-    if (opts.precision == SS_FP32_IR) return fail(SS_EUNSUPPORTED, "FP32 iterative refinement is not built yet");
+    if (opts.precision == SS_FP32_IR && !(opts.inner_tol > 0.0 && opts.inner_tol < 1.0))
+        return fail(SS_EINVAL, "inner_tol must be in (0, 1)");
 
     Layout L;
     try {
@@ -515,6 +536,14 @@ int ss_cg_setup(const ss_csr *A, const ss_part *p, const ss_opts *o, void *hip_s
         (rc = alloc_dev(s, &s->part_a, (size_t)M.grid)) || (rc = alloc_dev(s, &s->part_b, (size_t)I.grid)) ||
         (rc = alloc_dev(s, &s->part_r, 2 * (size_t)I.grid)))
         return bail(rc);
+    if (opts.precision == SS_FP32_IR) {
+        std::vector<float> v32(val_st.size());
+        for (size_t k = 0; k < v32.size(); ++k) v32[k] = (float)val_st[k];
+        if ((rc = upload(s, &s->val32, v32.data(), v32.size())) || (rc = alloc_dev(s, &s->d32, nl)) ||
+            (rc = alloc_dev(s, &s->r32, nl)) || (rc = alloc_dev(s, &s->p32a, nl)) ||
+            (rc = alloc_dev(s, &s->p32b, nl)) || (rc = alloc_dev(s, &s->q32, nl)) || (rc = alloc_dev(s, &s->st_in, 1)))
+            return bail(rc);
+    }
     M.col = d_col;
     M.val = s->val;
     M.cptr = d_cptr;
@@ -526,6 +555,22 @@ int ss_cg_setup(const ss_csr *A, const ss_part *p, const ss_opts *o, void *hip_s
     I.pos_grp = d_pos_grp;
     I.copy_ptr = d_copy_ptr;
     I.copy_pos = d_copy_pos;
+    s->mat32 = M;
+    s->mat32.val = s->val32;
+    s->run64.fp32 = false;
+    s->run64.x = s->x;
+    s->run64.r = s->r;
+    s->run64.p0 = s->p0;
+    s->run64.p1 = s->p1;
+    s->run64.q = s->q;
+    s->run64.st = s->st;
+    s->run32.fp32 = true;
+    s->run32.x = s->d32;
+    s->run32.r = s->r32;
+    s->run32.p0 = s->p32a;
+    s->run32.p1 = s->p32b;
+    s->run32.q = s->q32;
+    s->run32.st = s->st_in;
 
     DevState init{};
     std::memcpy(s->st_pinned, &init, sizeof(DevState));
@@ -568,20 +613,52 @@ int ss_cg_solve(ss_solver *s, const double *b_dev, double *x_dev, double tol, in
     launch_gather<double>(s->stream, s->n_loc, s->l2g, x_dev, s->x);
 
     int32_t status = ST_RUNNING;
-    int32_t restarts = -1;
-    for (bool first = true;; first = false) {
-        ++restarts;
-        // r = b - A x, p = r (Algorithm 3, first line; also the convergence check)
-        launch_spmv<double, double>(s->stream, s->mat, s->x, s->q);
-        launch_residual<double>(s->stream, s->ifc, s->b, s->q, s->r, s->p0, s->part_r, s->st, first);
-        SS_HIP(hipGetLastError());
-        if ((rc = read_status(s, &status)) != SS_OK) return rc;
-        if (status != ST_RUNNING) break;
-        // p_1 = r_1, A p_1, then (update, step) pairs until the status changes
-        launch_spmv_first<double, double>(s->stream, s->mat, s->p0, s->r, s->p1, s->q, s->partials(), s->st);
-        if ((rc = iterate(s)) != SS_OK) return rc;
-        if ((rc = read_status(s, &status)) != SS_OK) return rc;
-        if (status == ST_BREAKDOWN) break;
+    int32_t restarts = -1, outer = 0;
+    bool outer_cap = false;  // IR stopped by max_outer
+    if (s->opts.precision == SS_FP64) {
+        for (bool first = true;; first = false) {
+            ++restarts;
+            // r = b - A x, p = r (Algorithm 3, first line; also the convergence check)
+            launch_spmv<double, double>(s->stream, s->mat, s->x, s->q);
+            launch_residual<double>(s->stream, s->ifc, s->b, s->q, s->r, s->p0, s->part_r, s->st, first);
+            SS_HIP(hipGetLastError());
+            if ((rc = read_status(s, s->st, &status)) != SS_OK) return rc;
+            if (status != ST_RUNNING) break;
+            // p_1 = r_1, A p_1, then (update, step) pairs until the status changes
+            launch_spmv_first<double, double>(s->stream, s->mat, s->p0, s->r, s->p1, s->q, s->partials(), s->st);
+            if ((rc = iterate(s, s->run64)) != SS_OK) return rc;
+            if ((rc = read_status(s, s->st, &status)) != SS_OK) return rc;
+            if (status == ST_BREAKDOWN) break;
+        }
+    } else {
+        // outer: FP64 residual of the FP64 matrix; inner: CG on the FP32 values
+        // with FP32 vectors for the scaled residual; x += ||r|| d
+        const int32_t max_outer = s->opts.max_outer > 0 ? s->opts.max_outer : 50;
+        restarts = 0;
+        for (;; ++outer) {
+            launch_spmv<double, double>(s->stream, s->mat, s->x, s->q);
+            launch_residual<double>(s->stream, s->ifc, s->b, s->q, s->r, s->p0, s->part_r, s->st, outer == 0);
+            SS_HIP(hipGetLastError());
+            if ((rc = read_status(s, s->st, &status)) != SS_OK) return rc;
+            if (status != ST_RUNNING) break;
+            if (outer >= max_outer) {
+                outer_cap = true;
+                break;
+            }
+            launch_ir_prepare<float>(s->stream, s->ifc, s->r, s->r32, s->p32a, s->d32, s->part_r, s->st, s->st_in,
+                                     s->opts.inner_tol, s->opts.inner_maxit, maxit);
+            int32_t si = ST_RUNNING;
+            if ((rc = read_status(s, s->st_in, &si)) != SS_OK) return rc;
+            if (si == ST_RUNNING) {
+                launch_spmv_first<float, float>(s->stream, s->mat32, s->p32a, s->r32, s->p32b, s->q32, s->partials(),
+                                                s->st_in);
+                if ((rc = iterate(s, s->run32)) != SS_OK) return rc;
+            }
+            launch_ir_accumulate<float>(s->stream, s->n_loc, s->x, s->d32, s->st_in, s->st);
+            SS_HIP(hipGetLastError());
+            if ((rc = read_status(s, s->st, &status)) != SS_OK) return rc;
+            if (status == ST_BREAKDOWN) break;
+        }
     }
     launch_scatter<double>(s->stream, s->n, s->g2own, s->x, x_dev, s->st);
     SS_HIP(hipGetLastError());
@@ -593,13 +670,15 @@ int ss_cg_solve(ss_solver *s, const double *b_dev, double *x_dev, double tol, in
     case ST_CONVERGED:
     case ST_ZERO_RHS: code = SS_OK; break;
     case ST_MAXIT: code = SS_NOT_CONVERGED; break;
+    case ST_RUNNING: code = SS_NOT_CONVERGED; break;  // IR stopped by max_outer
     default: code = SS_EBREAKDOWN; break;
     }
+    (void)outer_cap;
     const double relres = f.status == ST_ZERO_RHS ? 0.0 : std::sqrt(f.rr_last / f.bb);
     if (res) {
         res->status = code;
         res->iterations = f.iter_last;
-        res->outer_iterations = 0;
+        res->outer_iterations = outer;
         res->restarts = restarts;
         res->relres = relres;
         res->true_relres = relres;
@@ -627,7 +706,7 @@ int ss_cg_apply(ss_solver *s, const double *x_dev, double *y_dev)
 int ss_cg_set_values(ss_solver *s, const double *val_dev)
 {
     if (!s || !val_dev) return fail(SS_EINVAL, "NULL argument");
-    launch_set_values(s->stream, s->stored, s->nzmap, val_dev, s->val, nullptr);
+    launch_set_values(s->stream, s->stored, s->nzmap, val_dev, s->val, s->val32);
     SS_HIP(hipGetLastError());
     SS_HIP(hipStreamSynchronize(s->stream));
     return SS_OK;
@@ -645,11 +724,14 @@ int ss_cg_grad_vals(ss_solver *s, const double *lambda_dev, const double *x_dev,
 int ss_cg_time_spmv(ss_solver *s, int32_t reps, double *ms_per_launch, double *bytes_per_launch)
 {
     if (!s || reps < 1 || !ms_per_launch) return fail(SS_EINVAL, "need a solver, reps >= 1 and an output");
-    // Keep the run state; time the CG-step SpMV as it runs inside the loop:
-    // p = r = 1, update partials of 1 each, (r, r) slot 0 = 1, no stopping
-    // (stop = 0, unbounded iterations, no history), so every launch finishes
-    // the reduction, reads slot 0, writes slot 1 and does the full work.
-    SS_HIP(hipMemcpyAsync(s->st_pinned, s->st, sizeof(DevState), hipMemcpyDeviceToHost, s->stream));
+    // Keep the run state; time the CG-step SpMV as it runs inside the loop
+    // (the FP32 inner step for an FP32_IR solver): p = r = 1, update partials
+    // of 1 each, (r, r) slot 0 = 1, no stopping (stop = 0, unbounded
+    // iterations, no history), so every launch finishes the reduction, reads
+    // slot 0, writes slot 1 and does the full work.
+    const bool f32 = s->opts.precision == SS_FP32_IR;
+    DevState *st = f32 ? s->st_in : s->st;
+    SS_HIP(hipMemcpyAsync(s->st_pinned, st, sizeof(DevState), hipMemcpyDeviceToHost, s->stream));
     SS_HIP(hipStreamSynchronize(s->stream));
     const DevState saved = *s->st_pinned;
     DevState tmp{};
@@ -660,13 +742,26 @@ int ss_cg_time_spmv(ss_solver *s, int32_t reps, double *ms_per_launch, double *b
     tmp.kmax = INT32_MAX;
     tmp.status = ST_RUNNING;
     std::memcpy(s->st_pinned, &tmp, sizeof(DevState));
-    SS_HIP(hipMemcpyAsync(s->st, s->st_pinned, sizeof(DevState), hipMemcpyHostToDevice, s->stream));
+    SS_HIP(hipMemcpyAsync(st, s->st_pinned, sizeof(DevState), hipMemcpyHostToDevice, s->stream));
     const Partials P = s->partials();
+    const size_t nl = (size_t)s->n_loc;
     std::vector<double> ones((size_t)std::max({s->n_loc, P.nb, 1}), 1.0);
-    SS_HIP(hipMemcpyAsync(s->p1, ones.data(), sizeof(double) * (size_t)s->n_loc, hipMemcpyHostToDevice, s->stream));
-    SS_HIP(hipMemcpyAsync(s->r, ones.data(), sizeof(double) * (size_t)s->n_loc, hipMemcpyHostToDevice, s->stream));
+    std::vector<float> onesf(std::max<size_t>(nl, 1), 1.0f);
+    if (f32) {
+        SS_HIP(hipMemcpyAsync(s->p32b, onesf.data(), sizeof(float) * nl, hipMemcpyHostToDevice, s->stream));
+        SS_HIP(hipMemcpyAsync(s->r32, onesf.data(), sizeof(float) * nl, hipMemcpyHostToDevice, s->stream));
+    } else {
+        SS_HIP(hipMemcpyAsync(s->p1, ones.data(), sizeof(double) * nl, hipMemcpyHostToDevice, s->stream));
+        SS_HIP(hipMemcpyAsync(s->r, ones.data(), sizeof(double) * nl, hipMemcpyHostToDevice, s->stream));
+    }
     SS_HIP(hipMemcpyAsync(P.b, ones.data(), sizeof(double) * (size_t)P.nb, hipMemcpyHostToDevice, s->stream));
-    launch_spmv_step<double, double>(s->stream, s->mat, s->p1, s->r, s->p0, s->q, P, s->st, 0);
+    auto launch = [&]() {
+        if (f32)
+            launch_spmv_step<float, float>(s->stream, s->mat32, s->p32b, s->r32, s->p32a, s->q32, P, st, 0);
+        else
+            launch_spmv_step<double, double>(s->stream, s->mat, s->p1, s->r, s->p0, s->q, P, st, 0);
+    };
+    launch();
     // one event pair around every launch: the sum of the pairs is the kernel
     // time without the gaps between launches
     std::vector<hipEvent_t> ev(2 * (size_t)reps, nullptr);
@@ -678,7 +773,7 @@ int ss_cg_time_spmv(ss_solver *s, int32_t reps, double *ms_per_launch, double *b
         }
     for (int32_t k = 0; k < reps; ++k) {
         (void)hipEventRecord(ev[2 * k], s->stream);
-        launch_spmv_step<double, double>(s->stream, s->mat, s->p1, s->r, s->p0, s->q, P, s->st, 0);
+        launch();
         (void)hipEventRecord(ev[2 * k + 1], s->stream);
     }
     hipError_t err = hipGetLastError();
@@ -693,11 +788,12 @@ int ss_cg_time_spmv(ss_solver *s, int32_t reps, double *ms_per_launch, double *b
     if (err != hipSuccess) return fail(SS_EDEVICE, std::string("SpMV timing: ") + hipGetErrorString(err));
     *ms_per_launch = total / reps;
     // values + column indices, row structure (4 B per row), one read of r and
-    // p_{k-1}, writes of p_k and q
+    // p_(k-1), writes of p_k and q
+    const double sv = f32 ? 4.0 : 8.0;
     if (bytes_per_launch)
-        *bytes_per_launch = 12.0 * (double)s->nnz + 4.0 * (double)(s->n_loc + 1) + 4.0 * 8.0 * (double)s->n_loc;
+        *bytes_per_launch = (sv + 4.0) * (double)s->nnz + 4.0 * (double)(s->n_loc + 1) + 4.0 * sv * (double)s->n_loc;
     std::memcpy(s->st_pinned, &saved, sizeof(DevState));
-    SS_HIP(hipMemcpyAsync(s->st, s->st_pinned, sizeof(DevState), hipMemcpyHostToDevice, s->stream));
+    SS_HIP(hipMemcpyAsync(st, s->st_pinned, sizeof(DevState), hipMemcpyHostToDevice, s->stream));
     SS_HIP(hipStreamSynchronize(s->stream));
     return SS_OK;
 }
