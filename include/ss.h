@@ -152,7 +152,7 @@ typedef struct {
     int32_t precision;   /* SS_FP64, or SS_FP32_IR: FP32 values and vectors in
                             the inner CG, FP64 dots, FP64 residuals and an
                             outer iterative-refinement loop                    */
-    double inner_tol;    /* IR: inner relative tolerance (<= 0: 1e-5)          */
+    double inner_tol;    /* IR: inner relative tolerance, in (0, 1); 1e-6     */
     int32_t inner_maxit; /* IR: inner iteration cap (<= 0: unlimited)          */
     int32_t max_outer;   /* IR: outer iteration cap (<= 0: 50)                 */
     int32_t check_every; /* CG iterations between host polls (<= 0: 32)        */

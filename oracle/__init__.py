@@ -191,7 +191,7 @@ def ss_cg(A, sd: SubDomains, b, x0=None, tol: float = 1e-10, maxit: int = 10000,
 
 
 def ss_ir(A, sd: SubDomains, b, x0=None, tol: float = 1e-10, maxit: int = 100000,
-          inner_tol: float = 1e-5, inner_maxit: int = 100000, max_outer: int = 50) -> tuple:
+          inner_tol: float = 1e-6, inner_maxit: int = 100000, max_outer: int = 50) -> tuple:
     S = _Sub(sd, A.val)
     b = _f64(b)
     x = np.zeros(A.n) if x0 is None else _f64(x0).copy()

@@ -413,7 +413,7 @@ void ss_opts_default(ss_opts *o)
     if (!o) return;
     std::memset(o, 0, sizeof(*o));
     o->precision = SS_FP64;
-    o->inner_tol = 1e-5;
+    o->inner_tol = 1e-6;
     o->inner_maxit = 0;
     o->max_outer = 50;
     o->check_every = kDefaultCheck;

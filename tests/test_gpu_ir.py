@@ -20,7 +20,11 @@ def _t(a):
     return torch.tensor(np.ascontiguousarray(a, dtype=np.float64), device=DEV)
 
 
+TIN = 1e-5  # inner tolerance used on both sides
+
+
 def _ir(A, p, **kw):
+    kw.setdefault("inner_tol", TIN)
     return ss.ss_cg_setup(A, p, ss.default_opts(precision=ss.SS_FP32_IR, **kw))
 
 
@@ -38,7 +42,7 @@ def test_first_inner_steps_match_oracle(q1, k):
     s = _ir(A, p, inner_maxit=k, max_outer=1)
     x = torch.zeros(A.n, dtype=torch.float64, device=DEV)
     r = ss.ss_cg_solve(s, _t(b), x, tol=1e-10, maxit=100000)
-    xo, ro = O.ss_ir(A, sd, b, tol=1e-10, inner_tol=1e-5, inner_maxit=k, max_outer=1)
+    xo, ro = O.ss_ir(A, sd, b, tol=1e-10, inner_tol=TIN, inner_maxit=k, max_outer=1)
     assert r.status == ss.SS_NOT_CONVERGED and ro.status == O.NOT_CONVERGED
     assert r.iterations == ro.iterations == k and r.outer_iterations == ro.outer == 1
     xg = x.cpu().numpy()
@@ -52,7 +56,7 @@ def test_ir_solve_reaches_fp64_residual(q1):
     s = _ir(A, p)
     x = torch.zeros(A.n, dtype=torch.float64, device=DEV)
     r = ss.ss_cg_solve(s, _t(b), x, tol=1e-10, maxit=100000, hist=True)
-    xo, ro = O.ss_ir(A, sd, b, tol=1e-10, inner_tol=1e-5)
+    xo, ro = O.ss_ir(A, sd, b, tol=1e-10, inner_tol=TIN)
     xg = x.cpu().numpy()
     true = np.linalg.norm(b - O.csr_matvec(A, xg)) / np.linalg.norm(b)
     assert r.status == ss.SS_OK and true <= 1e-10, (r, true)
