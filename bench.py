@@ -11,7 +11,19 @@ One step = one complete solve (every CG iteration: local SpMV of all
 sub-domains, interface assembly, dots and vector updates, plus the residual
 recomputation at convergence).  Prints one JSON line.
 
+The line also carries "variants", each timed on the same GPU after the main
+measurement (time to relative residual 1e-10, inputs resident):
+  mixed    -- Q1 hexahedral stiffness on 96^3 nodes (884,736 unknowns,
+              23.4M entries), 16 weighted-RCB sub-domains: plain FP64 CG vs
+              FP32 values/vectors with FP64 iterative refinement;
+  batched  -- 256 lognormal 5-point systems on 32^2..256^2 grids, 4
+              right-hand sides each: one batched solve (autotuned launch
+              shape) vs the 1024 (system, rhs) solves one by one;
+  adjoint  -- 64^3 smoothed-GRF diffusion, 8 boxes: forward solve and
+              forward + adjoint backward through torch.autograd.
+
   python bench.py [--steps K] [--warmup W] [--gpus 1] [--config 2]
+                  [--variants mixed,batched,adjoint | none]
 """
 from __future__ import annotations
 
@@ -80,6 +92,126 @@ def cpu_baseline(w, iters_gpu: int, sample_iters: int) -> dict:
     }
 
 
+def _timed(torch, fn, reps: int):
+    """Milliseconds per call of fn (one untimed call first); fn's last result."""
+    out = fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        out = fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) * 1e3 / max(reps, 1), out
+
+
+def variant_mixed(ss, torch, reps: int, tol: float) -> dict:
+    from workloads import config
+
+    w = config(3)
+    A = w.A
+    part = ss.partition_workload(w)
+    b = torch.tensor(w.b, dtype=torch.float64, device="cuda")
+    bn = float(torch.linalg.norm(b))
+    out, xs, s64 = {}, {}, None
+    for name, prec in (("fp64", ss.SS_FP64), ("fp32_ir", ss.SS_FP32_IR)):
+        s = ss.ss_cg_setup(A, part, ss.default_opts(precision=prec))
+        x = torch.zeros_like(b)
+
+        def run():
+            x.zero_()
+            return ss.ss_cg_solve(s, b, x, tol=tol, maxit=100000)
+
+        ms, r = _timed(torch, run, reps)
+        if s64 is None:
+            s64 = s
+        true = float(torch.linalg.norm(b - ss.ss_cg_apply(s64, x))) / bn
+        out[name] = {"ms": round(ms, 3), "status": r.status, "iterations": r.iterations,
+                     "outer_iterations": r.outer_iterations, "true_relres": true}
+        xs[name] = x.clone()
+        print(f"# mixed/{name}: {ms:.3f} ms, {r.iterations} iterations ({r.outer_iterations} outer), "
+              f"true relres {true:.2e}", file=sys.stderr, flush=True)
+    out["speedup_fp32_ir_over_fp64"] = round(out["fp64"]["ms"] / out["fp32_ir"]["ms"], 3)
+    out["fp32_ir_vs_fp64_solution"] = float(torch.linalg.norm(xs["fp32_ir"] - xs["fp64"]) /
+                                            torch.linalg.norm(xs["fp64"]))
+    out["workload"] = w.name
+    out["inner_tol"] = ss.default_opts().inner_tol
+    return out
+
+
+def variant_batched(ss, torch, reps: int, tol: float) -> dict:
+    import numpy as np
+
+    from workloads import config
+
+    w = config(4)
+    S, B = w.extra["systems"], w.extra["rhs"]
+    nrhs = B[0].shape[1]
+    bt = ss.ss_batch_setup(S, nrhs=nrhs)
+    b = torch.tensor(ss.pack_batch(B), dtype=torch.float64, device="cuda")
+    x = torch.zeros_like(b)
+    chosen, trials = ss.ss_batch_tune(bt, b, iters=8, force=True)
+
+    def run():
+        x.zero_()
+        return ss.ss_batch_solve(bt, b, x, tol=tol, maxit=100000)
+
+    ms_b, (res, summ) = _timed(torch, run, reps)
+    its = np.array([r.iterations for r in res])
+    print(f"# batched: {ms_b:.3f} ms for {len(res)} pairs, iterations {its.min()}..{its.max()}, tuning {chosen}",
+          file=sys.stderr, flush=True)
+    # one by one: one solver per system (set up outside the timing), every pair solved separately
+    solvers = [ss.ss_cg_setup(A, ss.ss_partition(A, ss.SS_PART_USER, 1, user_part=np.zeros(A.n))) for A in S]
+    cols = [[torch.tensor(np.ascontiguousarray(Bs[:, j]), device="cuda") for j in range(nrhs)] for Bs in B]
+    xs = [torch.zeros(A.n, dtype=torch.float64, device="cuda") for A in S]
+    worst = [ss.SS_OK]
+
+    def run_single():
+        for s, sol in enumerate(solvers):
+            for j in range(nrhs):
+                xs[s].zero_()
+                r = ss.ss_cg_solve(sol, cols[s][j], xs[s], tol=tol, maxit=100000)
+                worst[0] = min(worst[0], r.status) if r.status < 0 else max(worst[0], r.status)
+
+    ms_1, _ = _timed(torch, run_single, 1)
+    print(f"# one by one: {ms_1:.3f} ms", file=sys.stderr, flush=True)
+    return {
+        "workload": w.name, "pairs": len(res), "status": summ.status, "status_one_by_one": worst[0],
+        "batched_ms": round(ms_b, 3), "one_by_one_ms": round(ms_1, 3),
+        "speedup_batched_over_one_by_one": round(ms_1 / ms_b, 3),
+        "iterations_min": int(its.min()), "iterations_max": int(its.max()),
+        "max_relres": summ.relres, "tuning": chosen,
+        "tuning_trials_ms_per_iteration": {"best": round(min(t[1] for t in trials), 5),
+                                           "worst": round(max(t[1] for t in trials), 5), "count": len(trials)},
+    }
+
+
+def variant_adjoint(ss, torch, reps: int, tol: float) -> dict:
+    from workloads import config
+
+    w = config(5)
+    solver = ss.ss_cg_setup(w.A, ss.partition_workload(w))
+    xt = torch.tensor(w.extra["x_target"], dtype=torch.float64, device="cuda")
+    v0 = torch.tensor(w.A.val, dtype=torch.float64, device="cuda")
+    b0 = torch.tensor(w.b, dtype=torch.float64, device="cuda")
+
+    def fwd():
+        with torch.no_grad():
+            return ss.sscg_solve(v0, b0, solver, tol=tol)
+
+    def fwd_bwd():
+        vals = v0.clone().requires_grad_(True)
+        b = b0.clone().requires_grad_(True)
+        x = ss.sscg_solve(vals, b, solver, tol=tol, adj_tol=tol)
+        loss = 0.5 * torch.sum((x - xt) ** 2)
+        loss.backward()
+        return vals.grad
+
+    ms_f, _ = _timed(torch, fwd, reps)
+    ms_fb, _ = _timed(torch, fwd_bwd, reps)
+    print(f"# adjoint: forward {ms_f:.3f} ms, forward+backward {ms_fb:.3f} ms", file=sys.stderr, flush=True)
+    return {"workload": w.name, "forward_ms": round(ms_f, 3), "forward_backward_ms": round(ms_fb, 3),
+            "backward_over_forward": round((ms_fb - ms_f) / ms_f, 3)}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -89,6 +221,9 @@ def main() -> int:
     ap.add_argument("--tol", type=float, default=1e-10)
     ap.add_argument("--cpu-iters", type=int, default=150)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--variants", default="mixed,batched,adjoint",
+                    help="comma list of mixed, batched, adjoint; 'none' to skip")
+    ap.add_argument("--variant-steps", type=int, default=3)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run plain 1 GiB device copies first (reference for PMC byte counters)")
     args = ap.parse_args()
@@ -182,6 +317,14 @@ def main() -> int:
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, r.iterations, args.cpu_iters)
+    chosen = [v for v in args.variants.split(",") if v and v != "none"]
+    funcs = {"mixed": variant_mixed, "batched": variant_batched, "adjoint": variant_adjoint}
+    if chosen:
+        out["variants"] = {}
+        del solver
+        for v in chosen:
+            out["variants"][v] = funcs[v](ss, torch, args.variant_steps, args.tol)
+            torch.cuda.empty_cache()
     print(json.dumps(out), flush=True)
     return 0
 

@@ -248,6 +248,93 @@ int ss_cg_info(const ss_solver *s, int32_t *n, int32_t *n_loc, int64_t *nnz, int
 
 void ss_cg_destroy(ss_solver *s);
 
+/* ------------------------------------------------------- batched solver */
+/*
+ * Many independent SPD systems, each with nrhs right-hand sides, solved
+ * together: every CG iteration of every (system, right-hand side) pair is one
+ * pass of two kernels over all systems still running, so the launch cost is
+ * shared by the whole batch and one read of each matrix serves all its
+ * right-hand sides.  Each pair runs exactly the CG of ss_cg_solve on its own
+ * (Algorithm 3, M = I, one sub-domain): own scalars, own stopping test,
+ * recomputed-residual restarts, own iteration count; a pair that stops keeps
+ * its x while the others go on, and a system whose pairs have all stopped
+ * drops out of the launches.  Only the summation order of the dot products
+ * differs from one-by-one solves.
+ *
+ * Vector layout at the boundary (b_dev, x_dev): device, FP64, the systems'
+ * rows concatenated in batch order, the nrhs values of a row adjacent:
+ * element (system s, row i, rhs j) at (row_offset[s] + i) * nrhs + j, where
+ * row_offset[s] = n_0 + ... + n_{s-1}.
+ */
+typedef struct ss_batch ss_batch;
+
+/* Launch shape of the batched kernels.  It changes timing only: results are
+ * bitwise the same for every choice (all partial sums are taken over fixed
+ * 512-row granules). */
+typedef struct {
+    int32_t tile_granules; /* 512-row granules per workgroup tile: 1, 2, 4, 8   */
+    int32_t grid;          /* workgroups per launch, a multiple of 8 in
+                              [8, 65536]; 0 = one per tile                     */
+    int32_t unroll;        /* matrix entries loaded per lane before use: 4, 8   */
+    int32_t check_every;   /* CG iterations between host polls, even, 2..1024  */
+} ss_batch_tuning;
+
+typedef struct {
+    ss_batch_tuning tuning;
+    double ms_per_iteration; /* all pairs running */
+} ss_batch_trial;
+
+/*
+ * ss_batch_setup -- uploads nsys systems (host CSR, n >= 1, columns sorted
+ * and in range, pattern and values symmetric) for nrhs right-hand sides each (1, 2 or 4; pad to 4 with zero columns otherwise: a zero
+ * right-hand side costs nothing) to the current HIP device.  Rows may hold at
+ * most 255 entries.  o: NULL or options (only the allocator fields and
+ * check_every are used).  Default tuning: 2 granules per tile, one workgroup
+ * per tile, unroll 8, check_every 32.
+ * Errors: SS_EINVAL, SS_EUNSUPPORTED (nrhs, row length), SS_ENOMEM,
+ * SS_EDEVICE.
+ */
+int ss_batch_setup(int32_t nsys, const ss_csr *systems, int32_t nrhs, const ss_opts *o, void *hip_stream,
+                   ss_batch **out);
+
+/*
+ * ss_batch_solve -- solves A_s x_sj = b_sj for every pair.  x_dev holds the
+ * initial guesses on entry and the solutions on return; b_dev and x_dev must
+ * not overlap.  tol, maxit: as ss_cg_solve, per pair.  res (host, may be
+ * NULL): nsys * nrhs results, pair (s, j) at s * nrhs + j (outer_iterations
+ * 0).  summary (host, may be NULL): the worst status, the largest iteration
+ * count, restart count and relative residual over the pairs.
+ * Returns SS_OK when every pair converged (or had b = 0), else
+ * SS_EBREAKDOWN if any pair broke down, else SS_NOT_CONVERGED.
+ */
+int ss_batch_solve(ss_batch *bt, const double *b_dev, double *x_dev, double tol, int32_t maxit, ss_result *res,
+                   ss_result *summary);
+
+/* Sets / reads the launch shape (SS_EINVAL for values outside the ranges). */
+int ss_batch_set_tuning(ss_batch *bt, const ss_batch_tuning *t);
+int ss_batch_get_tuning(const ss_batch *bt, ss_batch_tuning *t);
+
+/*
+ * ss_batch_tune -- the autotuner.  Times each candidate launch shape (tile
+ * granules 1/2/4/8 x grid one-per-tile/2048/1024 x unroll 4/8) over `iters`
+ * CG iterations (<= 0: 8) of this batch with right-hand sides b_dev, every
+ * pair running from x = 0 (x_dev is not touched), and keeps the fastest.
+ * The choice is remembered for the process, keyed by the batch structure
+ * (row counts, entry counts, nrhs, device): a later call for a batch of the
+ * same structure takes it without timing, unless force is nonzero.
+ * chosen (may be NULL) receives the shape in use; trials (may be NULL,
+ * capacity cap) the timings, *ntrials their count (0 when cached).
+ */
+int ss_batch_tune(ss_batch *bt, const double *b_dev, int32_t iters, int32_t force, ss_batch_tuning *chosen,
+                  ss_batch_trial *trials, int32_t cap, int32_t *ntrials);
+
+/* Sizes (any pointer may be NULL): systems, right-hand sides, total rows,
+ * stored entries of the systems and the device storage incl. padding. */
+int ss_batch_info(const ss_batch *bt, int32_t *nsys, int32_t *nrhs, int64_t *nrows, int64_t *nnz,
+                  int64_t *stored);
+
+void ss_batch_destroy(ss_batch *bt);
+
 /* --------------------------------------------------------------- errors */
 const char *ss_strerror(int code);
 const char *ss_last_error(void); /* detail of the last failure on this thread */

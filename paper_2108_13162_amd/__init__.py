@@ -50,6 +50,15 @@ class ss_result(C.Structure):
                 ("restarts", C.c_int32), ("relres", C.c_double), ("true_relres", C.c_double)]
 
 
+class ss_batch_tuning(C.Structure):
+    _fields_ = [("tile_granules", C.c_int32), ("grid", C.c_int32), ("unroll", C.c_int32),
+                ("check_every", C.c_int32)]
+
+
+class ss_batch_trial(C.Structure):
+    _fields_ = [("tuning", ss_batch_tuning), ("ms_per_iteration", C.c_double)]
+
+
 class SSError(RuntimeError):
     def __init__(self, code: int, where: str, detail: str = ""):
         self.code = code
@@ -83,6 +92,13 @@ def lib() -> C.CDLL:
         "ss_cg_time_spmv": (C.c_int, [P, i32, P, P]),
         "ss_cg_info": (C.c_int, [P, P, P, P, P, P]),
         "ss_cg_destroy": (None, [P]),
+        "ss_batch_setup": (C.c_int, [i32, P, i32, P, P, P]),
+        "ss_batch_solve": (C.c_int, [P, P, P, dbl, i32, P, P]),
+        "ss_batch_set_tuning": (C.c_int, [P, P]),
+        "ss_batch_get_tuning": (C.c_int, [P, P]),
+        "ss_batch_tune": (C.c_int, [P, P, i32, i32, P, P, i32, P]),
+        "ss_batch_info": (C.c_int, [P, P, P, P, P, P]),
+        "ss_batch_destroy": (None, [P]),
         "ss_strerror": (C.c_char_p, [C.c_int]),
         "ss_last_error": (C.c_char_p, []),
         "ss_version": (C.c_int, []),
@@ -345,6 +361,104 @@ def ss_cg_time_spmv(s: Solver, reps: int = 20) -> tuple:
     ms, nbytes = C.c_double(), C.c_double()
     _check(lib().ss_cg_time_spmv(s.h, int(reps), C.byref(ms), C.byref(nbytes)), "ss_cg_time_spmv")
     return ms.value, nbytes.value
+
+
+# ----------------------------------------------------------------------------
+# batched solver
+# ----------------------------------------------------------------------------
+
+class Batch:
+    """Handle of a batch of independent systems (ss_batch_setup)."""
+
+    def __init__(self, h, allocator, stream, sizes, nrhs):
+        self.h = h
+        self.allocator = allocator
+        self.stream = stream
+        self.sizes = np.asarray(sizes, dtype=np.int64)
+        self.offsets = np.concatenate([[0], np.cumsum(self.sizes)])
+        self.nrhs = nrhs
+        self.nrows = int(self.offsets[-1])
+
+    def __del__(self):
+        h, self.h = getattr(self, "h", None), None
+        if h and _lib is not None:
+            _lib.ss_batch_destroy(h)
+
+    def close(self):
+        self.__del__()
+
+    def info(self) -> dict:
+        v = [C.c_int32(), C.c_int32(), C.c_int64(), C.c_int64(), C.c_int64()]
+        _check(lib().ss_batch_info(self.h, *[C.byref(t) for t in v]), "ss_batch_info")
+        return dict(zip(["nsys", "nrhs", "nrows", "nnz", "stored"], [t.value for t in v]))
+
+
+def _tuning_dict(t: ss_batch_tuning) -> dict:
+    return {"tile_granules": t.tile_granules, "grid": t.grid, "unroll": t.unroll, "check_every": t.check_every}
+
+
+def ss_batch_setup(systems, nrhs: int = 4, opts: Optional[ss_opts] = None, device=None) -> Batch:
+    """Uploads the systems (host CSR objects) for nrhs right-hand sides each."""
+    torch = _torch()
+    if not torch.cuda.is_available():
+        raise RuntimeError("ss_batch_setup needs a GPU")
+    dev = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+    o = default_opts() if opts is None else opts
+    alloc = _TorchAllocator(dev)
+    o.alloc, o.free, o.alloc_ctx = alloc.alloc_cb, alloc.free_cb, None
+    host = [_HostCSR(A) for A in systems]
+    arr = (ss_csr * len(host))(*[h.s for h in host])
+    stream = torch.cuda.current_stream(dev)
+    out = C.c_void_p()
+    with torch.cuda.device(dev):
+        _check(lib().ss_batch_setup(len(host), arr, int(nrhs), C.byref(o), C.c_void_p(stream.cuda_stream),
+                                    C.byref(out)), "ss_batch_setup")
+    return Batch(out, alloc, stream, [A.n for A in systems], int(nrhs))
+
+
+def ss_batch_solve(bt: Batch, b, x, tol: float = 1e-10, maxit: int = 100000):
+    """Solves every (system, rhs) pair in place on x.  b, x: device float64
+    tensors of nrows * nrhs elements, row-major [row][rhs] with the systems'
+    rows concatenated.  Returns (per-pair Result list in (system, rhs) order,
+    summary Result)."""
+    n = bt.nrows * bt.nrhs
+    pb, px = _dev_f64(b, n, "b"), _dev_f64(x, n, "x")
+    np_ = len(bt.sizes) * bt.nrhs
+    res = (ss_result * np_)()
+    summ = ss_result()
+    code = lib().ss_batch_solve(bt.h, pb, px, float(tol), int(maxit), res, C.byref(summ))
+    _check(code, "ss_batch_solve", ok=(SS_OK, SS_NOT_CONVERGED, SS_EBREAKDOWN))
+    conv = lambda r: Result(r.status, r.iterations, r.outer_iterations, r.restarts, r.relres, r.true_relres)
+    return [conv(r) for r in res], conv(summ)
+
+
+def ss_batch_tune(bt: Batch, b, iters: int = 8, force: bool = False):
+    """Autotuner: returns (chosen tuning dict, list of (tuning dict, ms per iteration))."""
+    n = bt.nrows * bt.nrhs
+    cap = 64
+    trials = (ss_batch_trial * cap)()
+    nt = C.c_int32()
+    chosen = ss_batch_tuning()
+    _check(lib().ss_batch_tune(bt.h, _dev_f64(b, n, "b"), int(iters), int(bool(force)), C.byref(chosen), trials,
+                               cap, C.byref(nt)), "ss_batch_tune")
+    return _tuning_dict(chosen), [(_tuning_dict(trials[i].tuning), trials[i].ms_per_iteration)
+                                  for i in range(nt.value)]
+
+
+def ss_batch_set_tuning(bt: Batch, tile_granules: int, grid: int, unroll: int, check_every: int) -> None:
+    t = ss_batch_tuning(tile_granules, grid, unroll, check_every)
+    _check(lib().ss_batch_set_tuning(bt.h, C.byref(t)), "ss_batch_set_tuning")
+
+
+def ss_batch_get_tuning(bt: Batch) -> dict:
+    t = ss_batch_tuning()
+    _check(lib().ss_batch_get_tuning(bt.h, C.byref(t)), "ss_batch_get_tuning")
+    return _tuning_dict(t)
+
+
+def pack_batch(blocks) -> np.ndarray:
+    """Host helper: per-system [n_s, nrhs] arrays -> the flat batch layout."""
+    return np.ascontiguousarray(np.concatenate([np.asarray(b, dtype=np.float64) for b in blocks], axis=0)).ravel()
 
 
 # ----------------------------------------------------------------------------

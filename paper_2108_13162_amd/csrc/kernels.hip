@@ -20,28 +20,21 @@
 // products and sums are rounded separately, as the expressions are written.
 #include "kernels.h"
 
+#include "device_common.h"
+
 #include <algorithm>
 #include <cmath>
 
 namespace ss {
 namespace {
 
-__device__ __forceinline__ int xcd_remap(int b, int grid)
-{
-    // workgroup b runs on XCD b % 8; give each XCD a contiguous range of work
-    const int per = grid / kNumXcd;
-    return (b % kNumXcd) * per + b / kNumXcd;
-}
+using dev::block_sum_all;
+using dev::wave_sum;
+using dev::xcd_remap;
 
-__device__ __forceinline__ int32_t load_status(const DevState *st)
-{
-    return __hip_atomic_load(&st->status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
+__device__ __forceinline__ int32_t load_status(const DevState *st) { return dev::flag_load(&st->status); }
 
-__device__ __forceinline__ void store_status(DevState *st, int32_t v)
-{
-    __hip_atomic_store(&st->status, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
+__device__ __forceinline__ void store_status(DevState *st, int32_t v) { dev::flag_store(&st->status, v); }
 
 // Status read once per workgroup and shared, so the whole workgroup takes the
 // same branch.
@@ -50,35 +43,6 @@ __device__ __forceinline__ bool running(const DevState *st, int *s_flag)
     if (threadIdx.x == 0) *s_flag = load_status(st);
     __syncthreads();
     return *s_flag == ST_RUNNING;
-}
-
-template <typename T>
-__device__ __forceinline__ T wave_sum(T v)
-{
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = v + __shfl_xor(v, o, 64);
-    return v;
-}
-
-// Fixed-order sum over the workgroup, returned to every thread.
-// ws: kBS/64 + 1 slots.
-template <typename T>
-__device__ __forceinline__ T block_sum_all(T v, T *ws)
-{
-    v = wave_sum(v);
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    if (lane == 0) ws[w] = v;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        T t = T(0);
-#pragma unroll
-        for (int i = 0; i < kBS / 64; ++i) t = t + ws[i];
-        ws[kBS / 64] = t;
-    }
-    __syncthreads();
-    const T t = ws[kBS / 64];
-    __syncthreads();
-    return t;
 }
 
 // Sum of n partials in a fixed order (thread t adds partials t, t+kBS, ...

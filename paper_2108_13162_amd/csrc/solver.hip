@@ -10,6 +10,7 @@
 #include <string>
 #include <vector>
 
+#include "host_common.h"
 #include "kernels.h"
 #include "ss_internal.h"
 
@@ -21,54 +22,6 @@ constexpr int kDefaultCheck = 32;
 constexpr int32_t kHistMax = 1 << 22;  // residual history entries kept on the device
 constexpr int kSpmvGridMax = 1024;      // persistent SpMV workgroups (4 per CU)
 constexpr int kGridLimit = 65536;       // upper bound accepted for a requested grid
-
-struct DeviceMem {
-    ss_alloc_fn alloc = nullptr;
-    ss_free_fn release = nullptr;
-    void *ctx = nullptr;
-    std::vector<void *> blocks;
-
-    void *get(size_t bytes)
-    {
-        if (bytes == 0) bytes = 16;
-        bytes = (bytes + 255) & ~size_t(255);
-        void *p = nullptr;
-        if (alloc) {
-            p = alloc(ctx, bytes);
-        } else if (hipMalloc(&p, bytes) != hipSuccess) {
-            (void)hipGetLastError();
-            p = nullptr;
-        }
-        if (p) blocks.push_back(p);
-        return p;
-    }
-    void put(void *p)
-    {
-        auto it = std::find(blocks.begin(), blocks.end(), p);
-        if (it == blocks.end()) return;
-        blocks.erase(it);
-        if (release)
-            release(ctx, p);
-        else
-            (void)hipFree(p);
-    }
-    void clear()
-    {
-        for (void *p : blocks) {
-            if (release)
-                release(ctx, p);
-            else
-                (void)hipFree(p);
-        }
-        blocks.clear();
-    }
-};
-
-#define SS_HIP(call)                                                                                         \
-    do {                                                                                                     \
-        hipError_t e_ = (call);                                                                              \
-        if (e_ != hipSuccess) return fail(SS_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
-    } while (0)
 
 // Host image of the device data of one partition.
 struct Layout {

@@ -141,3 +141,32 @@ def test_invalid_inputs_rejected():
     _expect_einval(A, method=ss.SS_PART_RCB, nparts=2, coords=grid_coords((4, 4)), weights=[1.0, -1.0])
     _expect_einval(A, method=ss.SS_PART_USER, nparts=2, user_part=np.full(A.n, 2))
     _expect_einval(A, method=7, nparts=1)
+
+
+def test_batch_setup_rejects_invalid_inputs_before_device_use():
+    # every check below happens on the host, before any device call
+    A = poisson2d(4)
+    hs = [ss._HostCSR(A), ss._HostCSR(poisson2d(3))]
+    arr = (ss.ss_csr * 2)(*[h.s for h in hs])
+    out = C.c_void_p()
+    L = ss.lib()
+    assert L.ss_batch_setup(2, arr, 3, None, None, C.byref(out)) == ss.SS_EUNSUPPORTED
+    assert "nrhs" in ss.last_error()
+    assert L.ss_batch_setup(0, arr, 4, None, None, C.byref(out)) == ss.SS_EINVAL
+    assert L.ss_batch_setup(2, None, 4, None, None, C.byref(out)) == ss.SS_EINVAL
+    bad = CSR(A.n, A.rowptr.copy(), A.colidx.copy(), A.val.copy())
+    bad.val[1] = -2.0  # asymmetric values in the second system
+    hb = [hs[0], ss._HostCSR(bad)]
+    arr = (ss.ss_csr * 2)(*[h.s for h in hb])
+    assert L.ss_batch_setup(2, arr, 4, None, None, C.byref(out)) == ss.SS_EINVAL
+    assert "system 1" in ss.last_error() and "not symmetric" in ss.last_error()
+    # a dense 300 x 300 SPD system: rows longer than 255 entries
+    n = 300
+    D = np.full((n, n), -1.0 / n) + np.eye(n) * 2.0
+    rp = np.arange(0, n * n + 1, n, dtype=np.int32)
+    ci = np.tile(np.arange(n, dtype=np.int32), n)
+    hd = [ss._HostCSR(CSR(n, rp, ci, D.ravel()))]
+    arr = (ss.ss_csr * 1)(*[h.s for h in hd])
+    assert L.ss_batch_setup(1, arr, 4, None, None, C.byref(out)) == ss.SS_EUNSUPPORTED
+    assert "255" in ss.last_error()
+    assert not out.value
