@@ -137,7 +137,7 @@ def variant_mixed(ss, torch, reps: int, tol: float) -> dict:
     return out
 
 
-def variant_batched(ss, torch, reps: int, tol: float) -> dict:
+def variant_batched(ss, torch, reps: int, tol: float, one_by_one: bool = True) -> dict:
     import numpy as np
 
     from workloads import config
@@ -158,6 +158,23 @@ def variant_batched(ss, torch, reps: int, tol: float) -> dict:
     its = np.array([r.iterations for r in res])
     print(f"# batched: {ms_b:.3f} ms for {len(res)} pairs, iterations {its.min()}..{its.max()}, tuning {chosen}",
           file=sys.stderr, flush=True)
+    out = {
+        "workload": w.name, "pairs": len(res), "status": summ.status, "batched_ms": round(ms_b, 3),
+        "iterations_min": int(its.min()), "iterations_max": int(its.max()),
+        "max_relres": summ.relres, "tuning": chosen,
+        "tuning_trials_ms_per_iteration": {"best": round(min(t[1] for t in trials), 5),
+                                           "worst": round(max(t[1] for t in trials), 5), "count": len(trials)},
+    }
+    # algorithmic bytes: every iteration of a system while any of its pairs runs
+    # reads the matrix once (12 B per entry + 1 B row length) and moves 10
+    # vector values of 8 B per row and right-hand side (SpMV: r and p read
+    # once, p and q written; update: x, p, r, q read, x and r written)
+    per_sys_its = its.reshape(len(S), nrhs).max(axis=1)
+    nbytes = sum(int(k) * (12 * A.nnz + A.n + 80 * nrhs * A.n) for k, A in zip(per_sys_its, S))
+    out["algorithmic_bytes"] = nbytes
+    out["effective_gbps"] = round(nbytes / (ms_b * 1e-3) / 1e9, 1)
+    if not one_by_one:
+        return out
     # one by one: one solver per system (set up outside the timing), every pair solved separately
     solvers = [ss.ss_cg_setup(A, ss.ss_partition(A, ss.SS_PART_USER, 1, user_part=np.zeros(A.n))) for A in S]
     cols = [[torch.tensor(np.ascontiguousarray(Bs[:, j]), device="cuda") for j in range(nrhs)] for Bs in B]
@@ -173,15 +190,9 @@ def variant_batched(ss, torch, reps: int, tol: float) -> dict:
 
     ms_1, _ = _timed(torch, run_single, 1)
     print(f"# one by one: {ms_1:.3f} ms", file=sys.stderr, flush=True)
-    return {
-        "workload": w.name, "pairs": len(res), "status": summ.status, "status_one_by_one": worst[0],
-        "batched_ms": round(ms_b, 3), "one_by_one_ms": round(ms_1, 3),
-        "speedup_batched_over_one_by_one": round(ms_1 / ms_b, 3),
-        "iterations_min": int(its.min()), "iterations_max": int(its.max()),
-        "max_relres": summ.relres, "tuning": chosen,
-        "tuning_trials_ms_per_iteration": {"best": round(min(t[1] for t in trials), 5),
-                                           "worst": round(max(t[1] for t in trials), 5), "count": len(trials)},
-    }
+    out.update({"status_one_by_one": worst[0], "one_by_one_ms": round(ms_1, 3),
+                "speedup_batched_over_one_by_one": round(ms_1 / ms_b, 3)})
+    return out
 
 
 def variant_adjoint(ss, torch, reps: int, tol: float) -> dict:
@@ -212,35 +223,8 @@ def variant_adjoint(ss, torch, reps: int, tol: float) -> dict:
             "backward_over_forward": round((ms_fb - ms_f) / ms_f, 3)}
 
 
-def main() -> int:
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--config", type=int, default=2, choices=[1, 2, 5])
-    ap.add_argument("--tol", type=float, default=1e-10)
-    ap.add_argument("--cpu-iters", type=int, default=150)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--variants", default="mixed,batched,adjoint",
-                    help="comma list of mixed, batched, adjoint; 'none' to skip")
-    ap.add_argument("--variant-steps", type=int, default=3)
-    ap.add_argument("--copy-calibration", action="store_true",
-                    help="run plain 1 GiB device copies first (reference for PMC byte counters)")
-    args = ap.parse_args()
-    world = int(os.environ.get("WORLD_SIZE", "1"))
-    if args.gpus != 1 or world != 1:
-        print("bench.py: this build runs on one GPU only (all sub-domains resident on one MI355X); "
-              f"--gpus {args.gpus} / WORLD_SIZE {world} is not supported", file=sys.stderr)
-        return 2
-
-    import numpy as np
-    import torch
-
-    import paper_2108_13162_amd as ss
-    from workloads import config
-
-    if args.copy_calibration:
-        calibrate_copy(torch)
+def main_measurement(args, ss, torch, config):
+    """The main line: time to 1e-10 of FP64 sub-structured CG on the chosen workload."""
     w = config(args.config)
     A = w.A
     part = ss.partition_workload(w)
@@ -268,7 +252,7 @@ def main() -> int:
     r = results[-1] if results else ss.ss_cg_solve(solver, b, x, tol=args.tol, maxit=100000)
     if any(q.status != ss.SS_OK for q in results):
         print(f"bench.py: solve did not converge: {[q.status for q in results]}", file=sys.stderr)
-        return 1
+        return None
     print(f"# timed: {args.steps} solves, {ms_step:.3f} ms each, {r.iterations} iterations", file=sys.stderr,
           flush=True)
 
@@ -317,13 +301,52 @@ def main() -> int:
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, r.iterations, args.cpu_iters)
+    return out
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--config", type=int, default=2, choices=[1, 2, 5])
+    ap.add_argument("--tol", type=float, default=1e-10)
+    ap.add_argument("--cpu-iters", type=int, default=150)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--variants", default="mixed,batched,adjoint",
+                    help="comma list of mixed, batched, adjoint; 'none' to skip")
+    ap.add_argument("--variant-steps", type=int, default=3)
+    ap.add_argument("--no-main", action="store_true",
+                    help="profiling aid: skip the main measurement, print only the variants")
+    ap.add_argument("--no-one-by-one", action="store_true",
+                    help="profiling aid: skip the one-by-one half of the batched comparison")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run plain 1 GiB device copies first (reference for PMC byte counters)")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py: this build runs on one GPU only (all sub-domains resident on one MI355X); "
+              f"--gpus {args.gpus} / WORLD_SIZE {world} is not supported", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    import paper_2108_13162_amd as ss
+    from workloads import config
+
+    if args.copy_calibration:
+        calibrate_copy(torch)
+    out = {} if args.no_main else main_measurement(args, ss, torch, config)
+    if out is None:
+        return 1
     chosen = [v for v in args.variants.split(",") if v and v != "none"]
     funcs = {"mixed": variant_mixed, "batched": variant_batched, "adjoint": variant_adjoint}
     if chosen:
         out["variants"] = {}
-        del solver
         for v in chosen:
-            out["variants"][v] = funcs[v](ss, torch, args.variant_steps, args.tol)
+            kw = {"one_by_one": not args.no_one_by_one} if v == "batched" else {}
+            out["variants"][v] = funcs[v](ss, torch, args.variant_steps, args.tol, **kw)
             torch.cuda.empty_cache()
     print(json.dumps(out), flush=True)
     return 0
