@@ -29,6 +29,7 @@
 #include <algorithm>
 #include <climits>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -49,6 +50,7 @@ constexpr int kWaves = kWG / 64;
 constexpr int kChunk = 64;                       // rows per SELL chunk
 constexpr int kGranRows = 512;                   // rows per granule
 constexpr int kMaxRowLen = 255;
+constexpr int kRingBytes = 32768;                // LDS window of the staged SpMV
 constexpr int kGridLimit = 65536;
 
 enum : int32_t { BS_RUNNING = 0, BS_CONVERGED = 1, BS_MAXIT = 2, BS_BREAKDOWN = 3, BS_ZERO_RHS = 4 };
@@ -70,6 +72,7 @@ struct BTiles {
     const int32_t *tile_g0;   // [ntiles+1] granules of tile t: tile_g0[t] .. tile_g0[t+1]
     const int32_t *gran_c0;   // [ngran+1] chunks of granule g
     const int32_t *sys_g0;    // [nsys+1] granules of system s
+    const int32_t *sys_h;     // [nsys] largest |column - row| of system s
 };
 
 // Per-pair CG state, pair (s, j) at index s * NR + j.  (r, r) and the
@@ -118,6 +121,16 @@ __device__ __forceinline__ void st_row(double *__restrict__ v, int row, const do
         p[0] = make_double2(o[0], o[1]);
         p[1] = make_double2(o[2], o[3]);
     }
+}
+
+template <int NR>
+__device__ __forceinline__ double pick(const double (&a)[NR], int j)
+{
+    double v = a[0];
+#pragma unroll
+    for (int i = 1; i < NR; ++i)
+        if (j == i) v = a[i];
+    return v;
 }
 
 // The pair statuses of system s into LDS; true if any pair is running.
@@ -213,6 +226,13 @@ __device__ __forceinline__ Share list_share(int nact)
 //  M_FIRST: p = r (pairs running), q = A p, partials (p, q) -> part_a.
 //  M_STEP : (r, r) from part_b -> stopping test, beta; p = r + beta pin;
 //           q = A p, partials (p, q) -> part_a.
+//
+// Staged path (systems whose entries all lie within h <= HMAX rows of the
+// diagonal): the workgroup keeps the vector it multiplies (p = r + beta p,
+// r or pin) for the rows [first row of the granule - h, last row + h) in an
+// LDS ring of W rows, sliding granule by granule through its tile, so every
+// vector row is read from memory once per tile (plus the 2h halo rows) and
+// the column gathers are LDS reads.  Other systems gather from memory.
 template <int NR, int U, int MODE>
 __global__ __launch_bounds__(kWG) void k_bspmv(BMat M, BTiles T, BState S, const double *__restrict__ pin,
                                                const double *__restrict__ r, double *__restrict__ pout,
@@ -220,8 +240,11 @@ __global__ __launch_bounds__(kWG) void k_bspmv(BMat M, BTiles T, BState S, const
                                                const double *__restrict__ part_b, int slot)
 {
     constexpr bool CG = MODE != M_PLAIN;
+    constexpr int W = kRingBytes / (8 * NR);  // ring rows (power of two)
+    constexpr int HMAX = (W - kGranRows) / 2;
     __shared__ double ws[kWaves * NR];
     __shared__ int32_t sh_st[NR];
+    __shared__ __align__(16) double ring[W * NR];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const Share sh = list_share(*T.nlist);
     for (int i = sh.i; i < sh.end; i += sh.step) {
@@ -275,8 +298,34 @@ __global__ __launch_bounds__(kWG) void k_bspmv(BMat M, BTiles T, BState S, const
             if (!any) continue;
         }
         const int g0 = T.tile_g0[t], g1 = T.tile_g0[t + 1];
+        const int h = T.sys_h[s];
+        const bool staged = h <= HMAX;
+        const int S0 = M.crow[T.gran_c0[T.sys_g0[s]]], S1 = M.crow[T.gran_c0[T.sys_g0[s + 1]]];
+        int hi = -1;  // ring holds rows [.., hi)
         for (int g = g0; g < g1; ++g) {
             const int c0 = T.gran_c0[g], c1 = T.gran_c0[g + 1];
+            if (staged) {
+                const int a = M.crow[c0], e = M.crow[c1];
+                const int need = min(S1, e + h);
+                const int from = hi < 0 ? max(S0, a - h) : hi;
+                for (int row = from + (int)threadIdx.x; row < need; row += kWG) {
+                    double v[NR];
+                    if (MODE == M_PLAIN) {
+                        ld_row<NR>(pin, row, v);
+                    } else if (MODE == M_FIRST) {
+                        ld_row<NR>(r, row, v);
+                    } else {
+                        double rv[NR], pv[NR];
+                        ld_row<NR>(r, row, rv);
+                        ld_row<NR>(pin, row, pv);
+#pragma unroll
+                        for (int j = 0; j < NR; ++j) v[j] = rv[j] + beta[j] * pv[j];
+                    }
+                    st_row<NR>(ring, row & (W - 1), v);
+                }
+                hi = need;
+                __syncthreads();
+            }
             double acc[NR];
 #pragma unroll
             for (int j = 0; j < NR; ++j) acc[j] = 0.0;
@@ -304,7 +353,9 @@ __global__ __launch_bounds__(kWG) void k_bspmv(BMat M, BTiles T, BState S, const
 #pragma unroll
                     for (int u = 0; u < U; ++u) {
                         if (j0 + u < L) {
-                            if (MODE == M_PLAIN) {
+                            if (staged) {
+                                ld_row<NR>(ring, cc[u] & (W - 1), xx[u]);
+                            } else if (MODE == M_PLAIN) {
                                 ld_row<NR>(pin, cc[u], xx[u]);
                             } else if (MODE == M_FIRST) {
                                 ld_row<NR>(r, cc[u], xx[u]);
@@ -328,7 +379,9 @@ __global__ __launch_bounds__(kWG) void k_bspmv(BMat M, BTiles T, BState S, const
                     st_row<NR>(q, row, sum);
                     if (CG) {
                         double pr[NR];
-                        if (MODE == M_FIRST) {
+                        if (staged) {
+                            ld_row<NR>(ring, row & (W - 1), pr);
+                        } else if (MODE == M_FIRST) {
                             ld_row<NR>(r, row, pr);
                         } else {
                             double rv[NR], pv[NR];
@@ -343,22 +396,15 @@ __global__ __launch_bounds__(kWG) void k_bspmv(BMat M, BTiles T, BState S, const
                     }
                 }
             }
-            if (CG) granule_store_rows<NR>(acc, part_a, g, ws);
+            if (CG)
+                granule_store_rows<NR>(acc, part_a, g, ws);  // ends with a barrier
+            else if (staged)
+                __syncthreads();  // ring reads done before the next granule is staged
         }
     }
 }
 
 // ---- alpha + x / r update + (r, r) partials ----------------------------------
-
-template <int NR>
-__device__ __forceinline__ double pick(const double (&a)[NR], int j)
-{
-    double v = a[0];
-#pragma unroll
-    for (int i = 1; i < NR; ++i)
-        if (j == i) v = a[i];
-    return v;
-}
 
 template <int NR>
 __global__ __launch_bounds__(kWG) void k_bupdate(BMat M, BTiles T, BState S, double *__restrict__ x,
@@ -375,6 +421,21 @@ __global__ __launch_bounds__(kWG) void k_bupdate(BMat M, BTiles T, BState S, dou
         const int t = T.list[i];
         const int s = T.tile_sys[t];
         if (!load_sys_status<NR>(S, s, sh_st)) continue;
+        const int g0 = T.tile_g0[t], g1 = T.tile_g0[t + 1];
+        // operands of the first granule, loaded before alpha is known
+        double xv[NI], pv[NI], rv[NI], qv[NI];
+        int e0 = M.crow[T.gran_c0[g0]] * NR, e1 = M.crow[T.gran_c0[g0 + 1]] * NR;
+        bool full = e1 - e0 == kGranRows * NR;
+        if (full) {
+#pragma unroll
+            for (int k = 0; k < NI; ++k) {
+                const int e = e0 + (int)threadIdx.x + k * kWG;
+                xv[k] = x[e];
+                pv[k] = p[e];
+                rv[k] = r[e];
+                qv[k] = q[e];
+            }
+        }
         double pAp[NR], alpha[NR], runv[NR];
         sys_sum<NR>(part_a, T.sys_g0[s], T.sys_g0[s + 1], ws, pAp);
         const bool lead = T.tile_g0[t] == T.sys_g0[s] && threadIdx.x == 0;
@@ -400,20 +461,24 @@ __global__ __launch_bounds__(kWG) void k_bupdate(BMat M, BTiles T, BState S, dou
         if (!any) continue;
         const double a = pick<NR>(alpha, jt);
         const bool run = pick<NR>(runv, jt) != 0.0;
-        const int g0 = T.tile_g0[t], g1 = T.tile_g0[t + 1];
         for (int g = g0; g < g1; ++g) {
-            const int e0 = M.crow[T.gran_c0[g]] * NR, e1 = M.crow[T.gran_c0[g + 1]] * NR;
-            double accv = 0.0;
-            if (e1 - e0 == kGranRows * NR) {
-                double xv[NI], pv[NI], rv[NI], qv[NI];
+            if (g != g0) {
+                e0 = M.crow[T.gran_c0[g]] * NR;
+                e1 = M.crow[T.gran_c0[g + 1]] * NR;
+                full = e1 - e0 == kGranRows * NR;
+                if (full) {
 #pragma unroll
-                for (int k = 0; k < NI; ++k) {
-                    const int e = e0 + (int)threadIdx.x + k * kWG;
-                    xv[k] = x[e];
-                    pv[k] = p[e];
-                    rv[k] = r[e];
-                    qv[k] = q[e];
+                    for (int k = 0; k < NI; ++k) {
+                        const int e = e0 + (int)threadIdx.x + k * kWG;
+                        xv[k] = x[e];
+                        pv[k] = p[e];
+                        rv[k] = r[e];
+                        qv[k] = q[e];
+                    }
                 }
+            }
+            double accv = 0.0;
+            if (full) {
                 if (run) {
 #pragma unroll
                     for (int k = 0; k < NI; ++k) {
@@ -647,6 +712,7 @@ struct ss_batch {
     hipStream_t stream = nullptr, cap = nullptr;
     DeviceMem mem;
     std::vector<int32_t> sys_g0_h;
+    int32_t *sys_h = nullptr;
     // matrix and granules
     int32_t *col = nullptr, *cptr = nullptr, *crow = nullptr, *gran_c0 = nullptr, *sys_g0 = nullptr;
     double *val = nullptr;
@@ -672,7 +738,7 @@ struct ss_batch {
     BMat bmat() const { return BMat{col, val, cptr, crow, clen, rlen}; }
     BTiles tiles(bool full) const
     {
-        return BTiles{full ? list_full : list_act, full ? n_full : n_act, tile_sys, tile_g0, gran_c0, sys_g0};
+        return BTiles{full ? list_full : list_act, full ? n_full : n_act, tile_sys, tile_g0, gran_c0, sys_g0, sys_h};
     }
     BState state() const
     {
@@ -930,16 +996,19 @@ int ss_batch_setup(int32_t nsys, const ss_csr *systems, int32_t nrhs, const ss_o
     if ((opts.alloc == nullptr) != (opts.free == nullptr)) return fail(SS_EINVAL, "alloc and free go together");
 
     // host structure: SELL-64 chunks per system, granules of 8 chunks
-    std::vector<int32_t> rows_h(nsys);
+    std::vector<int32_t> rows_h(nsys), halo(nsys, 0);
     std::vector<int64_t> nnz_h(nsys);
     int64_t nrows = 0, nnz = 0, stored = 0, nchunks = 0;
     for (int s = 0; s < nsys; ++s) {
         const ss_csr *A = &systems[s];
         int rc = validate_csr(A, true);
         if (rc != SS_OK) return fail(rc, "system " + std::to_string(s) + ": " + ss_last_error());
-        for (int i = 0; i < A->n; ++i)
+        for (int i = 0; i < A->n; ++i) {
             if (A->rowptr[i + 1] - A->rowptr[i] > kMaxRowLen)
                 return fail(SS_EUNSUPPORTED, "system " + std::to_string(s) + ": a row holds more than 255 entries");
+            for (int k = A->rowptr[i]; k < A->rowptr[i + 1]; ++k)
+                halo[s] = std::max(halo[s], std::abs(A->colidx[k] - i));
+        }
         rows_h[s] = A->n;
         nnz_h[s] = A->nnz;
         nrows += A->n;
@@ -1030,6 +1099,7 @@ int ss_batch_setup(int32_t nsys, const ss_csr *systems, int32_t nrhs, const ss_o
     if ((rc = upload(b, &b->col, col)) || (rc = upload(b, &b->val, val)) || (rc = upload(b, &b->cptr, cptr)) ||
         (rc = upload(b, &b->crow, crow)) || (rc = upload(b, &b->clen, clen)) || (rc = upload(b, &b->rlen, rlen)) ||
         (rc = upload(b, &b->gran_c0, gran_c0)) || (rc = upload(b, &b->sys_g0, sys_g0)) ||
+        (rc = upload(b, &b->sys_h, halo)) ||
         (rc = alloc_dev(b, &b->tile_sys, (size_t)b->ngran)) || (rc = alloc_dev(b, &b->tile_g0, (size_t)b->ngran + 1)) ||
         (rc = alloc_dev(b, &b->sys_t0, (size_t)nsys + 1)) || (rc = alloc_dev(b, &b->list_full, (size_t)b->ngran)) ||
         (rc = alloc_dev(b, &b->list_act, (size_t)b->ngran)) || (rc = alloc_dev(b, &b->n_full, 1)) ||
