@@ -39,13 +39,18 @@ sys.path.insert(0, ROOT)
 
 METRIC = "time to rel-res 1e-10 + SpMV HBM GB/s; mixed/batched vs plain FP64 CG"
 HBM_PEAK_GBS = 8000.0
-KERNEL_SRC = os.path.join(ROOT, "paper_2108_13162_amd", "csrc", "kernels.hip")
+KERNEL_SRC = [os.path.join(ROOT, "paper_2108_13162_amd", "csrc", f)
+              for f in ("kernels.hip", "kernels.h", "device_common.h")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "spmv_cg_step_traffic.json")
 
 
 def kernel_sha() -> str:
-    with open(KERNEL_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    """SHA-256 prefix of the sources the single-system kernels are built from."""
+    h = hashlib.sha256()
+    for fn in KERNEL_SRC:
+        with open(fn, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def load_traffic(workload: str):
@@ -261,7 +266,7 @@ def main_measurement(args, ss, torch, config):
     achieved = spmv_bytes / (spmv_ms * 1e-3) / 1e9
     traffic = load_traffic(w.name)
     n_loc = info["n_loc"]
-    iter_bytes = spmv_bytes + 48.0 * n_loc  # + update kernel: x, p, r, q read; x, r written
+    iter_bytes = spmv_bytes + 24.0 * n_loc  # + update kernel: r, q read; r written
     ms_iter = ms_step / max(r.iterations, 1)
 
     out = {

@@ -233,11 +233,11 @@ int ss_cg_grad_vals(ss_solver *s, const double *lambda_dev, const double *x_dev,
 
 /* Average duration in milliseconds of one launch of the local SpMV kernel
  * (the CG-step variant; the FP32 inner step for an SS_FP32_IR solver),
- * timed with one HIP event pair around each of `reps`
- * back-to-back launches on the solver stream.  Leaves the solver state
- * unchanged except for scratch vectors.  Also reports the algorithmic bytes
- * that launch moves (values, column indices, row pointers, one read of the
- * two input vectors, two output vectors). */
+ * timed with one HIP event pair around `reps` back-to-back launches on the
+ * solver stream.  Leaves the solver state unchanged except for scratch
+ * vectors.  Also reports the algorithmic bytes that launch moves (values and
+ * column data of the stored entries, row structure, one read of r, p and x,
+ * writes of p, q and x). */
 int ss_cg_time_spmv(ss_solver *s, int32_t reps, double *ms_per_launch, double *bytes_per_launch);
 
 /* Sizes of the device problem (any pointer may be NULL): matrix_format is

@@ -37,8 +37,7 @@ struct DevState {
 };
 
 constexpr int kBS = 256;    // workgroup size of every kernel
-constexpr int kUI = 4;      // positions per thread per batch in the update / residual kernels
-constexpr int kSellU = 8;   // entries per lane per batch in the SELL-64 SpMV
+constexpr int kUI = 2;      // positions per thread per batch in the update / residual kernels
 constexpr int kNumXcd = 8;  // MI355X: workgroups are dealt round-robin to 8 XCDs
 
 // Grid size for `work` items remapped so that each XCD gets a contiguous range.
@@ -54,15 +53,23 @@ enum { FMT_SELL = 0, FMT_CSR = 1 };
 //    (cpos = first position of each), which spreads the interface chunks
 //    evenly over the persistent workgroups.
 //  CSR tiles: plain CSR cut into row tiles of at most tile_nnz entries.
+//  SELL column positions are stored per chunk either in 16 bits (col16: bit
+//  15 picks one of the chunk's two window bases, bits 0-14 the offset from
+//  it; used when every entry of the chunk falls in the two 32768-position
+//  windows) or as int32 positions (col).
 struct Mat {
     int32_t fmt;
     int32_t nrows;
     int32_t grid;                 // persistent grid of the SpMV kernels (multiple of 8)
-    const int32_t *col;           // column positions (SELL order or CSR order)
+    const int32_t *col;           // column positions (CSR order; SELL: wide chunks)
     const void *val;              // values, double or float, same order
     // SELL-64
     int32_t nchunks;
-    const int32_t *cptr;          // [nchunks+1] start of each chunk in col / val
+    int32_t unroll;               // entries per lane loaded before use: 5, 7, 8 or 9
+    const int32_t *cptr;          // [nchunks+1] start of each chunk in val
+    const int32_t *ccol;          // [nchunks] >= 0: start in col16; < 0: ~start in col
+    const uint16_t *col16;        // window offsets of the narrow chunks
+    const int2 *cbase;            // [nchunks] the two window bases of a narrow chunk
     const int32_t *cpos;          // [nchunks] first row position of each chunk
     const uint8_t *clen;          // [nchunks] entries per row slot of the chunk
     const uint8_t *rlen;          // [nrows] entries of each row (by position)
@@ -109,20 +116,21 @@ template <typename VT, typename XT>
 void launch_spmv_first(hipStream_t s, const Mat &A, const XT *pin, const XT *r, XT *pout, XT *q, Partials P,
                        DevState *state);
 // Later CG steps: each workgroup finishes (r, r) from P.b, records the
-// iteration (workgroup 0), tests for convergence, then pout = r + beta pin,
-// q = A_bd pout, partials -> P.a.
+// iteration (workgroup 0), tests for convergence, applies the previous
+// iteration's x += alpha pin (also when the run stops here), then
+// pout = r + beta pin, q = A_bd pout, partials -> P.a.
 template <typename VT, typename XT>
-void launch_spmv_step(hipStream_t s, const Mat &A, const XT *pin, const XT *r, XT *pout, XT *q, Partials P,
+void launch_spmv_step(hipStream_t s, const Mat &A, const XT *pin, const XT *r, XT *pout, XT *q, XT *x, Partials P,
                       DevState *state, int slot);
 // Interface assembly in place: every copy of an interface node gets the sum of
 // all its copies (ascending sub-domain).
 template <typename XT>
 void launch_iface_sum(hipStream_t s, const Iface &I, XT *q);
-// Each workgroup finishes (p, A p) from P.a -> alpha, then assembly,
-// x += alpha p, r -= alpha q and partials (r, r) -> P.b.
+// Each workgroup finishes (p, A p) from P.a -> alpha (recorded in the state
+// for the next step's x update), then assembly, r -= alpha q and partials
+// (r, r) -> P.b.
 template <typename XT>
-void launch_update(hipStream_t s, const Iface &I, XT *x, const XT *p, XT *r, const XT *q, Partials P,
-                   DevState *state, int slot);
+void launch_update(hipStream_t s, const Iface &I, XT *r, const XT *q, Partials P, DevState *state, int slot);
 // Fresh residual r = b - assemble(q), p0 = r, then one workgroup finishes
 // (r, r) [and (b, b) when `first`] and sets the status.  partial: 2 * I.grid.
 template <typename XT>

@@ -114,19 +114,38 @@ __device__ __forceinline__ double finish_rr(const double *__restrict__ part_b, i
 // Workgroup w (after the XCD remap) owns the stored chunks [w*cpb, (w+1)*cpb)
 // (cpos maps them to row positions); its 4 waves take every 4th chunk.
 
-template <typename VT, typename XT, int MODE>
+// Column position of a 16-bit entry: bit 15 selects the window base.
+__device__ __forceinline__ int narrow_col(uint32_t v, int2 base) { return ((v & 0x8000u) ? base.y : base.x) + (int)(v & 0x7fffu); }
+
+// Columns of entries j .. j+U-1 of a chunk (the last index repeated past L):
+// narrow chunks store 16-bit window offsets, wide ones int32 positions.
+template <int U>
+__device__ __forceinline__ void load_cols(int (&cc)[U], int cb, int2 base, int j0, int L, int lane,
+                                          const int32_t *__restrict__ col, const uint16_t *__restrict__ col16)
+{
+    if (cb >= 0) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) cc[u] = narrow_col(col16[cb + min(j0 + u, L - 1) * 64 + lane], base);
+    } else {
+#pragma unroll
+        for (int u = 0; u < U; ++u) cc[u] = col[~cb + min(j0 + u, L - 1) * 64 + lane];
+    }
+}
+
+template <typename VT, typename XT, int MODE, int U>
 __global__ __launch_bounds__(kBS) void k_spmv_sell(int32_t nrows, int32_t nchunks, const int32_t *__restrict__ cptr,
                                                    const int32_t *__restrict__ cpos,
                                                    const uint8_t *__restrict__ clen,
-                                                   const uint8_t *__restrict__ rlen, const int32_t *__restrict__ col,
+                                                   const uint8_t *__restrict__ rlen, const int32_t *__restrict__ ccol,
+                                                   const int32_t *__restrict__ col, const uint16_t *__restrict__ col16,
+                                                   const int2 *__restrict__ cbase,
                                                    const VT *__restrict__ val, const XT *__restrict__ pin,
                                                    const XT *__restrict__ r, XT *__restrict__ pout,
-                                                   XT *__restrict__ q, double *__restrict__ part_a,
+                                                   XT *__restrict__ q, XT *__restrict__ x, double *__restrict__ part_a,
                                                    const double *__restrict__ part_b, int32_t nb, int32_t slot,
                                                    DevState *__restrict__ st)
 {
     constexpr bool CG = MODE != SPMV_PLAIN;
-    constexpr int U = kSellU;
     constexpr int W = kBS / 64;
     __shared__ double ws[kBS / 64 + 1];
     __shared__ int s_flag;
@@ -140,24 +159,32 @@ __global__ __launch_bounds__(kBS) void k_spmv_sell(int32_t nrows, int32_t nchunk
     // first batch of the first chunk, loaded before beta is known
     int cc[U];
     VT vv[U];
-    int base = 0, L = 0;
+    int base = 0, L = 0, cb = 0, row = 0;
+    int2 wb = make_int2(0, 0);
     if (c < cend) {
         base = cptr[c];
         L = clen[c];
+        cb = ccol[c];
+        if (cb >= 0) wb = cbase[c];
+        row = cpos[c] + lane;
         if (L > 0) {
+            load_cols<U>(cc, cb, wb, 0, L, lane, col, col16);
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const int k = base + min(u, L - 1) * 64 + lane;
-                cc[u] = col[k];
-                vv[u] = val[k];
-            }
+            for (int u = 0; u < U; ++u) vv[u] = val[base + min(u, L - 1) * 64 + lane];
         }
     }
-    double beta = 0.0;
+    double beta = 0.0, alpha = 0.0;
     if (MODE == SPMV_STEP) {
+        alpha = st->alpha;  // x_k = x_{k-1} + alpha p_{k-1}, deferred to here
         bool stop;
         beta = finish_rr(part_b, nb, slot, st, ws, &stop);
-        if (stop) return;
+        if (stop) {
+            for (int c2 = rb * cpb + w; c2 < cend; c2 += W) {
+                const int rr = cpos[c2] + lane;
+                if (rr < nrows) x[rr] = (XT)((double)x[rr] + alpha * (double)pin[rr]);
+            }
+            return;
+        }
     }
 
     double acc = 0.0;
@@ -166,18 +193,17 @@ __global__ __launch_bounds__(kBS) void k_spmv_sell(int32_t nrows, int32_t nchunk
         if (!have) {
             base = cptr[c];
             L = clen[c];
+            cb = ccol[c];
+            if (cb >= 0) wb = cbase[c];
+            row = cpos[c] + lane;
         }
-        const int row = cpos[c] + lane;
         const int len = row < nrows ? (int)rlen[row] : 0;
-        XT s = XT(0);
+        XT sacc = XT(0);
         for (int j0 = 0; j0 < L; j0 += U) {
             if (!have) {
+                load_cols<U>(cc, cb, wb, j0, L, lane, col, col16);
 #pragma unroll
-                for (int u = 0; u < U; ++u) {
-                    const int k = base + min(j0 + u, L - 1) * 64 + lane;
-                    cc[u] = col[k];
-                    vv[u] = val[k];
-                }
+                for (int u = 0; u < U; ++u) vv[u] = val[base + min(j0 + u, L - 1) * 64 + lane];
             }
             have = false;
             XT xx[U];
@@ -185,15 +211,17 @@ __global__ __launch_bounds__(kBS) void k_spmv_sell(int32_t nrows, int32_t nchunk
             for (int u = 0; u < U; ++u) xx[u] = CG ? pupd(r[cc[u]], pin[cc[u]], beta) : pin[cc[u]];
 #pragma unroll
             for (int u = 0; u < U; ++u)
-                if (j0 + u < len) s = s + (XT)vv[u] * xx[u];
+                if (j0 + u < len) sacc = sacc + (XT)vv[u] * xx[u];
         }
         have = false;
         if (row < nrows) {
-            q[row] = s;
+            q[row] = sacc;
             if (CG) {
-                const XT pr = pupd(r[row], pin[row], beta);
+                const XT pold = pin[row];
+                const XT pr = pupd(r[row], pold, beta);
                 pout[row] = pr;
-                acc = acc + (double)pr * (double)s;
+                if (MODE == SPMV_STEP) x[row] = (XT)((double)x[row] + alpha * (double)pold);
+                acc = acc + (double)pr * (double)sacc;
             }
         }
     }
@@ -215,9 +243,9 @@ __global__ __launch_bounds__(kBS) void k_spmv_csr(const int32_t *__restrict__ ro
                                                   const VT *__restrict__ val, const int32_t *__restrict__ tile_row,
                                                   int32_t ntiles, const XT *__restrict__ pin,
                                                   const XT *__restrict__ r, XT *__restrict__ pout,
-                                                  XT *__restrict__ q, double *__restrict__ part_a,
-                                                  const double *__restrict__ part_b, int32_t nb, int32_t slot,
-                                                  DevState *__restrict__ st)
+                                                  XT *__restrict__ q, XT *__restrict__ x,
+                                                  double *__restrict__ part_a, const double *__restrict__ part_b,
+                                                  int32_t nb, int32_t slot, DevState *__restrict__ st)
 {
     constexpr bool CG = MODE != SPMV_PLAIN;
     constexpr int NI = TN / kBS;
@@ -226,15 +254,21 @@ __global__ __launch_bounds__(kBS) void k_spmv_csr(const int32_t *__restrict__ ro
     __shared__ double ws[kBS / 64 + 1];
     __shared__ int s_flag;
     if (CG && !running(st, &s_flag)) return;
-    double beta = 0.0;
-    if (MODE == SPMV_STEP) {
-        bool stop;
-        beta = finish_rr(part_b, nb, slot, st, ws, &stop);
-        if (stop) return;
-    }
     const int rb = xcd_remap(blockIdx.x, gridDim.x);
     const int tpb = (ntiles + (int)gridDim.x - 1) / (int)gridDim.x;
     const int tend = min(rb * tpb + tpb, ntiles);
+    double beta = 0.0, alpha = 0.0;
+    if (MODE == SPMV_STEP) {
+        alpha = st->alpha;  // x_k = x_{k-1} + alpha p_{k-1}, deferred to here
+        bool stop;
+        beta = finish_rr(part_b, nb, slot, st, ws, &stop);
+        if (stop) {
+            if (rb * tpb < tend)
+                for (int row = tile_row[rb * tpb] + (int)threadIdx.x; row < tile_row[tend]; row += kBS)
+                    x[row] = (XT)((double)x[row] + alpha * (double)pin[row]);
+            return;
+        }
+    }
     double acc = 0.0;
     for (int tile = rb * tpb; tile < tend; ++tile) {
         const int r0 = tile_row[tile], r1 = tile_row[tile + 1];
@@ -263,8 +297,10 @@ __global__ __launch_bounds__(kBS) void k_spmv_csr(const int32_t *__restrict__ ro
                 for (int t = a; t < e; ++t) s = s + prod[t];
                 q[row] = s;
                 if (CG) {
-                    const XT pr = pupd(r[row], pin[row], beta);
+                    const XT pold = pin[row];
+                    const XT pr = pupd(r[row], pold, beta);
                     pout[row] = pr;
+                    if (MODE == SPMV_STEP) x[row] = (XT)((double)x[row] + alpha * (double)pold);
                     acc = acc + (double)pr * (double)s;
                 }
             }
@@ -281,8 +317,10 @@ __global__ __launch_bounds__(kBS) void k_spmv_csr(const int32_t *__restrict__ ro
             if (threadIdx.x == 0) {
                 q[r0] = s;
                 if (CG) {
-                    const XT pr = pupd(r[r0], pin[r0], beta);
+                    const XT pold = pin[r0];
+                    const XT pr = pupd(r[r0], pold, beta);
                     pout[r0] = pr;
+                    if (MODE == SPMV_STEP) x[r0] = (XT)((double)x[r0] + alpha * (double)pold);
                     acc = acc + (double)pr * (double)s;
                 }
             }
@@ -316,17 +354,17 @@ __global__ __launch_bounds__(kBS) void k_iface_sum(int32_t ngamma, const int32_t
     for (int u = copy_ptr[g]; u < copy_ptr[g + 1]; ++u) q[copy_pos[u]] = t;
 }
 
-// ---- alpha + assembly + x / r update + (r, r) partials ------------------------
+// ---- alpha + assembly + r update + (r, r) partials ----------------------------
 //
 // Workgroup b (in dispatch order, so the slower interface batches start
-// first) takes positions [b*B, b*B + B), B = kUI * kBS.
+// first) takes positions [b*B, b*B + B), B = kUI * kBS.  x += alpha p is left
+// to the next SpMV step, which reads p anyway.
 
 template <typename XT>
 __global__ __launch_bounds__(kBS) void k_update(int32_t n_loc, int32_t n_own, int32_t n_if,
                                                 const int32_t *__restrict__ pos_grp,
                                                 const int32_t *__restrict__ copy_ptr,
-                                                const int32_t *__restrict__ copy_pos, XT *__restrict__ x,
-                                                const XT *__restrict__ p, XT *__restrict__ r,
+                                                const int32_t *__restrict__ copy_pos, XT *__restrict__ r,
                                                 const XT *__restrict__ q, double *__restrict__ part_b,
                                                 const double *__restrict__ part_a, int32_t na, int32_t slot,
                                                 DevState *__restrict__ st)
@@ -338,13 +376,11 @@ __global__ __launch_bounds__(kBS) void k_update(int32_t n_loc, int32_t n_own, in
     const int b0 = (int)blockIdx.x * B;
     // a full batch of interior positions: operands loaded before alpha is known
     const bool plain = b0 >= n_if && b0 + B <= n_loc;
-    XT xv[kUI], pv[kUI], rv[kUI], qv[kUI];
+    XT rv[kUI], qv[kUI];
     if (plain) {
 #pragma unroll
         for (int i = 0; i < kUI; ++i) {
             const int c = b0 + (int)threadIdx.x + i * kBS;
-            xv[i] = x[c];
-            pv[i] = p[c];
             rv[i] = r[c];
             qv[i] = q[c];
         }
@@ -366,7 +402,6 @@ __global__ __launch_bounds__(kBS) void k_update(int32_t n_loc, int32_t n_own, in
 #pragma unroll
         for (int i = 0; i < kUI; ++i) {
             const int c = b0 + (int)threadIdx.x + i * kBS;
-            x[c] = (XT)((double)xv[i] + alpha * (double)pv[i]);
             const XT rc = (XT)((double)rv[i] - alpha * (double)qv[i]);
             r[c] = rc;
             acc = acc + (double)rc * (double)rc;
@@ -376,7 +411,6 @@ __global__ __launch_bounds__(kBS) void k_update(int32_t n_loc, int32_t n_own, in
             const int c = b0 + (int)threadIdx.x + i * kBS;
             if (c < n_loc) {
                 const XT qc = c >= n_if ? q[c] : assembled(q, pos_grp[c], copy_ptr, copy_pos);
-                x[c] = (XT)((double)x[c] + alpha * (double)p[c]);
                 const XT rc = (XT)((double)r[c] - alpha * (double)qc);
                 r[c] = rc;
                 if (c < n_own || c >= n_if) acc = acc + (double)rc * (double)rc;
@@ -564,10 +598,11 @@ __global__ __launch_bounds__(kBS) void k_grad_vals(Mat A, const int32_t *__restr
         const int row = A.cpos[c] + lane;
         if (row >= A.nrows) return;
         const double li = lambda[l2g[row]];
-        const int base = A.cptr[c], len = A.rlen[row];
+        const int base = A.cptr[c], len = A.rlen[row], cb = A.ccol[c];
         for (int j = 0; j < len; ++j) {
             const int k = base + j * 64 + lane;
-            dvals[nzmap[k]] = -(li * x[l2g[A.col[k]]]);
+            const int cj = cb >= 0 ? narrow_col(A.col16[cb + j * 64 + lane], A.cbase[c]) : A.col[~cb + j * 64 + lane];
+            dvals[nzmap[k]] = -(li * x[l2g[cj]]);
         }
     } else {
         if (t >= A.nrows) return;
@@ -591,20 +626,28 @@ __global__ __launch_bounds__(kBS) void k_set_values(int64_t len, const int32_t *
 inline int nblocks(int64_t n) { return (int)((n + kBS - 1) / kBS); }
 
 template <typename VT, typename XT, int MODE>
-void spmv_dispatch(hipStream_t s, const Mat &A, const XT *pin, const XT *r, XT *pout, XT *q, Partials P,
+void spmv_dispatch(hipStream_t s, const Mat &A, const XT *pin, const XT *r, XT *pout, XT *q, XT *x, Partials P,
                    DevState *st, int slot)
 {
     if (A.nrows == 0) return;
     const dim3 grid(A.grid), block(kBS);
     if (A.fmt == FMT_SELL) {
-        hipLaunchKernelGGL((k_spmv_sell<VT, XT, MODE>), grid, block, 0, s, A.nrows, A.nchunks, A.cptr, A.cpos, A.clen,
-                           A.rlen,
-                           A.col, (const VT *)A.val, pin, r, pout, q, P.a, (const double *)P.b, P.nb, slot, st);
+#define SS_SELL(U)                                                                                               \
+    hipLaunchKernelGGL((k_spmv_sell<VT, XT, MODE, U>), grid, block, 0, s, A.nrows, A.nchunks, A.cptr, A.cpos,    \
+                       A.clen, A.rlen, A.ccol, A.col, A.col16, A.cbase, (const VT *)A.val, pin, r, pout, q, x, P.a, \
+                       (const double *)P.b, P.nb, slot, st)
+        switch (A.unroll) {
+        case 5: SS_SELL(5); break;
+        case 7: SS_SELL(7); break;
+        case 9: SS_SELL(9); break;
+        default: SS_SELL(8); break;
+        }
+#undef SS_SELL
         return;
     }
 #define SS_SPMV(TN)                                                                                              \
     hipLaunchKernelGGL((k_spmv_csr<VT, XT, TN, MODE>), grid, block, 0, s, A.rowptr, A.col, (const VT *)A.val,    \
-                       A.tile_row, A.ntiles, pin, r, pout, q, P.a, (const double *)P.b, P.nb, slot, st)
+                       A.tile_row, A.ntiles, pin, r, pout, q, x, P.a, (const double *)P.b, P.nb, slot, st)
     switch (A.tile_nnz) {
     case 1024: SS_SPMV(1024); break;
     case 4096: SS_SPMV(4096); break;
@@ -632,21 +675,22 @@ void launch_scatter(hipStream_t s, int32_t n, const int32_t *g2own, const XT *sr
 template <typename VT, typename XT>
 void launch_spmv(hipStream_t s, const Mat &A, const XT *x, XT *q)
 {
-    spmv_dispatch<VT, XT, SPMV_PLAIN>(s, A, x, nullptr, nullptr, q, Partials{nullptr, nullptr, 0, 0}, nullptr, 0);
+    spmv_dispatch<VT, XT, SPMV_PLAIN>(s, A, x, nullptr, nullptr, q, nullptr, Partials{nullptr, nullptr, 0, 0}, nullptr,
+                                      0);
 }
 
 template <typename VT, typename XT>
 void launch_spmv_first(hipStream_t s, const Mat &A, const XT *pin, const XT *r, XT *pout, XT *q, Partials P,
                        DevState *st)
 {
-    spmv_dispatch<VT, XT, SPMV_FIRST>(s, A, pin, r, pout, q, P, st, 0);
+    spmv_dispatch<VT, XT, SPMV_FIRST>(s, A, pin, r, pout, q, nullptr, P, st, 0);
 }
 
 template <typename VT, typename XT>
-void launch_spmv_step(hipStream_t s, const Mat &A, const XT *pin, const XT *r, XT *pout, XT *q, Partials P,
+void launch_spmv_step(hipStream_t s, const Mat &A, const XT *pin, const XT *r, XT *pout, XT *q, XT *x, Partials P,
                       DevState *st, int slot)
 {
-    spmv_dispatch<VT, XT, SPMV_STEP>(s, A, pin, r, pout, q, P, st, slot);
+    spmv_dispatch<VT, XT, SPMV_STEP>(s, A, pin, r, pout, q, x, P, st, slot);
 }
 
 template <typename XT>
@@ -658,11 +702,10 @@ void launch_iface_sum(hipStream_t s, const Iface &I, XT *q)
 }
 
 template <typename XT>
-void launch_update(hipStream_t s, const Iface &I, XT *x, const XT *p, XT *r, const XT *q, Partials P, DevState *st,
-                   int slot)
+void launch_update(hipStream_t s, const Iface &I, XT *r, const XT *q, Partials P, DevState *st, int slot)
 {
     hipLaunchKernelGGL(k_update<XT>, dim3(I.grid), dim3(kBS), 0, s, I.n_loc, I.n_own, I.n_if, I.pos_grp,
-                       I.copy_ptr, I.copy_pos, x, p, r, q, P.b, (const double *)P.a, P.na, slot, st);
+                       I.copy_ptr, I.copy_pos, r, q, P.b, (const double *)P.a, P.na, slot, st);
 }
 
 template <typename XT>
@@ -718,11 +761,10 @@ void launch_ir_accumulate(hipStream_t s, int32_t n_loc, double *x64, const XT *d
     template void launch_spmv<XT, XT>(hipStream_t, const Mat &, const XT *, XT *);                                   \
     template void launch_spmv_first<XT, XT>(hipStream_t, const Mat &, const XT *, const XT *, XT *, XT *, Partials,  \
                                             DevState *);                                                             \
-    template void launch_spmv_step<XT, XT>(hipStream_t, const Mat &, const XT *, const XT *, XT *, XT *, Partials,   \
-                                           DevState *, int);                                                         \
+    template void launch_spmv_step<XT, XT>(hipStream_t, const Mat &, const XT *, const XT *, XT *, XT *, XT *,       \
+                                           Partials, DevState *, int);                                               \
     template void launch_iface_sum<XT>(hipStream_t, const Iface &, XT *);                                            \
-    template void launch_update<XT>(hipStream_t, const Iface &, XT *, const XT *, XT *, const XT *, Partials,        \
-                                    DevState *, int);                                                                \
+    template void launch_update<XT>(hipStream_t, const Iface &, XT *, const XT *, Partials, DevState *, int);       \
     template void launch_residual<XT>(hipStream_t, const Iface &, const XT *, const XT *, XT *, XT *, double *,      \
                                       DevState *, bool);                                                             \
     template void launch_ir_prepare<XT>(hipStream_t, const Iface &, const double *, XT *, XT *, XT *, double *,      \

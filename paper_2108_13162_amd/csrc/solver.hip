@@ -31,10 +31,16 @@ struct Layout {
     std::vector<int32_t> l2g, g2own, copy_pos, pos_grp;
     // matrix in device order
     int fmt = FMT_SELL;
-    std::vector<int32_t> col, nzmap;  // storage order (SELL padded: nzmap = -1)
+    std::vector<int32_t> col, nzmap;  // storage order (SELL padded: nzmap = -1); SELL: wide chunks only
+    std::vector<int32_t> ccol;        // SELL: per chunk, start in col16 (>= 0) or ~start in col
+    std::vector<uint16_t> col16;      // SELL: window offsets of the narrow chunks
+    std::vector<int32_t> cbase;       // SELL: two window bases per chunk
+    int64_t col_bytes = 0;            // bytes of the column data of the stored (non-padding) entries
+    bool encode_ok = true;            // column encoding verified
     std::vector<int32_t> cptr, cpos, rowptr, tile_row;
     std::vector<uint8_t> clen, rlen;
     int32_t nchunks = 0, ntiles = 0, tile_nnz = 2048;
+    int32_t unroll = 8;               // SELL: entries per lane loaded before use
     int64_t stored = 0;  // entries incl. padding
 };
 
@@ -132,6 +138,17 @@ void build_matrix(const ss_part *p, Layout &L, int32_t tile_nnz, int32_t force)
             L.cptr[i + 1] = L.cptr[i] + 64 * m;
         }
         L.stored = L.cptr[nch];
+        // the unroll that wastes the fewest loads on the chunk lengths (ties:
+        // the larger); a 7-point stencil gets 7, a 27-point one 9
+        int64_t best = INT64_MAX;
+        for (int32_t u : {9, 8, 7, 5}) {
+            int64_t slots = 0;
+            for (int32_t i = 0; i < nch; ++i) slots += (int64_t)((L.clen[i] + u - 1) / u) * u;
+            if (slots < best) {
+                best = slots;
+                L.unroll = u;
+            }
+        }
         // padding points at a valid position (the row itself, or 0 past the
         // last row) and is masked out by the row length
         L.col.assign((size_t)L.stored, 0);
@@ -151,6 +168,57 @@ void build_matrix(const ss_part *p, Layout &L, int32_t tile_nnz, int32_t force)
                     }
                 }
             }
+        // 16-bit columns for chunks whose entries all fall in two windows of
+        // 32768 positions: one around the chunk's rows, one at the lowest
+        // column outside it (the interface copies an interior chunk reads);
+        // int32 positions otherwise, and for a chunk holding no row past the end
+        std::vector<int32_t> wide;
+        L.ccol.assign(nch, 0);
+        L.cbase.assign(2 * (size_t)nch, 0);
+        L.col_bytes = 0;
+        for (int32_t i = 0; i < nch; ++i) {
+            const int64_t k0 = L.cptr[i], k1 = L.cptr[i + 1];
+            const int32_t b1 = std::max(0, L.cpos[i] - 16384);
+            int32_t lo2 = INT32_MAX, hi2 = -1;
+            for (int64_t k = k0; k < k1; ++k)
+                if (L.col[k] < b1 || L.col[k] > b1 + 32767) {
+                    lo2 = std::min(lo2, L.col[k]);
+                    hi2 = std::max(hi2, L.col[k]);
+                }
+            const bool narrow = L.cpos[i] + 64 <= nl && (hi2 < 0 || hi2 - lo2 <= 32767);
+            const int32_t b2 = hi2 < 0 ? 0 : lo2;
+            int64_t real = 0;
+            for (int32_t lane = 0; lane < 64; ++lane)
+                if (L.cpos[i] + lane < nl) real += L.rlen[L.cpos[i] + lane];
+            L.col_bytes += real * (narrow ? 2 : 4);
+            if (narrow) {
+                L.ccol[i] = (int32_t)L.col16.size();
+                L.cbase[2 * (size_t)i] = b1;
+                L.cbase[2 * (size_t)i + 1] = b2;
+                for (int64_t k = k0; k < k1; ++k) {
+                    const int32_t v = L.col[k];
+                    const bool in1 = v >= b1 && v <= b1 + 32767;
+                    L.col16.push_back(in1 ? (uint16_t)(v - b1) : (uint16_t)(0x8000u | (uint32_t)(v - b2)));
+                }
+            } else {
+                L.ccol[i] = ~(int32_t)wide.size();
+                wide.insert(wide.end(), L.col.begin() + k0, L.col.begin() + k1);
+            }
+        }
+        // every stored column must decode back to itself
+        for (int32_t i = 0; i < nch; ++i)
+            for (int64_t k = L.cptr[i]; k < L.cptr[i + 1]; ++k) {
+                int32_t v;
+                const int64_t off = k - L.cptr[i];
+                if (L.ccol[i] >= 0) {
+                    const uint32_t e = L.col16[(size_t)L.ccol[i] + off];
+                    v = ((e & 0x8000u) ? L.cbase[2 * (size_t)i + 1] : L.cbase[2 * (size_t)i]) + (int32_t)(e & 0x7fffu);
+                } else {
+                    v = wide[(size_t)~L.ccol[i] + off];
+                }
+                if (v != L.col[k] || v < 0 || v >= std::max(nl, 1)) L.encode_ok = false;
+            }
+        L.col.swap(wide);
     } else {
         L.fmt = FMT_CSR;
         L.rowptr.assign(nl + 1, 0);
@@ -158,6 +226,7 @@ void build_matrix(const ss_part *p, Layout &L, int32_t tile_nnz, int32_t force)
         L.stored = L.rowptr[nl];
         L.col.resize((size_t)L.stored);
         L.nzmap.resize((size_t)L.stored);
+        L.col_bytes = 4 * L.stored;
         for (int32_t t = 0; t < nl; ++t) {
             const int32_t u = src_row[t];
             for (int32_t e = p->bd_rowptr[u], k = L.rowptr[t]; e < p->bd_rowptr[u + 1]; ++e, ++k) {
@@ -186,6 +255,7 @@ void build_matrix(const ss_part *p, Layout &L, int32_t tile_nnz, int32_t force)
 
 struct ss_solver {
     int device = 0;
+    int64_t col_bytes = 0;  // column data of the stored entries (2 or 4 B each)
     hipStream_t stream = nullptr;
     hipStream_t cap = nullptr;  // private stream used only to capture graphs
     ss_opts opts{};
@@ -268,8 +338,8 @@ void enqueue_pair_t(ss_solver *s, const ss_solver::Run &R, const Mat &M, hipStre
     const int slot = j & 1;
     XT *pcur = (XT *)(slot ? R.p0 : R.p1);
     XT *pnext = (XT *)(slot ? R.p1 : R.p0);
-    launch_update<XT>(stream, s->ifc, (XT *)R.x, pcur, (XT *)R.r, (XT *)R.q, s->partials(), R.st, slot);
-    launch_spmv_step<XT, XT>(stream, M, pcur, (XT *)R.r, pnext, (XT *)R.q, s->partials(), R.st, slot);
+    launch_update<XT>(stream, s->ifc, (XT *)R.r, (XT *)R.q, s->partials(), R.st, slot);
+    launch_spmv_step<XT, XT>(stream, M, pcur, (XT *)R.r, pnext, (XT *)R.q, (XT *)R.x, s->partials(), R.st, slot);
 }
 
 void enqueue_pair(ss_solver *s, const ss_solver::Run &R, hipStream_t stream, int j)
@@ -418,6 +488,7 @@ int ss_cg_setup(const ss_csr *A, const ss_part *p, const ss_opts *o, void *hip_s
     } catch (const std::bad_alloc &) {
         return fail(SS_ENOMEM, "host allocation failed");
     }
+    if (!L.encode_ok) return fail(SS_EINVAL, "internal: column encoding check failed");
 
     ss_solver *s = new (std::nothrow) ss_solver;
     if (!s) return fail(SS_ENOMEM, "host allocation failed");
@@ -446,6 +517,7 @@ int ss_cg_setup(const ss_csr *A, const ss_part *p, const ss_opts *o, void *hip_s
     s->nnz = p->nnz;
     s->ngamma = (int32_t)p->gamma.size();
     s->stored = L.stored;
+    s->col_bytes = L.col_bytes;
 
     std::vector<double> val_st((size_t)L.stored, 0.0);
     for (int64_t k = 0; k < L.stored; ++k)
@@ -455,6 +527,7 @@ int ss_cg_setup(const ss_csr *A, const ss_part *p, const ss_opts *o, void *hip_s
     M.fmt = L.fmt;
     M.nrows = s->n_loc;
     M.nchunks = L.nchunks;
+    M.unroll = L.unroll;
     M.ntiles = L.ntiles;
     M.tile_nnz = L.tile_nnz;
     const int work = L.fmt == FMT_SELL ? (L.nchunks + kBS / 64 - 1) / (kBS / 64) : L.ntiles;
@@ -467,10 +540,15 @@ int ss_cg_setup(const ss_csr *A, const ss_part *p, const ss_opts *o, void *hip_s
     I.grid = std::max(1, (s->n_loc + kUI * kBS - 1) / (kUI * kBS));
 
     int32_t *d_col = nullptr, *d_cptr = nullptr, *d_cpos = nullptr, *d_rowptr = nullptr, *d_tile = nullptr, *d_pos_grp = nullptr,
-            *d_copy_ptr = nullptr, *d_copy_pos = nullptr;
+            *d_copy_ptr = nullptr, *d_copy_pos = nullptr, *d_ccol = nullptr;
+    uint16_t *d_col16 = nullptr;
+    int32_t *d_cbase = nullptr;
     uint8_t *d_clen = nullptr, *d_rlen = nullptr;
     const size_t nl = (size_t)s->n_loc;
     if ((rc = upload(s, &d_col, L.col.data(), L.col.size())) ||
+        (rc = upload(s, &d_col16, L.col16.data(), L.col16.size())) ||
+        (rc = upload(s, &d_ccol, L.ccol.data(), L.ccol.size())) ||
+        (rc = upload(s, &d_cbase, L.cbase.data(), L.cbase.size())) ||
         (rc = upload(s, &s->nzmap, L.nzmap.data(), L.nzmap.size())) ||
         (rc = upload(s, &s->val, val_st.data(), val_st.size())) ||
         (rc = upload(s, &d_cptr, L.cptr.data(), L.cptr.size())) ||
@@ -498,6 +576,9 @@ int ss_cg_setup(const ss_csr *A, const ss_part *p, const ss_opts *o, void *hip_s
             return bail(rc);
     }
     M.col = d_col;
+    M.col16 = d_col16;
+    M.ccol = d_ccol;
+    M.cbase = reinterpret_cast<const int2 *>(d_cbase);
     M.val = s->val;
     M.cptr = d_cptr;
     M.cpos = d_cpos;
@@ -710,41 +791,36 @@ int ss_cg_time_spmv(ss_solver *s, int32_t reps, double *ms_per_launch, double *b
     SS_HIP(hipMemcpyAsync(P.b, ones.data(), sizeof(double) * (size_t)P.nb, hipMemcpyHostToDevice, s->stream));
     auto launch = [&]() {
         if (f32)
-            launch_spmv_step<float, float>(s->stream, s->mat32, s->p32b, s->r32, s->p32a, s->q32, P, st, 0);
+            launch_spmv_step<float, float>(s->stream, s->mat32, s->p32b, s->r32, s->p32a, s->q32, s->d32, P, st, 0);
         else
-            launch_spmv_step<double, double>(s->stream, s->mat, s->p1, s->r, s->p0, s->q, P, st, 0);
+            launch_spmv_step<double, double>(s->stream, s->mat, s->p1, s->r, s->p0, s->q, s->x, P, st, 0);
     };
     launch();
-    // one event pair around every launch: the sum of the pairs is the kernel
-    // time without the gaps between launches
-    std::vector<hipEvent_t> ev(2 * (size_t)reps, nullptr);
+    // one event pair around `reps` back-to-back launches: the average
+    // includes the (sub-microsecond) dispatch gaps, as inside the CG loop
+    hipEvent_t ev[2] = {nullptr, nullptr};
     for (auto &e : ev)
         if (hipEventCreate(&e) != hipSuccess) {
             for (auto &f : ev)
                 if (f) (void)hipEventDestroy(f);
             return fail(SS_EDEVICE, "event creation failed");
         }
-    for (int32_t k = 0; k < reps; ++k) {
-        (void)hipEventRecord(ev[2 * k], s->stream);
-        launch();
-        (void)hipEventRecord(ev[2 * k + 1], s->stream);
-    }
+    (void)hipEventRecord(ev[0], s->stream);
+    for (int32_t k = 0; k < reps; ++k) launch();
+    (void)hipEventRecord(ev[1], s->stream);
     hipError_t err = hipGetLastError();
-    if (err == hipSuccess) err = hipEventSynchronize(ev.back());
-    double total = 0.0;
-    for (int32_t k = 0; k < reps && err == hipSuccess; ++k) {
-        float ms = 0.0f;
-        err = hipEventElapsedTime(&ms, ev[2 * k], ev[2 * k + 1]);
-        total += ms;
-    }
+    if (err == hipSuccess) err = hipEventSynchronize(ev[1]);
+    float total = 0.0f;
+    if (err == hipSuccess) err = hipEventElapsedTime(&total, ev[0], ev[1]);
     for (auto &e : ev) (void)hipEventDestroy(e);
     if (err != hipSuccess) return fail(SS_EDEVICE, std::string("SpMV timing: ") + hipGetErrorString(err));
     *ms_per_launch = total / reps;
-    // values + column indices, row structure (4 B per row), one read of r and
-    // p_(k-1), writes of p_k and q
+    // values and column data of the stored entries, row structure (4 B per
+    // row), one read of r, p_(k-1) and x, writes of p_k, q and x
     const double sv = f32 ? 4.0 : 8.0;
     if (bytes_per_launch)
-        *bytes_per_launch = (sv + 4.0) * (double)s->nnz + 4.0 * (double)(s->n_loc + 1) + 4.0 * sv * (double)s->n_loc;
+        *bytes_per_launch = sv * (double)s->nnz + (double)s->col_bytes + 4.0 * (double)(s->n_loc + 1) +
+                            6.0 * sv * (double)s->n_loc;
     std::memcpy(s->st_pinned, &saved, sizeof(DevState));
     SS_HIP(hipMemcpyAsync(st, s->st_pinned, sizeof(DevState), hipMemcpyHostToDevice, s->stream));
     SS_HIP(hipStreamSynchronize(s->stream));

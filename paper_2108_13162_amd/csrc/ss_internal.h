@@ -5,7 +5,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/ss.h"
+#include "ss.h"
 
 namespace ss {
 
