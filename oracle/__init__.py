@@ -43,6 +43,7 @@ def lib():
         L.orc_cg.argtypes = [i64, P, P, P, P, P, dbl, i32, P, P, P, P]
         L.orc_ss_cg.argtypes = [P, i64, P, P, P, P, P, dbl, i32, P, P, P, P]
         L.orc_ss_ir.argtypes = [P, i64, P, P, P, P, P, dbl, i32, dbl, i32, i32, P, P, P, P]
+        L.orc_ss_ru.argtypes = [P, i64, P, P, P, P, P, dbl, i32, dbl, i32, P, P, P, P]
         L.orc_grad_vals.argtypes = [i64, P, P, P, P, P]
         L.orc_chol_solve.argtypes = [i64, P, P, P]
         _lib = L
@@ -95,7 +96,7 @@ class Result:
     relres: float
     true_relres: float
     hist: Optional[np.ndarray] = None
-    outer: int = 0
+    outer: int = 0       # IR: outer corrections; RU: residual replacements inside the iteration
 
 
 # ----------------------------------------------------------------------------
@@ -200,6 +201,19 @@ def ss_ir(A, sd: SubDomains, b, x0=None, tol: float = 1e-10, maxit: int = 100000
                          tol, maxit, inner_tol, inner_maxit, max_outer, C.byref(it), C.byref(outer),
                          C.byref(rel), C.byref(tr))
     return x, Result(st, it.value, rel.value, tr.value, None, outer.value)
+
+
+def ss_ru(A, sd: SubDomains, b, x0=None, tol: float = 1e-10, maxit: int = 100000, delta: float = 0.1,
+          check_every: int = 32) -> tuple:
+    """FP32 CG with FP64 residual replacement (see orc_ss_ru); Result.outer =
+    replacements made inside the iteration."""
+    S = _Sub(sd, A.val)
+    b = _f64(b)
+    x = np.zeros(A.n) if x0 is None else _f64(x0).copy()
+    it, nref, rel, tr = C.c_int32(), C.c_int32(), C.c_double(), C.c_double()
+    st = lib().orc_ss_ru(S.ref(), A.n, _p(_i32(A.rowptr)), _p(_i32(A.colidx)), _p(_f64(A.val)), _p(b), _p(x),
+                         tol, maxit, delta, check_every, C.byref(it), C.byref(nref), C.byref(rel), C.byref(tr))
+    return x, Result(st, it.value, rel.value, tr.value, None, nref.value)
 
 
 def grad_vals(A, lam, x) -> np.ndarray:

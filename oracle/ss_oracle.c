@@ -372,6 +372,107 @@ out:
 }
 
 /* ---------------------------------------------------------------------- */
+/* FP32 CG with FP64 residual replacement ("reliable updates", Sleijpen &  */
+/* van der Vorst): CG (Algorithm 3) runs on fl32(A) with FP32 vectors, FP64 */
+/* dots and scalars, and accumulates its solution change in d.  Every m    */
+/* iterations after a (re)start, if the recursive ||r|| has dropped to     */
+/* delta times the last true residual, the correction is folded in,        */
+/* x += d, d = 0, and r is replaced by fl32(b - A x) computed in FP64 with  */
+/* the FP64 values; the search direction p is kept and CG continues with   */
+/* (r, r) of the new r.  When the recursion meets the tolerance (or the    */
+/* iteration limit) the same replacement is made and the stopping test is  */
+/* taken on the true residual; CG restarts from it (p = r) if that is still */
+/* above the tolerance.  Stopping rule as in cg_core; refreshes counts the */
+/* replacements made inside the iteration.                                 */
+/* ---------------------------------------------------------------------- */
+
+int orc_ss_ru(const orc_sub *S, int64_t n, const int32_t *rowptr, const int32_t *colidx,
+              const double *val, const double *b, double *x, double tol, int32_t maxit,
+              double delta, int32_t m, int32_t *iters, int32_t *refreshes, double *relres, double *true_rr)
+{
+    const int64_t nl = S->n_loc > 0 ? S->n_loc : 1;
+    double *bl = malloc(sizeof(double) * nl), *xl = malloc(sizeof(double) * nl), *r64 = malloc(sizeof(double) * nl);
+    float *d = malloc(sizeof(float) * nl), *r = malloc(sizeof(float) * nl), *p = malloc(sizeof(float) * nl),
+          *q = malloc(sizeof(float) * nl);
+    int st = ORC_OK;
+    int32_t k = 0, nref = 0;
+    double rr64 = 0.0;
+    if (!bl || !xl || !r64 || !d || !r || !p || !q || m < 1) { st = m < 1 ? ORC_EINVAL : ORC_ENOMEM; goto out; }
+    gather(S, b, bl);
+    gather(S, x, xl);
+    const double bb = orc_owned_dot(S->P, S->sub_off, S->n_int, S->n_own, bl, bl);
+    if (!isfinite(bb)) { st = ORC_EBREAKDOWN; goto out; }
+    if (bb == 0.0) { for (int64_t i = 0; i < S->n_loc; ++i) xl[i] = 0.0; *relres = 0.0; goto out; }
+    const double stop = tol * sqrt(bb);
+    for (int64_t i = 0; i < S->n_loc; ++i) d[i] = 0.0f;
+    for (;;) {
+        /* fold the correction in and take the true residual (FP64) */
+        for (int64_t i = 0; i < S->n_loc; ++i) {
+            xl[i] = xl[i] + (double)d[i];
+            d[i] = 0.0f;
+        }
+        orc_ss_spmv(S, xl, r64);
+        for (int64_t i = 0; i < S->n_loc; ++i) r64[i] = bl[i] - r64[i];
+        rr64 = orc_owned_dot(S->P, S->sub_off, S->n_int, S->n_own, r64, r64);
+        if (!isfinite(rr64)) { st = ORC_EBREAKDOWN; goto out; }
+        if (sqrt(rr64) <= stop) { st = ORC_OK; break; }
+        if (k >= maxit) { st = ORC_NOT_CONVERGED; break; }
+        /* (re)start: p = r */
+        for (int64_t i = 0; i < S->n_loc; ++i) {
+            r[i] = (float)r64[i];
+            p[i] = r[i];
+        }
+        double rr = orc_owned_dot_f32(S->P, S->sub_off, S->n_int, S->n_own, r, r);
+        double rref = sqrt(rr64);
+        const int32_t k0 = k;
+        for (;;) {
+            ss_spmv_f32(S, p, q);
+            const double pq = orc_owned_dot_f32(S->P, S->sub_off, S->n_int, S->n_own, p, q);
+            if (!(pq > 0.0) || !isfinite(pq)) { st = ORC_EBREAKDOWN; goto out; }
+            const double alpha = rr / pq;
+            for (int64_t i = 0; i < S->n_loc; ++i) {
+                d[i] = (float)((double)d[i] + alpha * (double)p[i]);
+                r[i] = (float)((double)r[i] - alpha * (double)q[i]);
+            }
+            const double rr1 = orc_owned_dot_f32(S->P, S->sub_off, S->n_int, S->n_own, r, r);
+            ++k;
+            if (!isfinite(rr1)) { st = ORC_EBREAKDOWN; goto out; }
+            if (sqrt(rr1) <= stop || k >= maxit) break; /* to the true-residual test */
+            const double beta = rr1 / rr;
+            for (int64_t i = 0; i < S->n_loc; ++i) p[i] = (float)((double)r[i] + beta * (double)p[i]);
+            rr = rr1;
+            if ((k - k0) % m == 0 && sqrt(rr) <= delta * rref) {
+                /* residual replacement, p kept */
+                for (int64_t i = 0; i < S->n_loc; ++i) {
+                    xl[i] = xl[i] + (double)d[i];
+                    d[i] = 0.0f;
+                }
+                orc_ss_spmv(S, xl, r64);
+                for (int64_t i = 0; i < S->n_loc; ++i) r64[i] = bl[i] - r64[i];
+                rr64 = orc_owned_dot(S->P, S->sub_off, S->n_int, S->n_own, r64, r64);
+                if (!isfinite(rr64)) { st = ORC_EBREAKDOWN; goto out; }
+                ++nref;
+                if (sqrt(rr64) <= stop) { st = ORC_OK; goto done; }
+                for (int64_t i = 0; i < S->n_loc; ++i) r[i] = (float)r64[i];
+                rr = orc_owned_dot_f32(S->P, S->sub_off, S->n_int, S->n_own, r, r);
+                rref = sqrt(rr64);
+            }
+        }
+    }
+done:
+    *relres = sqrt(rr64 / bb);
+out:
+    if (st != ORC_ENOMEM && st != ORC_EINVAL) {
+        scatter_owned(S, xl, x);
+        *true_rr = true_relres(n, rowptr, colidx, val, b, x);
+    }
+    *iters = k;
+    *refreshes = nref;
+    free(bl); free(xl); free(r64); free(d); free(r); free(p); free(q);
+    return st;
+}
+
+/* ---------------------------------------------------------------------- */
 /* Adjoint gradient on the stored pattern: for x = A^{-1} b and            */
 /* lambda = A^{-1} dL/dx, dL/da_ij = -lambda_i x_j for every stored entry  */
 /* taken as an independent parameter.                                      */

@@ -465,6 +465,64 @@ def test_ir_reaches_fp64_accuracy():
     assert np.max(np.abs(b - b.astype(np.float32))) > 1e-10
 
 
+def _ru_case():
+    M = 12
+    A = diffusion3d_lognormal(M, seed=3, sigma=0.5)
+    b = uniform_rhs(A.n, 104)
+    sd = O.split(A.rowptr, A.colidx, O.box_partition((M, M, M), (2, 2, 1)), 4)
+    return A, b, sd
+
+
+def test_ru_reaches_fp64_accuracy_near_fp64_iteration_count():
+    # FP32 CG with FP64 residual replacement: the true residual (numpy's own
+    # matvec) meets the tolerance, the error is within the FP64 bound, and
+    # because the search direction survives every replacement the iteration
+    # count stays near FP64 CG's (a restart-based refinement needs clearly more)
+    A, b, sd = _ru_case()
+    x, res = O.ss_ru(A, sd, b, tol=1e-10, delta=0.1, check_every=8)
+    D = A.to_dense()
+    true = np.linalg.norm(b - D @ x) / np.linalg.norm(b)
+    assert res.status == O.OK and true <= 1e-10 and res.outer >= 1
+    assert abs(res.true_relres - true) <= 1e-3 * true
+    ref = np.linalg.solve(D, b)
+    kappa = np.linalg.cond(D)
+    assert np.linalg.norm(x - ref) <= 2 * kappa * 1e-10 * np.linalg.norm(ref)
+    _, r64 = O.ss_cg(A, sd, b, tol=1e-10)
+    _, rir = O.ss_ir(A, sd, b, tol=1e-10, inner_tol=1e-6)
+    assert res.iterations <= 1.05 * r64.iterations + 3, (res.iterations, r64.iterations)
+    assert rir.iterations > 1.1 * res.iterations, (rir.iterations, res.iterations)
+
+
+def test_ru_replacement_matters():
+    # with no replacement inside the iteration (delta = 0) only the final
+    # true-residual check corrects the FP32 drift: it needs restarts and more
+    # iterations, and still ends at the tolerance
+    A, b, sd = _ru_case()
+    x0, r0 = O.ss_ru(A, sd, b, tol=1e-10, delta=0.0, check_every=8)
+    x1, r1 = O.ss_ru(A, sd, b, tol=1e-10, delta=0.1, check_every=8)
+    assert r0.status == O.OK and r0.outer == 0 and r0.true_relres <= 1e-10
+    assert r1.outer > 0 and r0.iterations > r1.iterations
+    # the replacement test only runs every check_every iterations
+    x2, r2 = O.ss_ru(A, sd, b, tol=1e-10, delta=0.1, check_every=10 ** 6)
+    assert r2.outer == 0 and r2.iterations == r0.iterations and np.array_equal(x2, x0)
+
+
+def test_ru_edge_cases():
+    A, b, sd = _ru_case()
+    x, r = O.ss_ru(A, sd, np.zeros(A.n), x0=np.ones(A.n))
+    assert r.status == O.OK and r.iterations == 0 and not x.any()
+    x, r = O.ss_ru(A, sd, b, maxit=0)
+    assert r.status == O.NOT_CONVERGED and r.iterations == 0
+    x, r = O.ss_ru(A, sd, b, maxit=5)
+    assert r.status == O.NOT_CONVERGED and r.iterations == 5
+    bn = b.copy()
+    bn[3] = np.nan
+    _, r = O.ss_ru(A, sd, bn)
+    assert r.status == O.EBREAKDOWN
+    _, r = O.ss_ru(A, sd, b, check_every=0)
+    assert r.status == O.EINVAL
+
+
 # ----------------------------------------------------------------------------
 # adjoint gradient: finite differences with symmetric perturbations
 # ----------------------------------------------------------------------------
