@@ -15,7 +15,9 @@ The line also carries "variants", each timed on the same GPU after the main
 measurement (time to relative residual 1e-10, inputs resident):
   mixed    -- Q1 hexahedral stiffness on 96^3 nodes (884,736 unknowns,
               23.4M entries), 16 weighted-RCB sub-domains: plain FP64 CG vs
-              FP32 values/vectors with FP64 iterative refinement;
+              FP32 values/vectors with FP64 iterative refinement (restarted
+              inner solves) and with FP64 residual replacement (reliable
+              updates, search direction kept);
   batched  -- 256 lognormal 5-point systems on 32^2..256^2 grids, 4
               right-hand sides each: one batched solve (autotuned launch
               shape) vs the 1024 (system, rhs) solves one by one;
@@ -117,7 +119,7 @@ def variant_mixed(ss, torch, reps: int, tol: float) -> dict:
     b = torch.tensor(w.b, dtype=torch.float64, device="cuda")
     bn = float(torch.linalg.norm(b))
     out, xs, s64 = {}, {}, None
-    for name, prec in (("fp64", ss.SS_FP64), ("fp32_ir", ss.SS_FP32_IR)):
+    for name, prec in (("fp64", ss.SS_FP64), ("fp32_ir", ss.SS_FP32_IR), ("fp32_ru", ss.SS_FP32_RU)):
         s = ss.ss_cg_setup(A, part, ss.default_opts(precision=prec))
         x = torch.zeros_like(b)
 
@@ -131,14 +133,17 @@ def variant_mixed(ss, torch, reps: int, tol: float) -> dict:
         true = float(torch.linalg.norm(b - ss.ss_cg_apply(s64, x))) / bn
         out[name] = {"ms": round(ms, 3), "status": r.status, "iterations": r.iterations,
                      "outer_iterations": r.outer_iterations, "true_relres": true}
+        if prec == ss.SS_FP32_RU:
+            out[name]["residual_replacements"] = out[name].pop("outer_iterations")
         xs[name] = x.clone()
         print(f"# mixed/{name}: {ms:.3f} ms, {r.iterations} iterations ({r.outer_iterations} outer), "
               f"true relres {true:.2e}", file=sys.stderr, flush=True)
-    out["speedup_fp32_ir_over_fp64"] = round(out["fp64"]["ms"] / out["fp32_ir"]["ms"], 3)
-    out["fp32_ir_vs_fp64_solution"] = float(torch.linalg.norm(xs["fp32_ir"] - xs["fp64"]) /
-                                            torch.linalg.norm(xs["fp64"]))
+    for v in ("fp32_ir", "fp32_ru"):
+        out[f"speedup_{v}_over_fp64"] = round(out["fp64"]["ms"] / out[v]["ms"], 3)
+        out[f"{v}_vs_fp64_solution"] = float(torch.linalg.norm(xs[v] - xs["fp64"]) / torch.linalg.norm(xs["fp64"]))
     out["workload"] = w.name
     out["inner_tol"] = ss.default_opts().inner_tol
+    out["ru_delta"] = ss.default_opts().ru_delta
     return out
 
 

@@ -139,7 +139,7 @@ void ss_part_destroy(ss_part *p);
 typedef void *(*ss_alloc_fn)(void *ctx, size_t bytes); /* returns device memory or NULL */
 typedef void (*ss_free_fn)(void *ctx, void *ptr);
 
-enum { SS_FP64 = 0, SS_FP32_IR = 1 };
+enum { SS_FP64 = 0, SS_FP32_IR = 1, SS_FP32_RU = 2 };
 
 /* Device storage of the block-diagonal matrix of all local matrices. */
 enum {
@@ -149,10 +149,14 @@ enum {
 };
 
 typedef struct {
-    int32_t precision;   /* SS_FP64, or SS_FP32_IR: FP32 values and vectors in
+    int32_t precision;   /* SS_FP64; SS_FP32_IR: FP32 values and vectors in
                             the inner CG, FP64 dots, FP64 residuals and an
-                            outer iterative-refinement loop                    */
+                            outer iterative-refinement loop; SS_FP32_RU: the
+                            same FP32 CG with FP64 residual replacement that
+                            keeps the search direction                         */
     double inner_tol;    /* IR: inner relative tolerance, in (0, 1); 1e-6     */
+    double ru_delta;     /* RU: replace the residual once the recursive one
+                            has dropped by this factor, in [0, 1]; 0.1        */
     int32_t inner_maxit; /* IR: inner iteration cap (<= 0: unlimited)          */
     int32_t max_outer;   /* IR: outer iteration cap (<= 0: 50)                 */
     int32_t check_every; /* CG iterations between host polls (<= 0: 32)        */
@@ -203,6 +207,15 @@ int ss_cg_setup(const ss_csr *A, const ss_part *p, const ss_opts *o, void *hip_s
  * on the FP32 values with FP32 vectors for r / ||r|| (FP64 dots and scalars)
  * until its residual drops by inner_tol (or inner_maxit iterations), then
  * x += ||r|| d; at most max_outer corrections (SS_NOT_CONVERGED beyond).
+ * With precision SS_FP32_RU, CG runs on the FP32 values with FP32 vectors
+ * (FP64 dots and scalars) and accumulates its solution change d; at the end
+ * of every polled chunk of check_every iterations, if the recursive ||r||
+ * has dropped to ru_delta times the last true residual, x += d (FP64), the
+ * residual is replaced by b - A x computed with the FP64 values and CG
+ * continues with the same search direction; the stopping test is taken on
+ * that true residual (and, when the recursion meets it, on a final
+ * replacement, restarting from it if needed).  outer_iterations reports the
+ * replacements made inside the iteration.
  * res (host, may be NULL) receives the result (iterations = all inner
  * iterations for SS_FP32_IR); hist_host (host, may be NULL, capacity
  * maxit+1) receives ||r_k||/||b|| for k = 0..iterations (FP32_IR: inner

@@ -25,7 +25,7 @@ LIB_PATH = os.path.join(HERE, "libss.so")
 
 SS_OK, SS_NOT_CONVERGED, SS_EINVAL, SS_ENOMEM, SS_EDEVICE, SS_EBREAKDOWN, SS_EUNSUPPORTED = 0, 1, -1, -2, -3, -4, -5
 SS_PART_BOX, SS_PART_RCB, SS_PART_USER = 0, 1, 2
-SS_FP64, SS_FP32_IR = 0, 1
+SS_FP64, SS_FP32_IR, SS_FP32_RU = 0, 1, 2
 SS_MAT_AUTO, SS_MAT_SELL, SS_MAT_CSR = 0, 1, 2
 
 _ALLOC_T = C.CFUNCTYPE(C.c_void_p, C.c_void_p, C.c_size_t)
@@ -38,7 +38,8 @@ class ss_csr(C.Structure):
 
 
 class ss_opts(C.Structure):
-    _fields_ = [("precision", C.c_int32), ("inner_tol", C.c_double), ("inner_maxit", C.c_int32),
+    _fields_ = [("precision", C.c_int32), ("inner_tol", C.c_double), ("ru_delta", C.c_double),
+                ("inner_maxit", C.c_int32),
                 ("max_outer", C.c_int32), ("check_every", C.c_int32), ("use_graph", C.c_int32),
                 ("tile_nnz", C.c_int32), ("matrix_format", C.c_int32), ("spmv_grid", C.c_int32),
                 ("alloc", _ALLOC_T), ("free", _FREE_T),

@@ -34,6 +34,11 @@ struct DevState {
     int32_t status;    // ST_*
     int32_t hist_cap;  // entries of hist
     double *hist;      // ||r_k|| / ||b||, device, or nullptr
+    // residual replacement (FP32 CG of an SS_FP32_RU solve)
+    double rref;       // ||b - A x|| at the last replacement (or start)
+    double delta;      // replace once sqrt(rr) <= delta * rref
+    int32_t refresh;   // decision of the current chunk end
+    int32_t nrefresh;  // replacements made
 };
 
 constexpr int kBS = 256;    // workgroup size of every kernel
@@ -149,6 +154,24 @@ void launch_ir_prepare(hipStream_t s, const Iface &I, const double *r64, XT *rin
 template <typename XT>
 void launch_ir_accumulate(hipStream_t s, int32_t n_loc, double *x64, const XT *d, const DevState *inner,
                           DevState *outer);
+
+// FP32 CG with FP64 residual replacement.  Start (after a fresh FP64
+// residual r64 in the outer state): rin = (XT) r64, d = 0, inner state from
+// the outer one (unscaled: same stop and (b, b)), rref = ||r64||.
+template <typename XT>
+void launch_ru_start(hipStream_t s, const Iface &I, const double *r64, XT *rin, XT *d, double *partial,
+                     const DevState *outer, DevState *inner, double delta);
+// Chunk end (graph-captured): decide whether to replace; if so x64 += d,
+// d = 0, q64 = A x64 (FP64 values), r64 = b - assemble(q64), rin = (XT) r64,
+// (rin, rin) -> inner slot 0, true residual -> stopping test (CONVERGED ends
+// the run).  Every launch returns at once when no replacement is due.
+template <typename XT>
+void launch_ru_refresh(hipStream_t s, const Iface &I, const Mat &A64, double *x64, XT *d, const double *b64,
+                       double *q64, double *r64, XT *rin, double *partial, DevState *inner, DevState *outer);
+// After the run: x64 += d, d = 0, iteration count to the outer state, a
+// breakdown propagated.
+template <typename XT>
+void launch_ru_fold(hipStream_t s, int32_t n_loc, double *x64, XT *d, const DevState *inner, DevState *outer);
 
 // Adjoint gradient on the pattern: dvals[nzmap[k]] = -lambda[row] x[col] for
 // every stored (non-padding) entry k of A in device order.

@@ -143,12 +143,13 @@ __global__ __launch_bounds__(kBS) void k_spmv_sell(int32_t nrows, int32_t nchunk
                                                    const XT *__restrict__ r, XT *__restrict__ pout,
                                                    XT *__restrict__ q, XT *__restrict__ x, double *__restrict__ part_a,
                                                    const double *__restrict__ part_b, int32_t nb, int32_t slot,
-                                                   DevState *__restrict__ st)
+                                                   DevState *__restrict__ st, const int32_t *__restrict__ gate)
 {
     constexpr bool CG = MODE != SPMV_PLAIN;
     constexpr int W = kBS / 64;
     __shared__ double ws[kBS / 64 + 1];
     __shared__ int s_flag;
+    if (gate && dev::flag_load(gate) == 0) return;
     if (CG && !running(st, &s_flag)) return;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int rb = xcd_remap(blockIdx.x, gridDim.x);
@@ -245,7 +246,8 @@ __global__ __launch_bounds__(kBS) void k_spmv_csr(const int32_t *__restrict__ ro
                                                   const XT *__restrict__ r, XT *__restrict__ pout,
                                                   XT *__restrict__ q, XT *__restrict__ x,
                                                   double *__restrict__ part_a, const double *__restrict__ part_b,
-                                                  int32_t nb, int32_t slot, DevState *__restrict__ st)
+                                                  int32_t nb, int32_t slot, DevState *__restrict__ st,
+                                                  const int32_t *__restrict__ gate)
 {
     constexpr bool CG = MODE != SPMV_PLAIN;
     constexpr int NI = TN / kBS;
@@ -253,6 +255,7 @@ __global__ __launch_bounds__(kBS) void k_spmv_csr(const int32_t *__restrict__ ro
     __shared__ XT wsx[kBS / 64 + 1];
     __shared__ double ws[kBS / 64 + 1];
     __shared__ int s_flag;
+    if (gate && dev::flag_load(gate) == 0) return;
     if (CG && !running(st, &s_flag)) return;
     const int rb = xcd_remap(blockIdx.x, gridDim.x);
     const int tpb = (ntiles + (int)gridDim.x - 1) / (int)gridDim.x;
@@ -564,6 +567,151 @@ __global__ __launch_bounds__(kBS) void k_ir_accumulate(int32_t n_loc, double *__
     x64[c] = x64[c] + sc * (double)d[c];
 }
 
+// ---- FP32 CG with FP64 residual replacement ----------------------------------
+
+template <typename XT>
+__global__ __launch_bounds__(kBS) void k_ru_start(int32_t n_loc, int32_t n_own, int32_t n_if,
+                                                  const double *__restrict__ r64, XT *__restrict__ rin,
+                                                  XT *__restrict__ d, double *__restrict__ partial)
+{
+    constexpr int B = kUI * kBS;
+    __shared__ double ws[kBS / 64 + 1];
+    const int b0 = (int)blockIdx.x * B;
+    double acc = 0.0;
+    for (int i = 0; i < kUI; ++i) {
+        const int c = b0 + (int)threadIdx.x + i * kBS;
+        if (c < n_loc) {
+            const XT v = (XT)r64[c];
+            rin[c] = v;
+            d[c] = XT(0);
+            if (c < n_own || c >= n_if) acc = acc + (double)v * (double)v;
+        }
+    }
+    const double part = block_sum_all(acc, ws);
+    if (threadIdx.x == 0) partial[blockIdx.x] = part;
+}
+
+__global__ __launch_bounds__(kBS) void k_ru_start_finish(DevState *in, const DevState *outer, const double *partial,
+                                                         int n, double delta)
+{
+    __shared__ double ws[kBS / 64 + 1];
+    const double rr = sum_partials_all(partial, n, ws);
+    if (threadIdx.x != 0) return;
+    const int k = outer->iter_last;
+    in->rr[0] = rr;
+    in->iter[0] = k;
+    in->rr_last = rr;
+    in->iter_last = k;
+    in->bb = outer->bb;
+    in->tol = outer->tol;
+    in->stop = outer->stop;
+    in->kmax = outer->kmax;
+    in->hist = outer->hist;
+    in->hist_cap = outer->hist_cap;
+    in->rref = sqrt(outer->rr_last);
+    in->delta = delta;
+    in->refresh = 0;
+    store_status(in, isfinite(rr) ? ST_RUNNING : ST_BREAKDOWN);
+}
+
+// Chunk end: replace now?  (After an even number of steps the current
+// (r, r) and iteration count are in slot 0.)
+__global__ void k_ru_check(DevState *in)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const bool now = load_status(in) == ST_RUNNING && sqrt(in->rr[0]) <= in->delta * in->rref;
+    dev::flag_store(&in->refresh, now ? 1 : 0);
+}
+
+template <typename XT>
+__global__ __launch_bounds__(kBS) void k_ru_fold_gated(int32_t n_loc, double *__restrict__ x64, XT *__restrict__ d,
+                                                       const DevState *__restrict__ in)
+{
+    if (dev::flag_load(&in->refresh) == 0) return;
+    const int c = blockIdx.x * kBS + threadIdx.x;
+    if (c >= n_loc) return;
+    x64[c] = x64[c] + (double)d[c];
+    d[c] = XT(0);
+}
+
+template <typename XT>
+__global__ __launch_bounds__(kBS) void k_ru_residual(int32_t n_loc, int32_t n_own, int32_t n_if,
+                                                     const int32_t *__restrict__ pos_grp,
+                                                     const int32_t *__restrict__ copy_ptr,
+                                                     const int32_t *__restrict__ copy_pos,
+                                                     const double *__restrict__ b, const double *__restrict__ q,
+                                                     double *__restrict__ r64, XT *__restrict__ rin,
+                                                     double *__restrict__ partial, const DevState *__restrict__ in)
+{
+    constexpr int B = kUI * kBS;
+    __shared__ double ws[kBS / 64 + 1];
+    if (dev::flag_load(&in->refresh) == 0) return;
+    const int b0 = (int)blockIdx.x * B;
+    double a64 = 0.0, a32 = 0.0;
+    for (int i = 0; i < kUI; ++i) {
+        const int c = b0 + (int)threadIdx.x + i * kBS;
+        if (c < n_loc) {
+            const double qc = c >= n_if ? q[c] : assembled(q, pos_grp[c], copy_ptr, copy_pos);
+            const double rc = b[c] - qc;
+            r64[c] = rc;
+            const XT v = (XT)rc;
+            rin[c] = v;
+            if (c < n_own || c >= n_if) {
+                a64 = a64 + rc * rc;
+                a32 = a32 + (double)v * (double)v;
+            }
+        }
+    }
+    const double p64 = block_sum_all(a64, ws);
+    const double p32 = block_sum_all(a32, ws);
+    if (threadIdx.x == 0) {
+        partial[blockIdx.x] = p64;
+        partial[gridDim.x + blockIdx.x] = p32;
+    }
+}
+
+// The true residual decides: converged, or CG goes on from the new r with
+// the same search direction.
+__global__ __launch_bounds__(kBS) void k_ru_refresh_finish(DevState *in, DevState *outer, const double *partial, int n)
+{
+    __shared__ double ws[kBS / 64 + 1];
+    __shared__ int32_t go;
+    if (threadIdx.x == 0) go = dev::flag_load(&in->refresh);
+    __syncthreads();
+    if (go == 0) return;
+    const double rr64 = sum_partials_all(partial, n, ws);
+    const double rr32 = sum_partials_all(partial + n, n, ws);
+    if (threadIdx.x != 0) return;
+    const int k = in->iter[0];
+    outer->rr_last = rr64;
+    in->nrefresh = in->nrefresh + 1;
+    if (in->hist && k < in->hist_cap) in->hist[k] = sqrt(rr64 / in->bb);
+    if (!isfinite(rr64) || !isfinite(rr32)) {
+        store_status(in, ST_BREAKDOWN);
+    } else if (sqrt(rr64) <= in->stop) {
+        store_status(in, ST_CONVERGED);
+    } else {
+        in->rr[0] = rr32;
+        in->rr_last = rr32;
+        in->rref = sqrt(rr64);
+    }
+}
+
+template <typename XT>
+__global__ __launch_bounds__(kBS) void k_ru_fold(int32_t n_loc, double *__restrict__ x64, XT *__restrict__ d,
+                                                 const DevState *__restrict__ in, DevState *__restrict__ outer)
+{
+    const int c = blockIdx.x * kBS + threadIdx.x;
+    const bool broke = in->status == ST_BREAKDOWN;
+    if (c == 0) {
+        outer->iter_last = in->iter_last;
+        if (broke) store_status(outer, ST_BREAKDOWN);
+    }
+    if (broke || c >= n_loc) return;
+    x64[c] = x64[c] + (double)d[c];
+    d[c] = XT(0);
+}
+
 // ---- gathers, scatters, gradient -------------------------------------------
 
 template <typename XT>
@@ -627,7 +775,7 @@ inline int nblocks(int64_t n) { return (int)((n + kBS - 1) / kBS); }
 
 template <typename VT, typename XT, int MODE>
 void spmv_dispatch(hipStream_t s, const Mat &A, const XT *pin, const XT *r, XT *pout, XT *q, XT *x, Partials P,
-                   DevState *st, int slot)
+                   DevState *st, int slot, const int32_t *gate = nullptr)
 {
     if (A.nrows == 0) return;
     const dim3 grid(A.grid), block(kBS);
@@ -635,7 +783,7 @@ void spmv_dispatch(hipStream_t s, const Mat &A, const XT *pin, const XT *r, XT *
 #define SS_SELL(U)                                                                                               \
     hipLaunchKernelGGL((k_spmv_sell<VT, XT, MODE, U>), grid, block, 0, s, A.nrows, A.nchunks, A.cptr, A.cpos,    \
                        A.clen, A.rlen, A.ccol, A.col, A.col16, A.cbase, (const VT *)A.val, pin, r, pout, q, x, P.a, \
-                       (const double *)P.b, P.nb, slot, st)
+                       (const double *)P.b, P.nb, slot, st, gate)
         switch (A.unroll) {
         case 5: SS_SELL(5); break;
         case 7: SS_SELL(7); break;
@@ -647,7 +795,7 @@ void spmv_dispatch(hipStream_t s, const Mat &A, const XT *pin, const XT *r, XT *
     }
 #define SS_SPMV(TN)                                                                                              \
     hipLaunchKernelGGL((k_spmv_csr<VT, XT, TN, MODE>), grid, block, 0, s, A.rowptr, A.col, (const VT *)A.val,    \
-                       A.tile_row, A.ntiles, pin, r, pout, q, x, P.a, (const double *)P.b, P.nb, slot, st)
+                       A.tile_row, A.ntiles, pin, r, pout, q, x, P.a, (const double *)P.b, P.nb, slot, st, gate)
     switch (A.tile_nnz) {
     case 1024: SS_SPMV(1024); break;
     case 4096: SS_SPMV(4096); break;
@@ -754,6 +902,35 @@ void launch_ir_accumulate(hipStream_t s, int32_t n_loc, double *x64, const XT *d
                        outer);
 }
 
+template <typename XT>
+void launch_ru_start(hipStream_t s, const Iface &I, const double *r64, XT *rin, XT *d, double *partial,
+                     const DevState *outer, DevState *inner, double delta)
+{
+    hipLaunchKernelGGL(k_ru_start<XT>, dim3(I.grid), dim3(kBS), 0, s, I.n_loc, I.n_own, I.n_if, r64, rin, d, partial);
+    hipLaunchKernelGGL(k_ru_start_finish, dim3(1), dim3(kBS), 0, s, inner, outer, partial, I.grid, delta);
+}
+
+template <typename XT>
+void launch_ru_refresh(hipStream_t s, const Iface &I, const Mat &A64, double *x64, XT *d, const double *b64,
+                       double *q64, double *r64, XT *rin, double *partial, DevState *inner, DevState *outer)
+{
+    hipLaunchKernelGGL(k_ru_check, dim3(1), dim3(64), 0, s, inner);
+    hipLaunchKernelGGL(k_ru_fold_gated<XT>, dim3(nblocks(std::max(I.n_loc, 1))), dim3(kBS), 0, s, I.n_loc, x64, d,
+                       inner);
+    spmv_dispatch<double, double, SPMV_PLAIN>(s, A64, x64, nullptr, nullptr, q64, nullptr,
+                                              Partials{nullptr, nullptr, 0, 0}, nullptr, 0, &inner->refresh);
+    hipLaunchKernelGGL(k_ru_residual<XT>, dim3(I.grid), dim3(kBS), 0, s, I.n_loc, I.n_own, I.n_if, I.pos_grp,
+                       I.copy_ptr, I.copy_pos, b64, q64, r64, rin, partial, inner);
+    hipLaunchKernelGGL(k_ru_refresh_finish, dim3(1), dim3(kBS), 0, s, inner, outer, partial, I.grid);
+}
+
+template <typename XT>
+void launch_ru_fold(hipStream_t s, int32_t n_loc, double *x64, XT *d, const DevState *inner, DevState *outer)
+{
+    hipLaunchKernelGGL(k_ru_fold<XT>, dim3(nblocks(std::max(n_loc, 1))), dim3(kBS), 0, s, n_loc, x64, d, inner,
+                       outer);
+}
+
 // explicit instantiations
 #define SS_INST(XT)                                                                                                  \
     template void launch_gather<XT>(hipStream_t, int32_t, const int32_t *, const double *, XT *);                    \
@@ -769,7 +946,12 @@ void launch_ir_accumulate(hipStream_t s, int32_t n_loc, double *x64, const XT *d
                                       DevState *, bool);                                                             \
     template void launch_ir_prepare<XT>(hipStream_t, const Iface &, const double *, XT *, XT *, XT *, double *,      \
                                         const DevState *, DevState *, double, int32_t, int32_t);                     \
-    template void launch_ir_accumulate<XT>(hipStream_t, int32_t, double *, const XT *, const DevState *, DevState *);
+    template void launch_ir_accumulate<XT>(hipStream_t, int32_t, double *, const XT *, const DevState *, DevState *); \
+    template void launch_ru_start<XT>(hipStream_t, const Iface &, const double *, XT *, XT *, double *,             \
+                                      const DevState *, DevState *, double);                                         \
+    template void launch_ru_refresh<XT>(hipStream_t, const Iface &, const Mat &, double *, XT *, const double *,     \
+                                        double *, double *, XT *, double *, DevState *, DevState *);                 \
+    template void launch_ru_fold<XT>(hipStream_t, int32_t, double *, XT *, const DevState *, DevState *);
 SS_INST(double)
 SS_INST(float)
 #undef SS_INST

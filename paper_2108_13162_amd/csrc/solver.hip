@@ -291,6 +291,7 @@ struct ss_solver {
     // one CG run: its vectors, state and the graph of one polled chunk
     struct Run {
         bool fp32 = false;
+        bool ru = false;  // chunk ends with the gated FP64 residual replacement
         void *x = nullptr, *r = nullptr, *p0 = nullptr, *p1 = nullptr, *q = nullptr;
         DevState *st = nullptr;
         hipGraphExec_t exec = nullptr;
@@ -350,12 +351,22 @@ void enqueue_pair(ss_solver *s, const ss_solver::Run &R, hipStream_t stream, int
         enqueue_pair_t<double>(s, R, s->mat, stream, j);
 }
 
+// A polled chunk: `pairs` (update, step) pairs, then for a residual-
+// replacement run the gated replacement.
+void enqueue_chunk_work(ss_solver *s, const ss_solver::Run &R, hipStream_t stream, int32_t pairs)
+{
+    for (int32_t k = 0; k < pairs; ++k) enqueue_pair(s, R, stream, k);
+    if (R.ru)
+        launch_ru_refresh<float>(stream, s->ifc, s->mat, s->x, (float *)R.x, s->b, s->q, s->r, (float *)R.r,
+                                 s->part_r, R.st, s->st);
+}
+
 int ensure_chunk_graph(ss_solver *s, ss_solver::Run &R, int32_t pairs)
 {
     if (R.exec && R.pairs == pairs) return SS_OK;
     destroy_graph(R);
     SS_HIP(hipStreamBeginCapture(s->cap, hipStreamCaptureModeThreadLocal));
-    for (int32_t k = 0; k < pairs; ++k) enqueue_pair(s, R, s->cap, k);
+    enqueue_chunk_work(s, R, s->cap, pairs);
     hipGraph_t g = nullptr;
     SS_HIP(hipStreamEndCapture(s->cap, &g));
     R.graph = g;
@@ -369,7 +380,7 @@ int enqueue_chunk(ss_solver *s, ss_solver::Run &R, int32_t pairs)
     if (s->opts.use_graph) {
         SS_HIP(hipGraphLaunch(R.exec, s->stream));
     } else {
-        for (int32_t k = 0; k < pairs; ++k) enqueue_pair(s, R, s->stream, k);
+        enqueue_chunk_work(s, R, s->stream, pairs);
         SS_HIP(hipGetLastError());
     }
     return SS_OK;
@@ -437,6 +448,7 @@ void ss_opts_default(ss_opts *o)
     std::memset(o, 0, sizeof(*o));
     o->precision = SS_FP64;
     o->inner_tol = 1e-6;
+    o->ru_delta = 0.1;
     o->inner_maxit = 0;
     o->max_outer = 50;
     o->check_every = kDefaultCheck;
@@ -471,7 +483,10 @@ int ss_cg_setup(const ss_csr *A, const ss_part *p, const ss_opts *o, void *hip_s
     ss_opts opts;
     ss_opts_default(&opts);
     if (o) opts = *o;
-    if (opts.precision != SS_FP64 && opts.precision != SS_FP32_IR) return fail(SS_EINVAL, "unknown precision");
+    if (opts.precision != SS_FP64 && opts.precision != SS_FP32_IR && opts.precision != SS_FP32_RU)
+        return fail(SS_EINVAL, "unknown precision");
+    if (opts.precision == SS_FP32_RU && !(opts.ru_delta >= 0.0 && opts.ru_delta <= 1.0))
+        return fail(SS_EINVAL, "ru_delta must be in [0, 1]");
     if (opts.tile_nnz != 0 && opts.tile_nnz != 1024 && opts.tile_nnz != 2048 && opts.tile_nnz != 4096)
         return fail(SS_EINVAL, "tile_nnz must be 0, 1024, 2048 or 4096");
     if (opts.matrix_format < SS_MAT_AUTO || opts.matrix_format > SS_MAT_CSR)
@@ -567,7 +582,7 @@ int ss_cg_setup(const ss_csr *A, const ss_part *p, const ss_opts *o, void *hip_s
         (rc = alloc_dev(s, &s->part_a, (size_t)M.grid)) || (rc = alloc_dev(s, &s->part_b, (size_t)I.grid)) ||
         (rc = alloc_dev(s, &s->part_r, 2 * (size_t)I.grid)))
         return bail(rc);
-    if (opts.precision == SS_FP32_IR) {
+    if (opts.precision != SS_FP64) {
         std::vector<float> v32(val_st.size());
         for (size_t k = 0; k < v32.size(); ++k) v32[k] = (float)val_st[k];
         if ((rc = upload(s, &s->val32, v32.data(), v32.size())) || (rc = alloc_dev(s, &s->d32, nl)) ||
@@ -599,6 +614,7 @@ int ss_cg_setup(const ss_csr *A, const ss_part *p, const ss_opts *o, void *hip_s
     s->run64.q = s->q;
     s->run64.st = s->st;
     s->run32.fp32 = true;
+    s->run32.ru = opts.precision == SS_FP32_RU;
     s->run32.x = s->d32;
     s->run32.r = s->r32;
     s->run32.p0 = s->p32a;
@@ -664,6 +680,33 @@ int ss_cg_solve(ss_solver *s, const double *b_dev, double *x_dev, double tol, in
             if ((rc = read_status(s, s->st, &status)) != SS_OK) return rc;
             if (status == ST_BREAKDOWN) break;
         }
+    } else if (s->opts.precision == SS_FP32_RU) {
+        // FP32 CG with FP64 residual replacement: every (re)start takes the
+        // FP64 residual; the polled chunks end with the gated replacement
+        SS_HIP(hipMemsetAsync(&s->st_in->nrefresh, 0, sizeof(int32_t), s->stream));
+        for (bool first = true;; first = false) {
+            ++restarts;
+            launch_spmv<double, double>(s->stream, s->mat, s->x, s->q);
+            launch_residual<double>(s->stream, s->ifc, s->b, s->q, s->r, s->p0, s->part_r, s->st, first);
+            SS_HIP(hipGetLastError());
+            if ((rc = read_status(s, s->st, &status)) != SS_OK) return rc;
+            if (status != ST_RUNNING) break;
+            launch_ru_start<float>(s->stream, s->ifc, s->r, s->r32, s->d32, s->part_r, s->st, s->st_in,
+                                   s->opts.ru_delta);
+            launch_spmv_first<float, float>(s->stream, s->mat32, s->r32, s->r32, s->p32b, s->q32, s->partials(),
+                                            s->st_in);
+            if ((rc = iterate(s, s->run32)) != SS_OK) return rc;
+            launch_ru_fold<float>(s->stream, s->n_loc, s->x, s->d32, s->st_in, s->st);
+            SS_HIP(hipGetLastError());
+            if ((rc = read_status(s, s->st, &status)) != SS_OK) return rc;
+            if (status == ST_BREAKDOWN) break;
+        }
+        int32_t nref = 0;
+        SS_HIP(hipMemcpyAsync(&s->flag_pinned[0], &s->st_in->nrefresh, sizeof(int32_t), hipMemcpyDeviceToHost,
+                              s->stream));
+        SS_HIP(hipStreamSynchronize(s->stream));
+        nref = s->flag_pinned[0];
+        outer = nref;
     } else {
         // outer: FP64 residual of the FP64 matrix; inner: CG on the FP32 values
         // with FP32 vectors for the scaled residual; x += ||r|| d
@@ -763,7 +806,7 @@ int ss_cg_time_spmv(ss_solver *s, int32_t reps, double *ms_per_launch, double *b
     // of 1 each, (r, r) slot 0 = 1, no stopping (stop = 0, unbounded
     // iterations, no history), so every launch finishes the reduction, reads
     // slot 0, writes slot 1 and does the full work.
-    const bool f32 = s->opts.precision == SS_FP32_IR;
+    const bool f32 = s->opts.precision != SS_FP64;
     DevState *st = f32 ? s->st_in : s->st;
     SS_HIP(hipMemcpyAsync(s->st_pinned, st, sizeof(DevState), hipMemcpyDeviceToHost, s->stream));
     SS_HIP(hipStreamSynchronize(s->stream));

@@ -32,8 +32,8 @@ def test_library_exports_every_declared_symbol():
 
 def test_opts_layout_and_defaults():
     o = ss.default_opts()
-    assert C.sizeof(ss.ss_opts) == 72
-    assert o.precision == ss.SS_FP64 and o.inner_tol == 1e-6 and o.max_outer == 50
+    assert C.sizeof(ss.ss_opts) == 80
+    assert o.precision == ss.SS_FP64 and o.inner_tol == 1e-6 and o.max_outer == 50 and o.ru_delta == 0.1
     assert o.check_every == 32 and o.use_graph == 1 and o.tile_nnz == 0
     assert o.matrix_format == ss.SS_MAT_AUTO
     assert ss.lib().ss_version() >= 100
