@@ -131,8 +131,11 @@ def variant_mixed(ss, torch, reps: int, tol: float) -> dict:
         if s64 is None:
             s64 = s
         true = float(torch.linalg.norm(b - ss.ss_cg_apply(s64, x))) / bn
+        sp_ms, sp_bytes = ss.ss_cg_time_spmv(s, 30)
         out[name] = {"ms": round(ms, 3), "status": r.status, "iterations": r.iterations,
-                     "outer_iterations": r.outer_iterations, "true_relres": true}
+                     "outer_iterations": r.outer_iterations, "true_relres": true,
+                     "step_spmv_us": round(sp_ms * 1e3, 2),
+                     "step_spmv_gbps": round(sp_bytes / (sp_ms * 1e-3) / 1e9, 1)}
         if prec == ss.SS_FP32_RU:
             out[name]["residual_replacements"] = out[name].pop("outer_iterations")
         xs[name] = x.clone()

@@ -288,7 +288,7 @@ typedef struct {
     int32_t tile_granules; /* 512-row granules per workgroup tile: 1, 2, 4, 8   */
     int32_t grid;          /* workgroups per launch, a multiple of 8 in
                               [8, 65536]; 0 = one per tile                     */
-    int32_t unroll;        /* matrix entries loaded per lane before use: 4, 8   */
+    int32_t unroll;        /* matrix entries loaded per lane before use: 4, 5, 8 */
     int32_t check_every;   /* CG iterations between host polls, even, 2..1024  */
 } ss_batch_tuning;
 
@@ -329,7 +329,7 @@ int ss_batch_get_tuning(const ss_batch *bt, ss_batch_tuning *t);
 
 /*
  * ss_batch_tune -- the autotuner.  Times each candidate launch shape (tile
- * granules 1/2/4/8 x grid one-per-tile/2048/1024 x unroll 4/8) over `iters`
+ * granules 1/2/4/8 x grid one-per-tile/2048/1024 x unroll 4/5/8) over `iters`
  * CG iterations (<= 0: 8) of this batch with right-hand sides b_dev, every
  * pair running from x = 0 (x_dev is not touched), and keeps the fastest.
  * The choice is remembered for the process, keyed by the batch structure

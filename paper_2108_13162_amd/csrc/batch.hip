@@ -233,7 +233,7 @@ __device__ __forceinline__ Share list_share(int nact)
 // LDS ring of W rows, sliding granule by granule through its tile, so every
 // vector row is read from memory once per tile (plus the 2h halo rows) and
 // the column gathers are LDS reads.  Other systems gather from memory.
-template <int NR, int U, int MODE>
+template <int NR, int U, int MODE, bool ALL_STAGED>
 __global__ __launch_bounds__(kWG) void k_bspmv(BMat M, BTiles T, BState S, const double *__restrict__ pin,
                                                const double *__restrict__ r, double *__restrict__ pout,
                                                double *__restrict__ q, double *__restrict__ part_a,
@@ -299,11 +299,27 @@ __global__ __launch_bounds__(kWG) void k_bspmv(BMat M, BTiles T, BState S, const
         }
         const int g0 = T.tile_g0[t], g1 = T.tile_g0[t + 1];
         const int h = T.sys_h[s];
-        const bool staged = h <= HMAX;
+        const bool staged = ALL_STAGED || h <= HMAX;  // ALL_STAGED: every system qualifies
         const int S0 = M.crow[T.gran_c0[T.sys_g0[s]]], S1 = M.crow[T.gran_c0[T.sys_g0[s + 1]]];
         int hi = -1;  // ring holds rows [.., hi)
         for (int g = g0; g < g1; ++g) {
             const int c0 = T.gran_c0[g], c1 = T.gran_c0[g + 1];
+            // first batch of the wave's first chunk, issued before the staging
+            int cc[U];
+            double vv[U];
+            bool have = false;
+            if (c0 + w < c1) {
+                const int L0 = M.clen[c0 + w], base0 = M.cptr[c0 + w];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    if (u < L0) {
+                        const int k = base0 + u * kChunk + lane;
+                        cc[u] = M.col[k];
+                        vv[u] = M.val[k];
+                    }
+                }
+                have = true;
+            }
             if (staged) {
                 const int a = M.crow[c0], e = M.crow[c1];
                 const int need = min(S1, e + h);
@@ -339,42 +355,55 @@ __global__ __launch_bounds__(kWG) void k_bspmv(BMat M, BTiles T, BState S, const
 #pragma unroll
                 for (int j = 0; j < NR; ++j) sum[j] = 0.0;
                 for (int j0 = 0; j0 < L; j0 += U) {
-                    int cc[U];
-                    double vv[U];
+                    if (!have) {
 #pragma unroll
-                    for (int u = 0; u < U; ++u) {
-                        if (j0 + u < L) {
-                            const int k = base + (j0 + u) * kChunk + lane;
-                            cc[u] = M.col[k];
-                            vv[u] = M.val[k];
-                        }
-                    }
-                    double xx[U][NR];
-#pragma unroll
-                    for (int u = 0; u < U; ++u) {
-                        if (j0 + u < L) {
-                            if (staged) {
-                                ld_row<NR>(ring, cc[u] & (W - 1), xx[u]);
-                            } else if (MODE == M_PLAIN) {
-                                ld_row<NR>(pin, cc[u], xx[u]);
-                            } else if (MODE == M_FIRST) {
-                                ld_row<NR>(r, cc[u], xx[u]);
-                            } else {
-                                double rv[NR], pv[NR];
-                                ld_row<NR>(r, cc[u], rv);
-                                ld_row<NR>(pin, cc[u], pv);
-#pragma unroll
-                                for (int j = 0; j < NR; ++j) xx[u][j] = rv[j] + beta[j] * pv[j];
+                        for (int u = 0; u < U; ++u) {
+                            if (j0 + u < L) {
+                                const int k = base + (j0 + u) * kChunk + lane;
+                                cc[u] = M.col[k];
+                                vv[u] = M.val[k];
                             }
                         }
                     }
+                    have = false;
+                    if (staged) {
+                        // LDS gathers are short: use each entry at once
 #pragma unroll
-                    for (int u = 0; u < U; ++u)
-                        if (j0 + u < len) {
+                        for (int u = 0; u < U; ++u) {
+                            if (j0 + u < len) {
+                                double xr[NR];
+                                ld_row<NR>(ring, cc[u] & (W - 1), xr);
 #pragma unroll
-                            for (int j = 0; j < NR; ++j) sum[j] = sum[j] + vv[u] * xx[u][j];
+                                for (int j = 0; j < NR; ++j) sum[j] = sum[j] + vv[u] * xr[j];
+                            }
                         }
+                    } else {
+                        double xx[U][NR];
+#pragma unroll
+                        for (int u = 0; u < U; ++u) {
+                            if (j0 + u < L) {
+                                if (MODE == M_PLAIN) {
+                                    ld_row<NR>(pin, cc[u], xx[u]);
+                                } else if (MODE == M_FIRST) {
+                                    ld_row<NR>(r, cc[u], xx[u]);
+                                } else {
+                                    double rv[NR], pv[NR];
+                                    ld_row<NR>(r, cc[u], rv);
+                                    ld_row<NR>(pin, cc[u], pv);
+#pragma unroll
+                                    for (int j = 0; j < NR; ++j) xx[u][j] = rv[j] + beta[j] * pv[j];
+                                }
+                            }
+                        }
+#pragma unroll
+                        for (int u = 0; u < U; ++u)
+                            if (j0 + u < len) {
+#pragma unroll
+                                for (int j = 0; j < NR; ++j) sum[j] = sum[j] + vv[u] * xx[u][j];
+                            }
+                    }
                 }
+                have = false;
                 if (valid) {
                     st_row<NR>(q, row, sum);
                     if (CG) {
@@ -694,7 +723,7 @@ bool tuning_valid(const ss_batch_tuning &t)
     const int k = t.tile_granules;
     if (k != 1 && k != 2 && k != 4 && k != 8) return false;
     if (t.grid != 0 && (t.grid < 8 || t.grid > kGridLimit || t.grid % 8 != 0)) return false;
-    if (t.unroll != 4 && t.unroll != 8) return false;
+    if (t.unroll != 4 && t.unroll != 5 && t.unroll != 8) return false;
     if (t.check_every < 2 || t.check_every > 1024 || t.check_every % 2 != 0) return false;
     return true;
 }
@@ -708,6 +737,7 @@ struct ss_batch {
     int32_t nsys = 0, nrhs = 0, device = 0;
     int64_t nrows = 0, nnz = 0, stored = 0;
     int32_t nchunks = 0, ngran = 0, ntiles = 0;
+    int32_t max_halo = 0;  // largest |column - row| over all systems
     std::string key;  // structure signature for the tuning cache
     hipStream_t stream = nullptr, cap = nullptr;
     DeviceMem mem;
@@ -794,12 +824,19 @@ int apply_tuning(ss_batch *b, const ss_batch_tuning &t)
     return SS_OK;
 }
 
+// Largest |column - row| the staged SpMV handles for NR right-hand sides.
+int staged_halo(int nr) { return (kRingBytes / (8 * nr) - kGranRows) / 2; }
+
 template <int NR, int U, int MODE>
 void spmv_t(ss_batch *b, hipStream_t st, bool full, const double *pin, const double *r, double *pout, double *q,
             int slot)
 {
-    hipLaunchKernelGGL((k_bspmv<NR, U, MODE>), dim3(b->grid()), dim3(kWG), 0, st, b->bmat(), b->tiles(full),
-                       b->state(), pin, r, pout, q, b->part_a, b->part_b, slot);
+    if (b->max_halo <= staged_halo(NR))
+        hipLaunchKernelGGL((k_bspmv<NR, U, MODE, true>), dim3(b->grid()), dim3(kWG), 0, st, b->bmat(),
+                           b->tiles(full), b->state(), pin, r, pout, q, b->part_a, b->part_b, slot);
+    else
+        hipLaunchKernelGGL((k_bspmv<NR, U, MODE, false>), dim3(b->grid()), dim3(kWG), 0, st, b->bmat(),
+                           b->tiles(full), b->state(), pin, r, pout, q, b->part_a, b->part_b, slot);
 }
 
 template <int NR, int MODE>
@@ -808,6 +845,8 @@ void spmv_u(ss_batch *b, hipStream_t st, bool full, const double *pin, const dou
 {
     if (b->tun.unroll == 4)
         spmv_t<NR, 4, MODE>(b, st, full, pin, r, pout, q, slot);
+    else if (b->tun.unroll == 5)
+        spmv_t<NR, 5, MODE>(b, st, full, pin, r, pout, q, slot);
     else
         spmv_t<NR, 8, MODE>(b, st, full, pin, r, pout, q, slot);
 }
@@ -1085,6 +1124,7 @@ int ss_batch_setup(int32_t nsys, const ss_csr *systems, int32_t nrhs, const ss_o
     b->nchunks = (int32_t)cptr.size();
     b->ngran = (int32_t)gran_c0.size() - 1;
     b->sys_g0_h = sys_g0;
+    b->max_halo = *std::max_element(halo.begin(), halo.end());
     if (hipGetDevice(&b->device) != hipSuccess) return bail(fail(SS_EDEVICE, "no HIP device"));
     b->key = structure_key(rows_h, nnz_h, nrhs, b->device);
     if (hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking) != hipSuccess)
@@ -1239,7 +1279,7 @@ int ss_batch_tune(ss_batch *b, const double *b_dev, int32_t iters, int32_t force
     std::vector<ss_batch_tuning> cands;
     for (int k : {1, 2, 4, 8})
         for (int g : {0, 2048, 1024})
-            for (int u : {4, 8}) cands.push_back(ss_batch_tuning{k, g, u, pairs});
+            for (int u : {4, 5, 8}) cands.push_back(ss_batch_tuning{k, g, u, pairs});
     ss_batch_tuning best = b->tun;
     double best_ms = 0.0;
     int32_t n = 0;

@@ -104,7 +104,7 @@ def test_fixed_iterations_match_oracle(small, k):
 def test_results_independent_of_launch_shape(small):
     S, bt, B = small
     ref = None
-    for shape in [(2, 0, 8, 32), (1, 0, 4, 32), (8, 0, 8, 2), (1, 8, 8, 32), (4, 1024, 4, 64), (2, 16, 8, 4)]:
+    for shape in [(2, 0, 8, 32), (1, 0, 4, 32), (8, 0, 8, 2), (1, 8, 5, 32), (4, 1024, 4, 64), (2, 16, 5, 4)]:
         ss.ss_batch_set_tuning(bt, *shape)
         X, res, _ = _solve(bt, B)
         flat = np.concatenate([x.ravel() for x in X])
@@ -120,7 +120,7 @@ def test_autotuner_picks_a_candidate_and_caches_it(small):
     S, bt, B = small
     b = _t(ss.pack_batch(B))
     chosen, trials = ss.ss_batch_tune(bt, b, iters=4, force=True)
-    assert len(trials) == 24 and all(ms > 0 for _, ms in trials)
+    assert len(trials) == 36 and all(ms > 0 for _, ms in trials)
     shapes = [t for t, _ in trials]
     assert chosen in shapes
     best = min(trials, key=lambda t: t[1])[0]
@@ -223,3 +223,32 @@ def test_full_size_batch_256_systems_4_rhs():
             * np.linalg.norm(xr)
     its = np.array([r.iterations for r in res])
     print(f"cfg4 batch: iterations {its.min()}..{its.max()}, worst true relres {worst:.2e}")
+
+
+@pytest.mark.parametrize("nrhs", [4, 1])
+def test_wide_systems_take_the_direct_gather_path(nrhs):
+    # a 20^3 7-point system couples rows 400 apart, beyond the LDS window of
+    # the staged SpMV for 4 right-hand sides (and a random SPD pattern far
+    # beyond it for 1): those launches gather from memory; results must match
+    # the oracle pair by pair all the same, next to small staged-size systems
+    S = [diffusion3d_lognormal(20, seed=31, sigma=0.5)] + batch2d_lognormal(2, 8, 20, seed=32)
+    if nrhs == 1:
+        from workloads import random_spd_csr
+        S.append(random_spd_csr(5000, 6.0, seed=33))
+    bt = ss.ss_batch_setup(S, nrhs=nrhs)
+    B = _rhs(S, nrhs, 34)
+    X, res, summ = _solve(bt, B)
+    assert summ.status == ss.SS_OK
+    for s, A in enumerate(S):
+        for j in range(nrhs):
+            b = B[s][:, j]
+            xo, ro = O.cg(A, b, tol=1e-10, hist=False)
+            r = res[s * nrhs + j]
+            assert abs(r.iterations - ro.iterations) <= max(2, 0.05 * ro.iterations), (s, j, r, ro)
+            true = np.linalg.norm(b - O.csr_matvec(A, X[s][:, j])) / np.linalg.norm(b)
+            assert true <= 1e-10
+    # and the launch shape still changes nothing
+    ss.ss_batch_set_tuning(bt, 1, 8, 4, 2)
+    X2, res2, _ = _solve(bt, B)
+    assert all(np.array_equal(a, c) for a, c in zip(X, X2))
+    assert [r.iterations for r in res] == [r.iterations for r in res2]
