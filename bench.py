@@ -78,6 +78,22 @@ def calibrate_copy(torch, nbytes: int = 1 << 30, reps: int = 4) -> None:
     print(f"# copy calibration: {reps} copies of {nbytes} bytes", file=sys.stderr, flush=True)
 
 
+def stream_copy_gbps(torch, nbytes: int = 1 << 30, reps: int = 10) -> float:
+    """Achievable HBM bandwidth: a plain device-to-device copy (read + write)."""
+    a = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, b
+    return 2.0 * nbytes / (ms * 1e-3) / 1e9
+
+
 def cpu_baseline(w, iters_gpu: int, sample_iters: int) -> dict:
     import numpy as np
 
@@ -310,6 +326,7 @@ def main_measurement(args, ss, torch, config):
             "traffic": traffic,
             "launch_ms": round(spmv_ms, 5),
             "algorithmic_bytes": int(spmv_bytes),
+            "stream_copy_gbps": round(stream_copy_gbps(torch), 1),
         },
     }
     if not args.no_cpu_baseline:
