@@ -42,6 +42,8 @@ def lib():
         L.orc_ss_spmv.argtypes = [P, P, P]
         L.orc_cg.argtypes = [i64, P, P, P, P, P, dbl, i32, P, P, P, P]
         L.orc_ss_cg.argtypes = [P, i64, P, P, P, P, P, dbl, i32, P, P, P, P]
+        L.orc_pcg.argtypes = [i64, P, P, P, P, P, dbl, i32, P, P, P, P]
+        L.orc_ss_pcg.argtypes = [P, i64, P, P, P, P, P, dbl, i32, P, P, P, P]
         L.orc_ss_ir.argtypes = [P, i64, P, P, P, P, P, dbl, i32, dbl, i32, i32, P, P, P, P]
         L.orc_ss_ru.argtypes = [P, i64, P, P, P, P, P, dbl, i32, dbl, i32, P, P, P, P]
         L.orc_grad_vals.argtypes = [i64, P, P, P, P, P]
@@ -188,6 +190,29 @@ def ss_cg(A, sd: SubDomains, b, x0=None, tol: float = 1e-10, maxit: int = 10000,
     it, rel, tr = C.c_int32(), C.c_double(), C.c_double()
     st = lib().orc_ss_cg(S.ref(), A.n, _p(_i32(A.rowptr)), _p(_i32(A.colidx)), _p(_f64(A.val)), _p(b), _p(x),
                          tol, maxit, _p(h), C.byref(it), C.byref(rel), C.byref(tr))
+    return x, Result(st, it.value, rel.value, tr.value, h[: it.value + 1] if hist else None)
+
+
+def pcg(A, b, x0=None, tol: float = 1e-10, maxit: int = 10000, hist: bool = True) -> tuple:
+    """Jacobi-preconditioned CG on the global matrix (Algorithm 3, M = diag A)."""
+    b = _f64(b)
+    x = np.zeros(A.n) if x0 is None else _f64(x0).copy()
+    h = np.full(maxit + 1, np.nan)
+    it, rel, tr = C.c_int32(), C.c_double(), C.c_double()
+    st = lib().orc_pcg(A.n, _p(_i32(A.rowptr)), _p(_i32(A.colidx)), _p(_f64(A.val)), _p(b), _p(x), tol, maxit,
+                       _p(h), C.byref(it), C.byref(rel), C.byref(tr))
+    return x, Result(st, it.value, rel.value, tr.value, h[: it.value + 1] if hist else None)
+
+
+def ss_pcg(A, sd: SubDomains, b, x0=None, tol: float = 1e-10, maxit: int = 10000, hist: bool = True) -> tuple:
+    """Sub-structured Jacobi-preconditioned CG (every copy holds the global 1/a_ii)."""
+    S = _Sub(sd, A.val)
+    b = _f64(b)
+    x = np.zeros(A.n) if x0 is None else _f64(x0).copy()
+    h = np.full(maxit + 1, np.nan)
+    it, rel, tr = C.c_int32(), C.c_double(), C.c_double()
+    st = lib().orc_ss_pcg(S.ref(), A.n, _p(_i32(A.rowptr)), _p(_i32(A.colidx)), _p(_f64(A.val)), _p(b), _p(x),
+                          tol, maxit, _p(h), C.byref(it), C.byref(rel), C.byref(tr))
     return x, Result(st, it.value, rel.value, tr.value, h[: it.value + 1] if hist else None)
 
 

@@ -296,6 +296,134 @@ int orc_ss_cg(const orc_sub *S, int64_t n, const int32_t *rowptr, const int32_t 
 }
 
 /* ---------------------------------------------------------------------- */
+/* Preconditioned CG (Algorithm 3 with M = D, the diagonal of the global   */
+/* matrix): z = D^{-1} r, alpha = (z, r) / (S p, p), p = z + beta p with    */
+/* beta = (r_new, z_new) / (r, z).  Stopping rule, residual recomputation */
+/* and restarts as in cg_core, on the unpreconditioned ||r||.  dinv holds  */
+/* 1 / a_ii of every (local) position.                                     */
+/* ---------------------------------------------------------------------- */
+
+static int pcg_core(const orc_op *A, const double *dinv, const double *b, double *x, double tol, int32_t maxit,
+                    double *hist, int32_t *iters, double *relres)
+{
+    const int64_t n = A->n;
+    double *r = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    double *z = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    double *p = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    double *q = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    int status = ORC_OK;
+    int32_t k = 0;
+    double rr = 0.0, rz = 0.0;
+    if (!r || !z || !p || !q) { status = ORC_ENOMEM; goto done; }
+
+    const double bb = A->dot(A->ctx, b, b);
+    if (!isfinite(bb)) { status = ORC_EBREAKDOWN; goto done; }
+    if (bb == 0.0) {
+        for (int64_t i = 0; i < n; ++i) x[i] = 0.0;
+        if (hist) hist[0] = 0.0;
+        *relres = 0.0;
+        goto done;
+    }
+    const double stop = tol * sqrt(bb);
+
+    for (;;) {
+        /* r = f - S x, z = M^{-1} r, p = z */
+        A->apply(A->ctx, x, q);
+        for (int64_t i = 0; i < n; ++i) r[i] = b[i] - q[i];
+        for (int64_t i = 0; i < n; ++i) z[i] = dinv[i] * r[i];
+        for (int64_t i = 0; i < n; ++i) p[i] = z[i];
+        rr = A->dot(A->ctx, r, r);
+        rz = A->dot(A->ctx, r, z);
+        if (!isfinite(rr) || !isfinite(rz)) { status = ORC_EBREAKDOWN; goto done; }
+        if (hist) hist[k] = sqrt(rr / bb);
+        if (sqrt(rr) <= stop) { status = ORC_OK; break; }
+        if (k >= maxit) { status = ORC_NOT_CONVERGED; break; }
+
+        while (sqrt(rr) > stop && k < maxit) {
+            A->apply(A->ctx, p, q);                         /* S p_k          */
+            const double pq = A->dot(A->ctx, p, q);         /* (S p_k, p_k)   */
+            if (!(pq > 0.0) || !isfinite(pq)) { status = ORC_EBREAKDOWN; goto done; }
+            const double alpha = rz / pq;                   /* alpha_k        */
+            for (int64_t i = 0; i < n; ++i) x[i] = x[i] + alpha * p[i];
+            for (int64_t i = 0; i < n; ++i) r[i] = r[i] - alpha * q[i];
+            for (int64_t i = 0; i < n; ++i) z[i] = dinv[i] * r[i];
+            const double rr1 = A->dot(A->ctx, r, r);
+            const double rz1 = A->dot(A->ctx, r, z);
+            if (!isfinite(rr1) || !isfinite(rz1)) { status = ORC_EBREAKDOWN; goto done; }
+            const double beta = rz1 / rz;                   /* beta_k         */
+            for (int64_t i = 0; i < n; ++i) p[i] = z[i] + beta * p[i];
+            rr = rr1;
+            rz = rz1;
+            ++k;
+            if (hist) hist[k] = sqrt(rr / bb);
+        }
+    }
+    *relres = sqrt(rr / bb);
+done:
+    *iters = k;
+    free(r); free(z); free(p); free(q);
+    return status;
+}
+
+/* 1 / a_ii of the global matrix (EINVAL if a diagonal entry is missing or
+ * not positive). */
+static int diag_inv(int64_t n, const int32_t *rowptr, const int32_t *colidx, const double *val, double *dinv)
+{
+    for (int64_t i = 0; i < n; ++i) {
+        double d = 0.0;
+        for (int64_t k = rowptr[i]; k < rowptr[i + 1]; ++k)
+            if (colidx[k] == i) d = val[k];
+        if (!(d > 0.0)) return ORC_EINVAL;
+        dinv[i] = 1.0 / d;
+    }
+    return ORC_OK;
+}
+
+int orc_pcg(int64_t n, const int32_t *rowptr, const int32_t *colidx, const double *val,
+            const double *b, double *x, double tol, int32_t maxit,
+            double *hist, int32_t *iters, double *relres, double *true_rr)
+{
+    double *dinv = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    if (!dinv) return ORC_ENOMEM;
+    int st = diag_inv(n, rowptr, colidx, val, dinv);
+    if (st == ORC_OK) {
+        csr_ctx c = {n, rowptr, colidx, val};
+        orc_op op = {n, glob_apply, glob_dot, &c};
+        st = pcg_core(&op, dinv, b, x, tol, maxit, hist, iters, relres);
+        *true_rr = true_relres(n, rowptr, colidx, val, b, x);
+    }
+    free(dinv);
+    return st;
+}
+
+/* Sub-structured PCG: every copy of a node holds the node's global 1 / a_ii. */
+int orc_ss_pcg(const orc_sub *S, int64_t n, const int32_t *rowptr, const int32_t *colidx,
+               const double *val, const double *b, double *x, double tol, int32_t maxit,
+               double *hist, int32_t *iters, double *relres, double *true_rr)
+{
+    const size_t m = (size_t)(S->n_loc > 0 ? S->n_loc : 1);
+    double *dg = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    double *dl = (double *)malloc(sizeof(double) * m);
+    double *bl = (double *)malloc(sizeof(double) * m);
+    double *xl = (double *)malloc(sizeof(double) * m);
+    int st = ORC_ENOMEM;
+    if (dg && dl && bl && xl) {
+        st = diag_inv(n, rowptr, colidx, val, dg);
+        if (st == ORC_OK) {
+            gather(S, dg, dl);
+            gather(S, b, bl);
+            gather(S, x, xl);
+            orc_op op = {S->n_loc, ss_apply, ss_dot, S};
+            st = pcg_core(&op, dl, bl, xl, tol, maxit, hist, iters, relres);
+            scatter_owned(S, xl, x);
+            *true_rr = true_relres(n, rowptr, colidx, val, b, x);
+        }
+    }
+    free(dg); free(dl); free(bl); free(xl);
+    return st;
+}
+
+/* ---------------------------------------------------------------------- */
 /* FP32 values + FP64 iterative refinement (project variant)              */
 /*                                                                         */
 /* Outer: r = b - A x with FP64 values and vectors; stop when ||r|| <=     */

@@ -465,6 +465,80 @@ def test_ir_reaches_fp64_accuracy():
     assert np.max(np.abs(b - b.astype(np.float32))) > 1e-10
 
 
+# ----------------------------------------------------------------------------
+# Jacobi-preconditioned CG (Algorithm 3 with M = diag A)
+# ----------------------------------------------------------------------------
+
+def test_pcg_equals_cg_on_the_symmetrically_scaled_system():
+    # With M = D, PCG on A x = b produces x_k = D^{-1/2} y_k where y_k are the
+    # CG iterates on (D^{-1/2} A D^{-1/2}) y = D^{-1/2} b (the textbook
+    # equivalence); checked after k steps on a small lognormal system
+    M = 6
+    A = diffusion3d_lognormal(M, seed=7, sigma=1.0)
+    b = uniform_rhs(A.n, 107)
+    D = A.to_dense()
+    s = 1.0 / np.sqrt(np.diag(D))
+    As = _dense_to_csr(D * s[:, None] * s[None, :])
+    for k in (1, 3, 8):
+        x, rp = O.pcg(A, b, tol=0.0, maxit=k, hist=False)
+        y, rc = O.cg(As, s * b, tol=0.0, maxit=k, hist=False)
+        assert rp.iterations == rc.iterations == k
+        assert np.linalg.norm(x - s * y) <= 1e-11 * np.linalg.norm(x), k
+
+
+def test_pcg_diagonal_matrix_one_step():
+    d = np.array([1.0, 3.0, 0.5, 7.0, 2.0])
+    A = _dense_to_csr(np.diag(d))
+    b = np.array([1.0, -2.0, 3.0, 0.25, 5.0])
+    x, r = O.pcg(A, b, tol=1e-14)
+    assert r.status == O.OK and r.iterations == 1
+    assert np.allclose(x, b / d, rtol=1e-15)
+
+
+def test_pcg_accuracy_iterations_and_subdomains():
+    M = 12
+    A = diffusion3d_lognormal(M, seed=3, sigma=1.0)
+    b = uniform_rhs(A.n, 108)
+    D = A.to_dense()
+    ref = np.linalg.solve(D, b)
+    x, r = O.pcg(A, b, tol=1e-12, maxit=10000)
+    assert r.status == O.OK and r.true_relres <= 1e-12
+    kappa = np.linalg.cond(D)
+    assert np.linalg.norm(x - ref) <= 2 * kappa * 1e-12 * np.linalg.norm(ref)
+    _, rcg = O.cg(A, b, tol=1e-10, hist=False)
+    _, rp = O.pcg(A, b, tol=1e-10, hist=False)
+    assert rp.iterations < rcg.iterations
+    # sub-structuring regroups the SpMV and the dots only
+    its = []
+    for boxes in [(1, 1, 1), (2, 2, 1), (2, 2, 2), (3, 2, 2)]:
+        P = int(np.prod(boxes))
+        sd = O.split(A.rowptr, A.colidx, O.box_partition((M, M, M), boxes), P)
+        xs, rs = O.ss_pcg(A, sd, b, tol=1e-10, hist=False)
+        its.append(rs.iterations)
+        assert rs.status == O.OK and rs.true_relres <= 1e-10
+        if P == 1:
+            xg, rg = O.pcg(A, b, tol=1e-10, hist=False)
+            assert np.array_equal(xs, xg) and rs.iterations == rg.iterations
+    assert max(its) - min(its) <= 2, its
+
+
+def test_pcg_edge_cases():
+    A = diffusion3d_lognormal(5, seed=3, sigma=0.5)
+    x, r = O.pcg(A, np.zeros(A.n), x0=np.ones(A.n))
+    assert r.status == O.OK and r.iterations == 0 and not x.any()
+    bn = uniform_rhs(A.n, 3)
+    bn[2] = np.nan
+    _, r = O.pcg(A, bn)
+    assert r.status == O.EBREAKDOWN
+    # a non-positive diagonal entry has no Jacobi inverse
+    B = CSR(A.n, A.rowptr.copy(), A.colidx.copy(), A.val.copy())
+    rows = B.row_of_nz()
+    k0 = int(np.nonzero((rows == 0) & (B.colidx == 0))[0][0])
+    B.val[k0] = 0.0
+    _, r = O.pcg(B, uniform_rhs(A.n, 3))
+    assert r.status == O.EINVAL
+
+
 def _ru_case():
     M = 12
     A = diffusion3d_lognormal(M, seed=3, sigma=0.5)
