@@ -22,7 +22,9 @@ measurement (time to relative residual 1e-10, inputs resident):
               right-hand sides each: one batched solve (autotuned launch
               shape) vs the 1024 (system, rhs) solves one by one;
   adjoint  -- 64^3 smoothed-GRF diffusion, 8 boxes: forward solve and
-              forward + adjoint backward through torch.autograd.
+              forward + adjoint backward through torch.autograd;
+  jacobi   -- the main line's system with the Jacobi preconditioner
+              (Algorithm 3 with M = diag A) vs plain CG.
 
   python bench.py [--steps K] [--warmup W] [--gpus 1] [--config 2]
                   [--variants mixed,batched,adjoint | none]
@@ -224,6 +226,32 @@ def variant_batched(ss, torch, reps: int, tol: float, one_by_one: bool = True) -
     return out
 
 
+def variant_jacobi(ss, torch, reps: int, tol: float) -> dict:
+    """Jacobi-preconditioned CG (Algorithm 3 with M = diag A) vs plain CG on
+    the 128^3 lognormal system of the main line."""
+    from workloads import config
+
+    w = config(2)
+    part = ss.partition_workload(w)
+    b = torch.tensor(w.b, dtype=torch.float64, device="cuda")
+    out = {"workload": w.name}
+    for name, pc in (("cg", ss.SS_PRECOND_NONE), ("pcg_jacobi", ss.SS_PRECOND_JACOBI)):
+        s = ss.ss_cg_setup(w.A, part, ss.default_opts(precond=pc))
+        x = torch.zeros_like(b)
+
+        def run():
+            x.zero_()
+            return ss.ss_cg_solve(s, b, x, tol=tol, maxit=100000)
+
+        ms, r = _timed(torch, run, reps)
+        out[name] = {"ms": round(ms, 3), "status": r.status, "iterations": r.iterations, "relres": r.relres,
+                     "ms_per_iteration": round(ms / max(r.iterations, 1), 5)}
+        print(f"# jacobi/{name}: {ms:.3f} ms, {r.iterations} iterations", file=sys.stderr, flush=True)
+        del s
+    out["speedup_pcg_over_cg"] = round(out["cg"]["ms"] / out["pcg_jacobi"]["ms"], 3)
+    return out
+
+
 def variant_adjoint(ss, torch, reps: int, tol: float) -> dict:
     from workloads import config
 
@@ -343,8 +371,8 @@ def main() -> int:
     ap.add_argument("--tol", type=float, default=1e-10)
     ap.add_argument("--cpu-iters", type=int, default=150)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--variants", default="mixed,batched,adjoint",
-                    help="comma list of mixed, batched, adjoint; 'none' to skip")
+    ap.add_argument("--variants", default="mixed,batched,adjoint,jacobi",
+                    help="comma list of mixed, batched, adjoint, jacobi; 'none' to skip")
     ap.add_argument("--variant-steps", type=int, default=3)
     ap.add_argument("--no-main", action="store_true",
                     help="profiling aid: skip the main measurement, print only the variants")
@@ -371,7 +399,7 @@ def main() -> int:
     if out is None:
         return 1
     chosen = [v for v in args.variants.split(",") if v and v != "none"]
-    funcs = {"mixed": variant_mixed, "batched": variant_batched, "adjoint": variant_adjoint}
+    funcs = {"mixed": variant_mixed, "batched": variant_batched, "adjoint": variant_adjoint, "jacobi": variant_jacobi}
     if chosen:
         out["variants"] = {}
         for v in chosen:

@@ -141,6 +141,14 @@ typedef void (*ss_free_fn)(void *ctx, void *ptr);
 
 enum { SS_FP64 = 0, SS_FP32_IR = 1, SS_FP32_RU = 2 };
 
+/* Preconditioner M of Algorithm 3. */
+enum {
+    SS_PRECOND_NONE = 0,  /* M = I                                                */
+    SS_PRECOND_JACOBI = 1 /* M = diag(A) (every copy of a node uses the node's
+                             global diagonal entry, which must be positive);
+                             SS_FP64 only                                        */
+};
+
 /* Device storage of the block-diagonal matrix of all local matrices. */
 enum {
     SS_MAT_AUTO = 0, /* SELL-64 unless rows are too uneven, else CSR row tiles */
@@ -166,6 +174,7 @@ typedef struct {
                             1024, 2048, 4096                                  */
     int32_t matrix_format; /* SS_MAT_*                                        */
     int32_t spmv_grid;   /* persistent SpMV workgroups, 0 = tuned default      */
+    int32_t precond;     /* SS_PRECOND_*                                       */
     ss_alloc_fn alloc;   /* device allocator; NULL = hipMalloc                 */
     ss_free_fn free;     /* matching release; NULL = hipFree                   */
     void *alloc_ctx;
@@ -196,7 +205,9 @@ typedef struct {
 int ss_cg_setup(const ss_csr *A, const ss_part *p, const ss_opts *o, void *hip_stream, ss_solver **out);
 
 /*
- * ss_cg_solve -- CG (Algorithm 3, M = I) for A x = b.
+ * ss_cg_solve -- CG (Algorithm 3; M = I, or M = diag(A) with
+ * SS_PRECOND_JACOBI: z = M^{-1} r, alpha = (z, r) / (A p, p),
+ * beta = (r', z') / (r, z), p = z + beta p) for A x = b.
  * b_dev[n], x_dev[n]: device, global numbering; x_dev holds the initial
  * guess x_1 on entry and the solution on return.  Stopping rule (the paper
  * states none): ||r|| <= tol ||b||, with r recomputed as b - A x whenever the

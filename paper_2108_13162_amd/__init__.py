@@ -27,6 +27,7 @@ SS_OK, SS_NOT_CONVERGED, SS_EINVAL, SS_ENOMEM, SS_EDEVICE, SS_EBREAKDOWN, SS_EUN
 SS_PART_BOX, SS_PART_RCB, SS_PART_USER = 0, 1, 2
 SS_FP64, SS_FP32_IR, SS_FP32_RU = 0, 1, 2
 SS_MAT_AUTO, SS_MAT_SELL, SS_MAT_CSR = 0, 1, 2
+SS_PRECOND_NONE, SS_PRECOND_JACOBI = 0, 1
 
 _ALLOC_T = C.CFUNCTYPE(C.c_void_p, C.c_void_p, C.c_size_t)
 _FREE_T = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
@@ -42,6 +43,7 @@ class ss_opts(C.Structure):
                 ("inner_maxit", C.c_int32),
                 ("max_outer", C.c_int32), ("check_every", C.c_int32), ("use_graph", C.c_int32),
                 ("tile_nnz", C.c_int32), ("matrix_format", C.c_int32), ("spmv_grid", C.c_int32),
+                ("precond", C.c_int32),
                 ("alloc", _ALLOC_T), ("free", _FREE_T),
                 ("alloc_ctx", C.c_void_p)]
 

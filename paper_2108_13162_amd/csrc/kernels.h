@@ -23,6 +23,7 @@ enum : int32_t {
 // `status` is accessed with atomic loads / stores inside kernels.
 struct DevState {
     double rr[2];      // (r, r) of the current residual (weighted local dot), by slot
+    double rz[2];      // (r, z), z = M^{-1} r (equal to (r, r) without preconditioner), by slot
     int32_t iter[2];   // completed CG iterations, by slot
     double bb;         // (b, b)
     double tol;        // relative tolerance of the run
@@ -94,13 +95,15 @@ struct Iface {
     int32_t grid;                 // workgroups of the update kernels (multiple of 8)
     const int32_t *pos_grp, *copy_ptr, *copy_pos;
     int32_t ngamma;
+    const double *dinv;           // Jacobi: 1 / a_ii of every position, or nullptr (no preconditioner)
 };
 
-// Partial sums of the two reductions of a CG iteration.
+// Partial sums of the reductions of a CG iteration.
 struct Partials {
-    double *a;  // (p, A_s p), one per SpMV workgroup (count = Mat::grid)
-    double *b;  // (r, r), one per update workgroup (count = Iface::grid)
+    double *a;   // (p, A_s p), one per SpMV workgroup (count = Mat::grid)
+    double *b;   // (r, r), one per update workgroup (count = Iface::grid)
     int32_t na, nb;
+    double *b2;  // (r, z) with the Jacobi preconditioner (same count as b), else nullptr
 };
 
 // ---- launchers (all asynchronous on the given stream) ---------------------
@@ -120,10 +123,11 @@ void launch_spmv(hipStream_t s, const Mat &A, const XT *x, XT *q);
 template <typename VT, typename XT>
 void launch_spmv_first(hipStream_t s, const Mat &A, const XT *pin, const XT *r, XT *pout, XT *q, Partials P,
                        DevState *state);
-// Later CG steps: each workgroup finishes (r, r) from P.b, records the
-// iteration (workgroup 0), tests for convergence, applies the previous
-// iteration's x += alpha pin (also when the run stops here), then
-// pout = r + beta pin, q = A_bd pout, partials -> P.a.
+// Later CG steps: each workgroup finishes (r, r) from P.b (and (r, z) from
+// P.b2 when preconditioned), records the iteration (workgroup 0), tests for
+// convergence, applies the previous iteration's x += alpha pin (also when
+// the run stops here), then pout = r + beta pin (pass z as r when
+// preconditioned), q = A_bd pout, partials -> P.a.
 template <typename VT, typename XT>
 void launch_spmv_step(hipStream_t s, const Mat &A, const XT *pin, const XT *r, XT *pout, XT *q, XT *x, Partials P,
                       DevState *state, int slot);
@@ -133,14 +137,15 @@ template <typename XT>
 void launch_iface_sum(hipStream_t s, const Iface &I, XT *q);
 // Each workgroup finishes (p, A p) from P.a -> alpha (recorded in the state
 // for the next step's x update), then assembly, r -= alpha q and partials
-// (r, r) -> P.b.
+// (r, r) -> P.b; with I.dinv also z = D^{-1} r and (r, z) -> P.b2.
 template <typename XT>
-void launch_update(hipStream_t s, const Iface &I, XT *r, const XT *q, Partials P, DevState *state, int slot);
-// Fresh residual r = b - assemble(q), p0 = r, then one workgroup finishes
-// (r, r) [and (b, b) when `first`] and sets the status.  partial: 2 * I.grid.
+void launch_update(hipStream_t s, const Iface &I, XT *r, XT *z, const XT *q, Partials P, DevState *state, int slot);
+// Fresh residual r = b - assemble(q), z = D^{-1} r (with I.dinv), p0 = z
+// (= r without preconditioner), then one workgroup finishes (r, r), (r, z)
+// [and (b, b) when `first`] and sets the status.  partial: 3 * I.grid.
 template <typename XT>
-void launch_residual(hipStream_t s, const Iface &I, const XT *b, const XT *q, XT *r, XT *p0, double *partial,
-                     DevState *state, bool first);
+void launch_residual(hipStream_t s, const Iface &I, const XT *b, const XT *q, XT *r, XT *z, XT *p0,
+                     double *partial, DevState *state, bool first);
 
 // FP32-value iterative refinement.  ir_prepare: inner right-hand side
 // rin = (XT)(r64 / s) with s = sqrt(outer (r, r)), p0 = rin, d = 0, then one

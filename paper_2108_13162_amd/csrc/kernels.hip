@@ -73,25 +73,29 @@ __device__ __forceinline__ XT pupd(XT r, XT p, double beta)
 
 enum { SPMV_PLAIN = 0, SPMV_FIRST = 1, SPMV_STEP = 2 };
 
-// The CG-step prologue: finish (r, r) of the previous update, record
-// iteration k+1 (workgroup 0), stopping test.  Returns beta, or sets *stop.
-__device__ __forceinline__ double finish_rr(const double *__restrict__ part_b, int nb, int slot, DevState *st,
-                                            double *ws, bool *stop_out)
+// The CG-step prologue: finish (r, r) [and (r, z)] of the previous update,
+// record iteration k+1 (workgroup 0), stopping test on ||r||.  Returns
+// beta = (r, z)_new / (r, z), or sets *stop.  part_b2 = nullptr: no
+// preconditioner, (r, z) = (r, r).
+__device__ __forceinline__ double finish_rr(const double *__restrict__ part_b, const double *__restrict__ part_b2,
+                                            int nb, int slot, DevState *st, double *ws, bool *stop_out)
 {
     const double rr_new = sum_partials_all(part_b, nb, ws);
-    const double rr_cur = st->rr[slot];
+    const double rz_new = part_b2 ? sum_partials_all(part_b2, nb, ws) : rr_new;
+    const double rz_cur = st->rz[slot];
     const int k_new = st->iter[slot] + 1;
     int stop = ST_RUNNING;
-    if (!isfinite(rr_new))
+    if (!isfinite(rr_new) || !isfinite(rz_new))
         stop = ST_BREAKDOWN;
     else if (sqrt(rr_new) <= st->stop)
         stop = ST_CONVERGED;
     else if (k_new >= st->kmax)
         stop = ST_MAXIT;
-    const double beta = rr_new / rr_cur;
+    const double beta = rz_new / rz_cur;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         if (stop != ST_BREAKDOWN) {
             st->rr[slot ^ 1] = rr_new;
+            st->rz[slot ^ 1] = rz_new;
             st->iter[slot ^ 1] = k_new;
             st->rr_last = rr_new;
             st->iter_last = k_new;
@@ -142,7 +146,8 @@ __global__ __launch_bounds__(kBS) void k_spmv_sell(int32_t nrows, int32_t nchunk
                                                    const VT *__restrict__ val, const XT *__restrict__ pin,
                                                    const XT *__restrict__ r, XT *__restrict__ pout,
                                                    XT *__restrict__ q, XT *__restrict__ x, double *__restrict__ part_a,
-                                                   const double *__restrict__ part_b, int32_t nb, int32_t slot,
+                                                   const double *__restrict__ part_b,
+                                                   const double *__restrict__ part_b2, int32_t nb, int32_t slot,
                                                    DevState *__restrict__ st, const int32_t *__restrict__ gate)
 {
     constexpr bool CG = MODE != SPMV_PLAIN;
@@ -178,7 +183,7 @@ __global__ __launch_bounds__(kBS) void k_spmv_sell(int32_t nrows, int32_t nchunk
     if (MODE == SPMV_STEP) {
         alpha = st->alpha;  // x_k = x_{k-1} + alpha p_{k-1}, deferred to here
         bool stop;
-        beta = finish_rr(part_b, nb, slot, st, ws, &stop);
+        beta = finish_rr(part_b, part_b2, nb, slot, st, ws, &stop);
         if (stop) {
             for (int c2 = rb * cpb + w; c2 < cend; c2 += W) {
                 const int rr = cpos[c2] + lane;
@@ -246,8 +251,8 @@ __global__ __launch_bounds__(kBS) void k_spmv_csr(const int32_t *__restrict__ ro
                                                   const XT *__restrict__ r, XT *__restrict__ pout,
                                                   XT *__restrict__ q, XT *__restrict__ x,
                                                   double *__restrict__ part_a, const double *__restrict__ part_b,
-                                                  int32_t nb, int32_t slot, DevState *__restrict__ st,
-                                                  const int32_t *__restrict__ gate)
+                                                  const double *__restrict__ part_b2, int32_t nb, int32_t slot,
+                                                  DevState *__restrict__ st, const int32_t *__restrict__ gate)
 {
     constexpr bool CG = MODE != SPMV_PLAIN;
     constexpr int NI = TN / kBS;
@@ -264,7 +269,7 @@ __global__ __launch_bounds__(kBS) void k_spmv_csr(const int32_t *__restrict__ ro
     if (MODE == SPMV_STEP) {
         alpha = st->alpha;  // x_k = x_{k-1} + alpha p_{k-1}, deferred to here
         bool stop;
-        beta = finish_rr(part_b, nb, slot, st, ws, &stop);
+        beta = finish_rr(part_b, part_b2, nb, slot, st, ws, &stop);
         if (stop) {
             if (rb * tpb < tend)
                 for (int row = tile_row[rb * tpb] + (int)threadIdx.x; row < tile_row[tend]; row += kBS)
@@ -367,8 +372,9 @@ template <typename XT>
 __global__ __launch_bounds__(kBS) void k_update(int32_t n_loc, int32_t n_own, int32_t n_if,
                                                 const int32_t *__restrict__ pos_grp,
                                                 const int32_t *__restrict__ copy_ptr,
-                                                const int32_t *__restrict__ copy_pos, XT *__restrict__ r,
-                                                const XT *__restrict__ q, double *__restrict__ part_b,
+                                                const int32_t *__restrict__ copy_pos, const double *__restrict__ dinv,
+                                                XT *__restrict__ r, XT *__restrict__ z, const XT *__restrict__ q,
+                                                double *__restrict__ part_b, double *__restrict__ part_b2,
                                                 const double *__restrict__ part_a, int32_t na, int32_t slot,
                                                 DevState *__restrict__ st)
 {
@@ -376,23 +382,26 @@ __global__ __launch_bounds__(kBS) void k_update(int32_t n_loc, int32_t n_own, in
     __shared__ double ws[kBS / 64 + 1];
     __shared__ int s_flag;
     if (!running(st, &s_flag)) return;
+    const bool pc = dinv != nullptr;
     const int b0 = (int)blockIdx.x * B;
     // a full batch of interior positions: operands loaded before alpha is known
     const bool plain = b0 >= n_if && b0 + B <= n_loc;
     XT rv[kUI], qv[kUI];
+    double dv[kUI];
     if (plain) {
 #pragma unroll
         for (int i = 0; i < kUI; ++i) {
             const int c = b0 + (int)threadIdx.x + i * kBS;
             rv[i] = r[c];
             qv[i] = q[c];
+            dv[i] = pc ? dinv[c] : 1.0;
         }
     }
 
     // finish (p, A p): alpha, or a breakdown when it is not positive
     const double pAp = sum_partials_all(part_a, na, ws);
     const bool bad = !(pAp > 0.0) || !isfinite(pAp);
-    const double alpha = st->rr[slot] / pAp;
+    const double alpha = st->rz[slot] / pAp;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         st->pAp = pAp;
         st->alpha = alpha;
@@ -400,7 +409,7 @@ __global__ __launch_bounds__(kBS) void k_update(int32_t n_loc, int32_t n_own, in
     }
     if (bad) return;
 
-    double acc = 0.0;
+    double acc = 0.0, acc2 = 0.0;
     if (plain) {
 #pragma unroll
         for (int i = 0; i < kUI; ++i) {
@@ -408,6 +417,11 @@ __global__ __launch_bounds__(kBS) void k_update(int32_t n_loc, int32_t n_own, in
             const XT rc = (XT)((double)rv[i] - alpha * (double)qv[i]);
             r[c] = rc;
             acc = acc + (double)rc * (double)rc;
+            if (pc) {
+                const XT zc = (XT)(dv[i] * (double)rc);
+                z[c] = zc;
+                acc2 = acc2 + (double)rc * (double)zc;
+            }
         }
     } else {
         for (int i = 0; i < kUI; ++i) {
@@ -416,12 +430,22 @@ __global__ __launch_bounds__(kBS) void k_update(int32_t n_loc, int32_t n_own, in
                 const XT qc = c >= n_if ? q[c] : assembled(q, pos_grp[c], copy_ptr, copy_pos);
                 const XT rc = (XT)((double)r[c] - alpha * (double)qc);
                 r[c] = rc;
-                if (c < n_own || c >= n_if) acc = acc + (double)rc * (double)rc;
+                const bool own = c < n_own || c >= n_if;
+                if (own) acc = acc + (double)rc * (double)rc;
+                if (pc) {
+                    const XT zc = (XT)(dinv[c] * (double)rc);
+                    z[c] = zc;
+                    if (own) acc2 = acc2 + (double)rc * (double)zc;
+                }
             }
         }
     }
     const double part = block_sum_all(acc, ws);
     if (threadIdx.x == 0) part_b[blockIdx.x] = part;
+    if (pc) {
+        const double part2 = block_sum_all(acc2, ws);
+        if (threadIdx.x == 0) part_b2[blockIdx.x] = part2;
+    }
 }
 
 // ---- fresh residual r = b - A x (assembly of q = A_bd x included) -----------
@@ -430,14 +454,16 @@ template <typename XT, bool FIRST>
 __global__ __launch_bounds__(kBS) void k_residual(int32_t n_loc, int32_t n_own, int32_t n_if,
                                                   const int32_t *__restrict__ pos_grp,
                                                   const int32_t *__restrict__ copy_ptr,
-                                                  const int32_t *__restrict__ copy_pos, const XT *__restrict__ b,
-                                                  const XT *__restrict__ q, XT *__restrict__ r, XT *__restrict__ p0,
-                                                  double *__restrict__ partial)
+                                                  const int32_t *__restrict__ copy_pos,
+                                                  const double *__restrict__ dinv, const XT *__restrict__ b,
+                                                  const XT *__restrict__ q, XT *__restrict__ r, XT *__restrict__ z,
+                                                  XT *__restrict__ p0, double *__restrict__ partial)
 {
     constexpr int B = kUI * kBS;
     __shared__ double ws[kBS / 64 + 1];
+    const bool pc = dinv != nullptr;
     const int b0 = (int)blockIdx.x * B;
-    double arr = 0.0, abb = 0.0;
+    double arr = 0.0, abb = 0.0, arz = 0.0;
     for (int i = 0; i < kUI; ++i) {
         const int c = b0 + (int)threadIdx.x + i * kBS;
         if (c < n_loc) {
@@ -445,27 +471,37 @@ __global__ __launch_bounds__(kBS) void k_residual(int32_t n_loc, int32_t n_own, 
             const XT bc = b[c];
             const XT rc = bc - qc;
             r[c] = rc;
-            p0[c] = rc;
+            XT zc = rc;
+            if (pc) {
+                zc = (XT)(dinv[c] * (double)rc);
+                z[c] = zc;
+            }
+            p0[c] = zc;
             if (c < n_own || c >= n_if) {
                 arr = arr + (double)rc * (double)rc;
+                if (pc) arz = arz + (double)rc * (double)zc;
                 if (FIRST) abb = abb + (double)bc * (double)bc;
             }
         }
     }
     const double prr = block_sum_all(arr, ws);
     const double pbb = FIRST ? block_sum_all(abb, ws) : 0.0;
+    const double prz = pc ? block_sum_all(arz, ws) : 0.0;
     if (threadIdx.x == 0) {
         partial[blockIdx.x] = prr;
         partial[gridDim.x + blockIdx.x] = pbb;
+        partial[2 * gridDim.x + blockIdx.x] = prz;
     }
 }
 
-// One workgroup: (r, r) [and (b, b)], the stopping test, slot 0 of the state.
-__global__ __launch_bounds__(kBS) void k_finish_residual(DevState *st, const double *partial, int n, int first)
+// One workgroup: (r, r), (r, z) [and (b, b)], the stopping test, slot 0 of
+// the state.
+__global__ __launch_bounds__(kBS) void k_finish_residual(DevState *st, const double *partial, int n, int first, int pc)
 {
     __shared__ double ws[kBS / 64 + 1];
     const double rr = sum_partials_all(partial, n, ws);
     const double bb = first ? sum_partials_all(partial + n, n, ws) : 0.0;
+    const double rz = pc ? sum_partials_all(partial + 2 * n, n, ws) : rr;
     if (threadIdx.x != 0) return;
     if (first) {
         st->bb = bb;
@@ -480,12 +516,13 @@ __global__ __launch_bounds__(kBS) void k_finish_residual(DevState *st, const dou
         }
         st->stop = st->tol * sqrt(bb);
     }
-    if (!isfinite(rr)) {
+    if (!isfinite(rr) || !isfinite(rz)) {
         store_status(st, ST_BREAKDOWN);
         return;
     }
     const int k = st->iter_last;
     st->rr[0] = rr;
+    st->rz[0] = rz;
     st->iter[0] = k;
     st->rr_last = rr;
     if (st->hist && k < st->hist_cap) st->hist[k] = sqrt(rr / st->bb);
@@ -532,6 +569,7 @@ __global__ __launch_bounds__(kBS) void k_ir_start(DevState *in, const DevState *
     if (threadIdx.x != 0) return;
     const int k = outer->iter_last;
     in->rr[0] = rr;
+    in->rz[0] = rr;
     in->iter[0] = k;
     in->rr_last = rr;
     in->iter_last = k;
@@ -599,6 +637,7 @@ __global__ __launch_bounds__(kBS) void k_ru_start_finish(DevState *in, const Dev
     if (threadIdx.x != 0) return;
     const int k = outer->iter_last;
     in->rr[0] = rr;
+    in->rz[0] = rr;
     in->iter[0] = k;
     in->rr_last = rr;
     in->iter_last = k;
@@ -692,6 +731,7 @@ __global__ __launch_bounds__(kBS) void k_ru_refresh_finish(DevState *in, DevStat
         store_status(in, ST_CONVERGED);
     } else {
         in->rr[0] = rr32;
+        in->rz[0] = rr32;
         in->rr_last = rr32;
         in->rref = sqrt(rr64);
     }
@@ -783,7 +823,7 @@ void spmv_dispatch(hipStream_t s, const Mat &A, const XT *pin, const XT *r, XT *
 #define SS_SELL(U)                                                                                               \
     hipLaunchKernelGGL((k_spmv_sell<VT, XT, MODE, U>), grid, block, 0, s, A.nrows, A.nchunks, A.cptr, A.cpos,    \
                        A.clen, A.rlen, A.ccol, A.col, A.col16, A.cbase, (const VT *)A.val, pin, r, pout, q, x, P.a, \
-                       (const double *)P.b, P.nb, slot, st, gate)
+                       (const double *)P.b, (const double *)P.b2, P.nb, slot, st, gate)
         switch (A.unroll) {
         case 5: SS_SELL(5); break;
         case 7: SS_SELL(7); break;
@@ -795,7 +835,8 @@ void spmv_dispatch(hipStream_t s, const Mat &A, const XT *pin, const XT *r, XT *
     }
 #define SS_SPMV(TN)                                                                                              \
     hipLaunchKernelGGL((k_spmv_csr<VT, XT, TN, MODE>), grid, block, 0, s, A.rowptr, A.col, (const VT *)A.val,    \
-                       A.tile_row, A.ntiles, pin, r, pout, q, x, P.a, (const double *)P.b, P.nb, slot, st, gate)
+                       A.tile_row, A.ntiles, pin, r, pout, q, x, P.a, (const double *)P.b, (const double *)P.b2,  \
+                       P.nb, slot, st, gate)
     switch (A.tile_nnz) {
     case 1024: SS_SPMV(1024); break;
     case 4096: SS_SPMV(4096); break;
@@ -850,23 +891,24 @@ void launch_iface_sum(hipStream_t s, const Iface &I, XT *q)
 }
 
 template <typename XT>
-void launch_update(hipStream_t s, const Iface &I, XT *r, const XT *q, Partials P, DevState *st, int slot)
+void launch_update(hipStream_t s, const Iface &I, XT *r, XT *z, const XT *q, Partials P, DevState *st, int slot)
 {
     hipLaunchKernelGGL(k_update<XT>, dim3(I.grid), dim3(kBS), 0, s, I.n_loc, I.n_own, I.n_if, I.pos_grp,
-                       I.copy_ptr, I.copy_pos, r, q, P.b, (const double *)P.a, P.na, slot, st);
+                       I.copy_ptr, I.copy_pos, I.dinv, r, z, q, P.b, P.b2, (const double *)P.a, P.na, slot, st);
 }
 
 template <typename XT>
-void launch_residual(hipStream_t s, const Iface &I, const XT *b, const XT *q, XT *r, XT *p0, double *partial,
+void launch_residual(hipStream_t s, const Iface &I, const XT *b, const XT *q, XT *r, XT *z, XT *p0, double *partial,
                      DevState *st, bool first)
 {
     if (first)
         hipLaunchKernelGGL((k_residual<XT, true>), dim3(I.grid), dim3(kBS), 0, s, I.n_loc, I.n_own, I.n_if,
-                           I.pos_grp, I.copy_ptr, I.copy_pos, b, q, r, p0, partial);
+                           I.pos_grp, I.copy_ptr, I.copy_pos, I.dinv, b, q, r, z, p0, partial);
     else
         hipLaunchKernelGGL((k_residual<XT, false>), dim3(I.grid), dim3(kBS), 0, s, I.n_loc, I.n_own, I.n_if,
-                           I.pos_grp, I.copy_ptr, I.copy_pos, b, q, r, p0, partial);
-    hipLaunchKernelGGL(k_finish_residual, dim3(1), dim3(kBS), 0, s, st, partial, I.grid, first ? 1 : 0);
+                           I.pos_grp, I.copy_ptr, I.copy_pos, I.dinv, b, q, r, z, p0, partial);
+    hipLaunchKernelGGL(k_finish_residual, dim3(1), dim3(kBS), 0, s, st, partial, I.grid, first ? 1 : 0,
+                       I.dinv ? 1 : 0);
 }
 
 void launch_grad_vals(hipStream_t s, const Mat &A, const int32_t *nzmap, const int32_t *l2g, const double *lambda,
@@ -941,9 +983,9 @@ void launch_ru_fold(hipStream_t s, int32_t n_loc, double *x64, XT *d, const DevS
     template void launch_spmv_step<XT, XT>(hipStream_t, const Mat &, const XT *, const XT *, XT *, XT *, XT *,       \
                                            Partials, DevState *, int);                                               \
     template void launch_iface_sum<XT>(hipStream_t, const Iface &, XT *);                                            \
-    template void launch_update<XT>(hipStream_t, const Iface &, XT *, const XT *, Partials, DevState *, int);       \
-    template void launch_residual<XT>(hipStream_t, const Iface &, const XT *, const XT *, XT *, XT *, double *,      \
-                                      DevState *, bool);                                                             \
+    template void launch_update<XT>(hipStream_t, const Iface &, XT *, XT *, const XT *, Partials, DevState *, int); \
+    template void launch_residual<XT>(hipStream_t, const Iface &, const XT *, const XT *, XT *, XT *, XT *,          \
+                                      double *, DevState *, bool);                                                   \
     template void launch_ir_prepare<XT>(hipStream_t, const Iface &, const double *, XT *, XT *, XT *, double *,      \
                                         const DevState *, DevState *, double, int32_t, int32_t);                     \
     template void launch_ir_accumulate<XT>(hipStream_t, int32_t, double *, const XT *, const DevState *, DevState *); \

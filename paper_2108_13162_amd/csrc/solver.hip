@@ -274,6 +274,8 @@ struct ss_solver {
     // FP64 work vectors (device position order)
     double *b = nullptr, *x = nullptr, *r = nullptr, *p0 = nullptr, *p1 = nullptr, *q = nullptr;
     double *part_a = nullptr, *part_b = nullptr, *part_r = nullptr;  // SpMV, update, residual partials
+    // Jacobi preconditioner: 1 / a_ii per position, z = D^{-1} r, (r, z) partials
+    double *dinv = nullptr, *z = nullptr, *part_b2 = nullptr;
     DevState *st = nullptr;
     double *hist = nullptr;
     int32_t hist_cap = 0;
@@ -293,13 +295,14 @@ struct ss_solver {
         bool fp32 = false;
         bool ru = false;  // chunk ends with the gated FP64 residual replacement
         void *x = nullptr, *r = nullptr, *p0 = nullptr, *p1 = nullptr, *q = nullptr;
+        void *z = nullptr;  // preconditioned residual (nullptr: none)
         DevState *st = nullptr;
         hipGraphExec_t exec = nullptr;
         hipGraph_t graph = nullptr;
         int32_t pairs = 0;
     } run64, run32;
 
-    Partials partials() const { return Partials{part_a, part_b, mat.grid, ifc.grid}; }
+    Partials partials() const { return Partials{part_a, part_b, mat.grid, ifc.grid, part_b2}; }
 };
 
 namespace {
@@ -339,8 +342,9 @@ void enqueue_pair_t(ss_solver *s, const ss_solver::Run &R, const Mat &M, hipStre
     const int slot = j & 1;
     XT *pcur = (XT *)(slot ? R.p0 : R.p1);
     XT *pnext = (XT *)(slot ? R.p1 : R.p0);
-    launch_update<XT>(stream, s->ifc, (XT *)R.r, (XT *)R.q, s->partials(), R.st, slot);
-    launch_spmv_step<XT, XT>(stream, M, pcur, (XT *)R.r, pnext, (XT *)R.q, (XT *)R.x, s->partials(), R.st, slot);
+    XT *zr = (XT *)(R.z ? R.z : R.r);  // the vector p is built from: z, or r without preconditioner
+    launch_update<XT>(stream, s->ifc, (XT *)R.r, (XT *)R.z, (XT *)R.q, s->partials(), R.st, slot);
+    launch_spmv_step<XT, XT>(stream, M, pcur, zr, pnext, (XT *)R.q, (XT *)R.x, s->partials(), R.st, slot);
 }
 
 void enqueue_pair(ss_solver *s, const ss_solver::Run &R, hipStream_t stream, int j)
@@ -487,6 +491,20 @@ int ss_cg_setup(const ss_csr *A, const ss_part *p, const ss_opts *o, void *hip_s
         return fail(SS_EINVAL, "unknown precision");
     if (opts.precision == SS_FP32_RU && !(opts.ru_delta >= 0.0 && opts.ru_delta <= 1.0))
         return fail(SS_EINVAL, "ru_delta must be in [0, 1]");
+    if (opts.precond != SS_PRECOND_NONE && opts.precond != SS_PRECOND_JACOBI)
+        return fail(SS_EINVAL, "unknown precond");
+    if (opts.precond == SS_PRECOND_JACOBI && opts.precision != SS_FP64)
+        return fail(SS_EUNSUPPORTED, "the Jacobi preconditioner is available with SS_FP64 only");
+    std::vector<double> diag;
+    if (opts.precond == SS_PRECOND_JACOBI) {
+        diag.assign((size_t)A->n, 0.0);
+        for (int32_t i = 0; i < A->n; ++i)
+            for (int32_t k = A->rowptr[i]; k < A->rowptr[i + 1]; ++k)
+                if (A->colidx[k] == i) diag[i] = A->val[k];
+        for (int32_t i = 0; i < A->n; ++i)
+            if (!(diag[i] > 0.0) || !std::isfinite(diag[i]))
+                return fail(SS_EINVAL, "Jacobi needs a positive diagonal (row " + std::to_string(i) + ")");
+    }
     if (opts.tile_nnz != 0 && opts.tile_nnz != 1024 && opts.tile_nnz != 2048 && opts.tile_nnz != 4096)
         return fail(SS_EINVAL, "tile_nnz must be 0, 1024, 2048 or 4096");
     if (opts.matrix_format < SS_MAT_AUTO || opts.matrix_format > SS_MAT_CSR)
@@ -580,8 +598,16 @@ int ss_cg_setup(const ss_csr *A, const ss_part *p, const ss_opts *o, void *hip_s
         (rc = alloc_dev(s, &s->x, nl)) || (rc = alloc_dev(s, &s->r, nl)) || (rc = alloc_dev(s, &s->p0, nl)) ||
         (rc = alloc_dev(s, &s->p1, nl)) || (rc = alloc_dev(s, &s->q, nl)) || (rc = alloc_dev(s, &s->st, 1)) ||
         (rc = alloc_dev(s, &s->part_a, (size_t)M.grid)) || (rc = alloc_dev(s, &s->part_b, (size_t)I.grid)) ||
-        (rc = alloc_dev(s, &s->part_r, 2 * (size_t)I.grid)))
+        (rc = alloc_dev(s, &s->part_r, 3 * (size_t)I.grid)))
         return bail(rc);
+    if (opts.precond == SS_PRECOND_JACOBI) {
+        std::vector<double> dinv(nl);
+        for (size_t c = 0; c < nl; ++c) dinv[c] = 1.0 / diag[(size_t)L.l2g[c]];
+        if ((rc = upload(s, &s->dinv, dinv.data(), dinv.size())) || (rc = alloc_dev(s, &s->z, nl)) ||
+            (rc = alloc_dev(s, &s->part_b2, (size_t)I.grid)))
+            return bail(rc);
+        I.dinv = s->dinv;
+    }
     if (opts.precision != SS_FP64) {
         std::vector<float> v32(val_st.size());
         for (size_t k = 0; k < v32.size(); ++k) v32[k] = (float)val_st[k];
@@ -612,6 +638,7 @@ int ss_cg_setup(const ss_csr *A, const ss_part *p, const ss_opts *o, void *hip_s
     s->run64.p0 = s->p0;
     s->run64.p1 = s->p1;
     s->run64.q = s->q;
+    s->run64.z = s->z;
     s->run64.st = s->st;
     s->run32.fp32 = true;
     s->run32.ru = opts.precision == SS_FP32_RU;
@@ -670,12 +697,14 @@ int ss_cg_solve(ss_solver *s, const double *b_dev, double *x_dev, double tol, in
             ++restarts;
             // r = b - A x, p = r (Algorithm 3, first line; also the convergence check)
             launch_spmv<double, double>(s->stream, s->mat, s->x, s->q);
-            launch_residual<double>(s->stream, s->ifc, s->b, s->q, s->r, s->p0, s->part_r, s->st, first);
+            launch_residual<double>(s->stream, s->ifc, s->b, s->q, s->r, s->z, s->p0, s->part_r, s->st, first);
             SS_HIP(hipGetLastError());
             if ((rc = read_status(s, s->st, &status)) != SS_OK) return rc;
             if (status != ST_RUNNING) break;
             // p_1 = r_1, A p_1, then (update, step) pairs until the status changes
-            launch_spmv_first<double, double>(s->stream, s->mat, s->p0, s->r, s->p1, s->q, s->partials(), s->st);
+            // p_1 = z_1 (= r_1 without preconditioner)
+            launch_spmv_first<double, double>(s->stream, s->mat, s->p0, s->z ? s->z : s->r, s->p1, s->q,
+                                              s->partials(), s->st);
             if ((rc = iterate(s, s->run64)) != SS_OK) return rc;
             if ((rc = read_status(s, s->st, &status)) != SS_OK) return rc;
             if (status == ST_BREAKDOWN) break;
@@ -687,7 +716,7 @@ int ss_cg_solve(ss_solver *s, const double *b_dev, double *x_dev, double tol, in
         for (bool first = true;; first = false) {
             ++restarts;
             launch_spmv<double, double>(s->stream, s->mat, s->x, s->q);
-            launch_residual<double>(s->stream, s->ifc, s->b, s->q, s->r, s->p0, s->part_r, s->st, first);
+            launch_residual<double>(s->stream, s->ifc, s->b, s->q, s->r, s->z, s->p0, s->part_r, s->st, first);
             SS_HIP(hipGetLastError());
             if ((rc = read_status(s, s->st, &status)) != SS_OK) return rc;
             if (status != ST_RUNNING) break;
@@ -714,7 +743,7 @@ int ss_cg_solve(ss_solver *s, const double *b_dev, double *x_dev, double tol, in
         restarts = 0;
         for (;; ++outer) {
             launch_spmv<double, double>(s->stream, s->mat, s->x, s->q);
-            launch_residual<double>(s->stream, s->ifc, s->b, s->q, s->r, s->p0, s->part_r, s->st, outer == 0);
+            launch_residual<double>(s->stream, s->ifc, s->b, s->q, s->r, s->z, s->p0, s->part_r, s->st, outer == 0);
             SS_HIP(hipGetLastError());
             if ((rc = read_status(s, s->st, &status)) != SS_OK) return rc;
             if (status != ST_RUNNING) break;
@@ -813,6 +842,7 @@ int ss_cg_time_spmv(ss_solver *s, int32_t reps, double *ms_per_launch, double *b
     const DevState saved = *s->st_pinned;
     DevState tmp{};
     tmp.rr[0] = 1.0;
+    tmp.rz[0] = 1.0;
     tmp.iter[0] = 0;
     tmp.bb = 1.0;
     tmp.stop = 0.0;
@@ -832,6 +862,7 @@ int ss_cg_time_spmv(ss_solver *s, int32_t reps, double *ms_per_launch, double *b
         SS_HIP(hipMemcpyAsync(s->r, ones.data(), sizeof(double) * nl, hipMemcpyHostToDevice, s->stream));
     }
     SS_HIP(hipMemcpyAsync(P.b, ones.data(), sizeof(double) * (size_t)P.nb, hipMemcpyHostToDevice, s->stream));
+    if (P.b2) SS_HIP(hipMemcpyAsync(P.b2, ones.data(), sizeof(double) * (size_t)P.nb, hipMemcpyHostToDevice, s->stream));
     auto launch = [&]() {
         if (f32)
             launch_spmv_step<float, float>(s->stream, s->mat32, s->p32b, s->r32, s->p32a, s->q32, s->d32, P, st, 0);

@@ -1,0 +1,151 @@
+"""Jacobi-preconditioned sub-structured CG (Algorithm 3 with M = diag A,
+SS_PRECOND_JACOBI) against the oracle's PCG, through the C-ABI.
+
+The SpMV, the assembly and z = D^{-1} r are evaluated in the oracle's order
+and rounding; only the dot-product summation orders differ."""
+import numpy as np
+import pytest
+
+import oracle as O
+import paper_2108_13162_amd as ss
+from workloads import CSR, config, diffusion3d_lognormal, uniform_rhs
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def _t(a):
+    return torch.tensor(np.ascontiguousarray(a, dtype=np.float64), device=DEV)
+
+
+def _pcg(A, p, **kw):
+    return ss.ss_cg_setup(A, p, ss.default_opts(precond=ss.SS_PRECOND_JACOBI, **kw))
+
+
+@pytest.fixture(scope="module")
+def cases():
+    out = []
+    M = 13
+    A = diffusion3d_lognormal(M, seed=3, sigma=1.0)
+    out.append(("lognormal13_box2x2x2", A, ss.ss_partition(A, ss.SS_PART_BOX, 8, grid=(M, M, M), boxes=(2, 2, 2)),
+                O.split(A.rowptr, A.colidx, O.box_partition((M, M, M), (2, 2, 2)), 8)))
+    w = config(3, size=16)
+    out.append(("q1hex16_rcb16", w.A, ss.partition_workload(w),
+                O.split(w.A.rowptr, w.A.colidx, O.rcb_partition(w.coords, w.weights), 16)))
+    return out
+
+
+@pytest.mark.parametrize("k", [1, 10])
+def test_fixed_k_iterates(cases, k):
+    # bar as for plain CG: 1e-12 relative or 10x the oracle's own spread
+    # (global vs sub-structured PCG, which differ in dot summation order only)
+    for name, A, p, sd in cases:
+        b = uniform_rhs(A.n, 7)
+        s = _pcg(A, p)
+        x = torch.zeros(A.n, dtype=torch.float64, device=DEV)
+        r = ss.ss_cg_solve(s, _t(b), x, tol=0.0, maxit=k, hist=True)
+        xo, ro = O.ss_pcg(A, sd, b, tol=0.0, maxit=k)
+        xg_, rg_ = O.pcg(A, b, tol=0.0, maxit=k)
+        assert r.status == ss.SS_NOT_CONVERGED and r.iterations == k == ro.iterations, name
+        spread = np.linalg.norm(xg_ - xo) / np.linalg.norm(xo)
+        dx = np.linalg.norm(x.cpu().numpy() - xo) / np.linalg.norm(xo)
+        dh = np.max(np.abs(r.hist - ro.hist) / ro.hist)
+        print(f"{name} k={k}: gpu-oracle {dx:.2e} hist {dh:.2e}; oracle spread {spread:.2e}")
+        assert dx <= max(1e-12, 10 * spread), (name, dx, spread)
+
+
+def test_solve_to_tolerance(cases):
+    for name, A, p, sd in cases:
+        b = uniform_rhs(A.n, 11)
+        s = _pcg(A, p)
+        x = torch.zeros(A.n, dtype=torch.float64, device=DEV)
+        r = ss.ss_cg_solve(s, _t(b), x, tol=1e-10, maxit=5000, hist=True)
+        xo, ro = O.ss_pcg(A, sd, b, tol=1e-10, maxit=5000)
+        _, rcg = O.ss_cg(A, sd, b, tol=1e-10, maxit=5000)
+        xg = x.cpu().numpy()
+        assert r.status == ss.SS_OK, name
+        assert abs(r.iterations - ro.iterations) <= 2, (name, r.iterations, ro.iterations)
+        true = np.linalg.norm(b - O.csr_matvec(A, xg)) / np.linalg.norm(b)
+        assert true <= 1e-10 and abs(r.relres - true) <= 1e-3 * true, (name, r.relres, true)
+        xref = O.solve_reference(A, b)
+        err = np.linalg.norm(xg - xref) / np.linalg.norm(xref)
+        err_o = np.linalg.norm(xo - xref) / np.linalg.norm(xref)
+        print(f"{name}: PCG {r.iterations} (oracle {ro.iterations}, plain CG {rcg.iterations}), error {err:.2e}")
+        assert err <= max(1e-9, 2 * err_o), (name, err, err_o)
+        assert r.iterations < rcg.iterations
+
+
+def test_deterministic_and_graph_eager_identical(cases):
+    name, A, p, sd = cases[0]
+    b = _t(uniform_rhs(A.n, 12))
+    out = []
+    for g in (1, 1, 0):
+        s = _pcg(A, p, use_graph=g)
+        x = torch.zeros(A.n, dtype=torch.float64, device=DEV)
+        r = ss.ss_cg_solve(s, b, x, tol=1e-10, maxit=5000, hist=True)
+        out.append((x.cpu().numpy(), r.iterations, r.hist))
+    for o in out[1:]:
+        assert np.array_equal(o[0], out[0][0]) and o[1] == out[0][1] and np.array_equal(o[2], out[0][2])
+
+
+def test_subdomain_independence():
+    M = 12
+    A = diffusion3d_lognormal(M, seed=5, sigma=1.0)
+    b = uniform_rhs(A.n, 13)
+    its = []
+    for boxes in [(1, 1, 1), (2, 2, 1), (2, 2, 2), (3, 2, 2)]:
+        P = int(np.prod(boxes))
+        s = _pcg(A, ss.ss_partition(A, ss.SS_PART_BOX, P, grid=(M, M, M), boxes=boxes))
+        x = torch.zeros(A.n, dtype=torch.float64, device=DEV)
+        r = ss.ss_cg_solve(s, _t(b), x, tol=1e-10, maxit=5000)
+        assert r.status == ss.SS_OK
+        its.append(r.iterations)
+    assert max(its) - min(its) <= 2, its
+
+
+def test_pcg_edge_cases():
+    M = 7
+    A = diffusion3d_lognormal(M, seed=3, sigma=0.5)
+    p = ss.ss_partition(A, ss.SS_PART_BOX, 8, grid=(M, M, M), boxes=(2, 2, 2))
+    s = _pcg(A, p)
+    x = torch.ones(A.n, dtype=torch.float64, device=DEV)
+    r = ss.ss_cg_solve(s, torch.zeros(A.n, dtype=torch.float64, device=DEV), x)
+    assert r.status == ss.SS_OK and r.iterations == 0 and not x.cpu().numpy().any()
+    bn = uniform_rhs(A.n, 2)
+    bn[0] = np.nan
+    r = ss.ss_cg_solve(s, _t(bn), torch.zeros(A.n, dtype=torch.float64, device=DEV))
+    assert r.status == ss.SS_EBREAKDOWN
+    # a diagonal matrix: one step (M = A)
+    n = 40
+    d = np.linspace(0.5, 9.0, n)
+    D = CSR(n, np.arange(n + 1, dtype=np.int32), np.arange(n, dtype=np.int32), d)
+    pd = ss.ss_partition(D, ss.SS_PART_USER, 3, user_part=np.arange(n) % 3)
+    sd = _pcg(D, pd)
+    bd = uniform_rhs(n, 4)
+    x = torch.zeros(n, dtype=torch.float64, device=DEV)
+    r = ss.ss_cg_solve(sd, _t(bd), x, tol=1e-14)
+    assert r.status == ss.SS_OK and r.iterations == 1
+    assert np.allclose(x.cpu().numpy(), bd / d, rtol=1e-15)
+    # no positive diagonal -> rejected; only FP64
+    Z = CSR(A.n, A.rowptr.copy(), A.colidx.copy(), A.val.copy())
+    rows = Z.row_of_nz()
+    Z.val[int(np.nonzero((rows == 3) & (Z.colidx == 3))[0][0])] = 0.0
+    with pytest.raises(ss.SSError):
+        _pcg(Z, ss.ss_partition(Z, ss.SS_PART_BOX, 8, grid=(M, M, M), boxes=(2, 2, 2)))
+    with pytest.raises(ss.SSError):
+        _pcg(A, p, precision=ss.SS_FP32_RU)
+
+
+def test_full_size_cfg2_pcg():
+    # 128^3 lognormal diffusion, 8 boxes: Jacobi cuts the iteration count
+    w = config(2)
+    A, b = w.A, w.b
+    s = _pcg(A, ss.partition_workload(w))
+    x = torch.zeros(A.n, dtype=torch.float64, device=DEV)
+    r = ss.ss_cg_solve(s, _t(b), x, tol=1e-10, maxit=100000)
+    xg = x.cpu().numpy()
+    true = np.linalg.norm(b - O.csr_matvec(A, xg)) / np.linalg.norm(b)
+    print(f"cfg2 PCG: {r.iterations} iterations, true relres {true:.2e}")
+    assert r.status == ss.SS_OK and true <= 1e-10
+    assert abs(r.iterations - 686) <= 14  # oracle: 686
