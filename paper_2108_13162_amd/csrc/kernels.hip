@@ -64,6 +64,61 @@ __device__ __forceinline__ double sum_partials_all(const double *__restrict__ pa
     return block_sum_all(v, ws);
 }
 
+// Sum of n partials at a 16-byte aligned address, 16 values per thread in
+// flight per round: thread t adds the pairs t, t + kBS, ... (each pair's two
+// values in order), thread 0 the odd last value, then the workgroup tree.
+// A fixed order, so every workgroup obtains the same bits.
+__device__ __forceinline__ double sum_partials_vec(const double *__restrict__ partial, int n)
+{
+    const double2 *p2 = reinterpret_cast<const double2 *>(partial);
+    const int npair = n >> 1;
+    double v = 0.0;
+    for (int base = 0; base < npair; base += 8 * kBS) {
+        double2 t[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const int idx = base + i * kBS + (int)threadIdx.x;
+            t[i] = idx < npair ? p2[idx] : make_double2(0.0, 0.0);
+        }
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            v = v + t[i].x;
+            v = v + t[i].y;
+        }
+    }
+    if ((n & 1) && threadIdx.x == 0) v = v + partial[n - 1];
+    return v;
+}
+
+// Two fixed-order workgroup sums in one pass (each with exactly the order of
+// block_sum_all).  ws: 2 * (kBS/64) + 2 slots.
+__device__ __forceinline__ void block_sum2_all(double &a, double &b, double *ws)
+{
+    constexpr int W = kBS / 64;
+    a = wave_sum(a);
+    b = wave_sum(b);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0) {
+        ws[w] = a;
+        ws[W + w] = b;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double ta = 0.0, tb = 0.0;
+#pragma unroll
+        for (int i = 0; i < W; ++i) {
+            ta = ta + ws[i];
+            tb = tb + ws[W + i];
+        }
+        ws[2 * W] = ta;
+        ws[2 * W + 1] = tb;
+    }
+    __syncthreads();
+    a = ws[2 * W];
+    b = ws[2 * W + 1];
+    __syncthreads();
+}
+
 // p_k = r_k + beta p_{k-1}, evaluated in FP64 and rounded to the vector type.
 template <typename XT>
 __device__ __forceinline__ XT pupd(XT r, XT p, double beta)
@@ -80,8 +135,15 @@ enum { SPMV_PLAIN = 0, SPMV_FIRST = 1, SPMV_STEP = 2 };
 __device__ __forceinline__ double finish_rr(const double *__restrict__ part_b, const double *__restrict__ part_b2,
                                             int nb, int slot, DevState *st, double *ws, bool *stop_out)
 {
-    const double rr_new = sum_partials_all(part_b, nb, ws);
-    const double rz_new = part_b2 ? sum_partials_all(part_b2, nb, ws) : rr_new;
+    double rr_new, rz_new;
+    if (part_b2) {
+        rr_new = sum_partials_vec(part_b, nb);
+        rz_new = sum_partials_vec(part_b2, nb);
+        block_sum2_all(rr_new, rz_new, ws);
+    } else {
+        rr_new = block_sum_all(sum_partials_vec(part_b, nb), ws);
+        rz_new = rr_new;
+    }
     const double rz_cur = st->rz[slot];
     const int k_new = st->iter[slot] + 1;
     int stop = ST_RUNNING;
@@ -152,7 +214,7 @@ __global__ __launch_bounds__(kBS) void k_spmv_sell(int32_t nrows, int32_t nchunk
 {
     constexpr bool CG = MODE != SPMV_PLAIN;
     constexpr int W = kBS / 64;
-    __shared__ double ws[kBS / 64 + 1];
+    __shared__ double ws[2 * (kBS / 64) + 2];
     __shared__ int s_flag;
     if (gate && dev::flag_load(gate) == 0) return;
     if (CG && !running(st, &s_flag)) return;
@@ -258,7 +320,7 @@ __global__ __launch_bounds__(kBS) void k_spmv_csr(const int32_t *__restrict__ ro
     constexpr int NI = TN / kBS;
     __shared__ XT prod[TN];
     __shared__ XT wsx[kBS / 64 + 1];
-    __shared__ double ws[kBS / 64 + 1];
+    __shared__ double ws[2 * (kBS / 64) + 2];
     __shared__ int s_flag;
     if (gate && dev::flag_load(gate) == 0) return;
     if (CG && !running(st, &s_flag)) return;
@@ -379,7 +441,7 @@ __global__ __launch_bounds__(kBS) void k_update(int32_t n_loc, int32_t n_own, in
                                                 DevState *__restrict__ st)
 {
     constexpr int B = kUI * kBS;
-    __shared__ double ws[kBS / 64 + 1];
+    __shared__ double ws[2 * (kBS / 64) + 2];
     __shared__ int s_flag;
     if (!running(st, &s_flag)) return;
     const bool pc = dinv != nullptr;
@@ -399,7 +461,7 @@ __global__ __launch_bounds__(kBS) void k_update(int32_t n_loc, int32_t n_own, in
     }
 
     // finish (p, A p): alpha, or a breakdown when it is not positive
-    const double pAp = sum_partials_all(part_a, na, ws);
+    const double pAp = block_sum_all(sum_partials_vec(part_a, na), ws);
     const bool bad = !(pAp > 0.0) || !isfinite(pAp);
     const double alpha = st->rz[slot] / pAp;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -440,11 +502,15 @@ __global__ __launch_bounds__(kBS) void k_update(int32_t n_loc, int32_t n_own, in
             }
         }
     }
-    const double part = block_sum_all(acc, ws);
-    if (threadIdx.x == 0) part_b[blockIdx.x] = part;
     if (pc) {
-        const double part2 = block_sum_all(acc2, ws);
-        if (threadIdx.x == 0) part_b2[blockIdx.x] = part2;
+        block_sum2_all(acc, acc2, ws);
+        if (threadIdx.x == 0) {
+            part_b[blockIdx.x] = acc;
+            part_b2[blockIdx.x] = acc2;
+        }
+    } else {
+        const double part = block_sum_all(acc, ws);
+        if (threadIdx.x == 0) part_b[blockIdx.x] = part;
     }
 }
 
@@ -460,7 +526,7 @@ __global__ __launch_bounds__(kBS) void k_residual(int32_t n_loc, int32_t n_own, 
                                                   XT *__restrict__ p0, double *__restrict__ partial)
 {
     constexpr int B = kUI * kBS;
-    __shared__ double ws[kBS / 64 + 1];
+    __shared__ double ws[2 * (kBS / 64) + 2];
     const bool pc = dinv != nullptr;
     const int b0 = (int)blockIdx.x * B;
     double arr = 0.0, abb = 0.0, arz = 0.0;
@@ -498,7 +564,7 @@ __global__ __launch_bounds__(kBS) void k_residual(int32_t n_loc, int32_t n_own, 
 // the state.
 __global__ __launch_bounds__(kBS) void k_finish_residual(DevState *st, const double *partial, int n, int first, int pc)
 {
-    __shared__ double ws[kBS / 64 + 1];
+    __shared__ double ws[2 * (kBS / 64) + 2];
     const double rr = sum_partials_all(partial, n, ws);
     const double bb = first ? sum_partials_all(partial + n, n, ws) : 0.0;
     const double rz = pc ? sum_partials_all(partial + 2 * n, n, ws) : rr;
@@ -543,7 +609,7 @@ __global__ __launch_bounds__(kBS) void k_ir_prepare(int32_t n_loc, int32_t n_own
                                                     double *__restrict__ partial, const DevState *__restrict__ outer)
 {
     constexpr int B = kUI * kBS;
-    __shared__ double ws[kBS / 64 + 1];
+    __shared__ double ws[2 * (kBS / 64) + 2];
     const double sc = sqrt(outer->rr_last);
     const int b0 = (int)blockIdx.x * B;
     double acc = 0.0;
@@ -564,7 +630,7 @@ __global__ __launch_bounds__(kBS) void k_ir_prepare(int32_t n_loc, int32_t n_own
 __global__ __launch_bounds__(kBS) void k_ir_start(DevState *in, const DevState *outer, const double *partial, int n,
                                                   double inner_tol, int32_t inner_maxit, int32_t maxit)
 {
-    __shared__ double ws[kBS / 64 + 1];
+    __shared__ double ws[2 * (kBS / 64) + 2];
     const double rr = sum_partials_all(partial, n, ws);
     if (threadIdx.x != 0) return;
     const int k = outer->iter_last;
@@ -613,7 +679,7 @@ __global__ __launch_bounds__(kBS) void k_ru_start(int32_t n_loc, int32_t n_own, 
                                                   XT *__restrict__ d, double *__restrict__ partial)
 {
     constexpr int B = kUI * kBS;
-    __shared__ double ws[kBS / 64 + 1];
+    __shared__ double ws[2 * (kBS / 64) + 2];
     const int b0 = (int)blockIdx.x * B;
     double acc = 0.0;
     for (int i = 0; i < kUI; ++i) {
@@ -632,7 +698,7 @@ __global__ __launch_bounds__(kBS) void k_ru_start(int32_t n_loc, int32_t n_own, 
 __global__ __launch_bounds__(kBS) void k_ru_start_finish(DevState *in, const DevState *outer, const double *partial,
                                                          int n, double delta)
 {
-    __shared__ double ws[kBS / 64 + 1];
+    __shared__ double ws[2 * (kBS / 64) + 2];
     const double rr = sum_partials_all(partial, n, ws);
     if (threadIdx.x != 0) return;
     const int k = outer->iter_last;
@@ -683,7 +749,7 @@ __global__ __launch_bounds__(kBS) void k_ru_residual(int32_t n_loc, int32_t n_ow
                                                      double *__restrict__ partial, const DevState *__restrict__ in)
 {
     constexpr int B = kUI * kBS;
-    __shared__ double ws[kBS / 64 + 1];
+    __shared__ double ws[2 * (kBS / 64) + 2];
     if (dev::flag_load(&in->refresh) == 0) return;
     const int b0 = (int)blockIdx.x * B;
     double a64 = 0.0, a32 = 0.0;
@@ -713,7 +779,7 @@ __global__ __launch_bounds__(kBS) void k_ru_residual(int32_t n_loc, int32_t n_ow
 // the same search direction.
 __global__ __launch_bounds__(kBS) void k_ru_refresh_finish(DevState *in, DevState *outer, const double *partial, int n)
 {
-    __shared__ double ws[kBS / 64 + 1];
+    __shared__ double ws[2 * (kBS / 64) + 2];
     __shared__ int32_t go;
     if (threadIdx.x == 0) go = dev::flag_load(&in->refresh);
     __syncthreads();
