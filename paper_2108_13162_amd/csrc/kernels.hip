@@ -217,7 +217,8 @@ __global__ __launch_bounds__(kBS) void k_spmv_sell(int32_t nrows, int32_t nchunk
     __shared__ double ws[2 * (kBS / 64) + 2];
     __shared__ int s_flag;
     if (gate && dev::flag_load(gate) == 0) return;
-    if (CG && !running(st, &s_flag)) return;
+    // the status word is read while the first matrix loads are in flight
+    if (CG && threadIdx.x == 0) s_flag = load_status(st);
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int rb = xcd_remap(blockIdx.x, gridDim.x);
     const int cpb = (nchunks + (int)gridDim.x - 1) / (int)gridDim.x;
@@ -240,6 +241,10 @@ __global__ __launch_bounds__(kBS) void k_spmv_sell(int32_t nrows, int32_t nchunk
 #pragma unroll
             for (int u = 0; u < U; ++u) vv[u] = val[base + min(u, L - 1) * 64 + lane];
         }
+    }
+    if (CG) {
+        __syncthreads();
+        if (s_flag != ST_RUNNING) return;
     }
     double beta = 0.0, alpha = 0.0;
     if (MODE == SPMV_STEP) {
@@ -443,7 +448,8 @@ __global__ __launch_bounds__(kBS) void k_update(int32_t n_loc, int32_t n_own, in
     constexpr int B = kUI * kBS;
     __shared__ double ws[2 * (kBS / 64) + 2];
     __shared__ int s_flag;
-    if (!running(st, &s_flag)) return;
+    // the status word is read while the first operand loads are in flight
+    if (threadIdx.x == 0) s_flag = load_status(st);
     const bool pc = dinv != nullptr;
     const int b0 = (int)blockIdx.x * B;
     // a full batch of interior positions: operands loaded before alpha is known
@@ -459,6 +465,8 @@ __global__ __launch_bounds__(kBS) void k_update(int32_t n_loc, int32_t n_own, in
             dv[i] = pc ? dinv[c] : 1.0;
         }
     }
+    __syncthreads();
+    if (s_flag != ST_RUNNING) return;
 
     // finish (p, A p): alpha, or a breakdown when it is not positive
     const double pAp = block_sum_all(sum_partials_vec(part_a, na), ws);
