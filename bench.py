@@ -197,11 +197,11 @@ def variant_batched(ss, torch, reps: int, tol: float, one_by_one: bool = True) -
                                            "worst": round(max(t[1] for t in trials), 5), "count": len(trials)},
     }
     # algorithmic bytes: every iteration of a system while any of its pairs runs
-    # reads the matrix once (12 B per entry + 1 B row length) and moves 10
-    # vector values of 8 B per row and right-hand side (SpMV: r and p read
-    # once, p and q written; update: x, p, r, q read, x and r written)
+    # reads the matrix once (12 B per entry + 1 B row length) and moves 9
+    # vector values of 8 B per row and right-hand side (CG step: r, p, x read
+    # once, p, q, x written; update: r, q read, r written)
     per_sys_its = its.reshape(len(S), nrhs).max(axis=1)
-    nbytes = sum(int(k) * (12 * A.nnz + A.n + 80 * nrhs * A.n) for k, A in zip(per_sys_its, S))
+    nbytes = sum(int(k) * (12 * A.nnz + A.n + 72 * nrhs * A.n) for k, A in zip(per_sys_its, S))
     out["algorithmic_bytes"] = nbytes
     out["effective_gbps"] = round(nbytes / (ms_b * 1e-3) / 1e9, 1)
     if not one_by_one:

@@ -17,9 +17,10 @@
 // have a running pair (a device-side list, rebuilt at the end of every polled
 // chunk of iterations):
 //   k_bupdate: (p, A p) of the system from its granule partials -> alpha per
-//              pair, x += alpha p, r -= alpha q, granule partials of (r, r);
-//   k_bspmv:   (r, r) -> stopping test and beta per pair, p = r + beta p on
-//              the fly, q = A p, granule partials of (p, A p).
+//              pair, r -= alpha q, granule partials of (r, r);
+//   k_bspmv:   (r, r) -> stopping test and beta per pair, x += alpha p of the
+//              previous update for the tile's own rows (it reads p anyway),
+//              p = r + beta p on the fly, q = A p, granule partials of (p, A p).
 // Every workgroup of a system computes the system's scalars itself from the
 // same partials in the same order (bitwise equal everywhere); the workgroup
 // of the system's first tile records them.  A pair that stops freezes its x
@@ -85,6 +86,7 @@ struct BState {
     int32_t *it_last, *status, *restarts;
     int32_t *nrun;        // pairs still running (device)
     const int32_t *kmax;  // iteration limit (device)
+    double *alpha;        // alpha of the last update per pair (0 for a stopped pair)
 };
 
 __device__ __forceinline__ double *rr_slot(const BState &S, int slot) { return slot ? S.rr1 : S.rr0; }
@@ -233,11 +235,29 @@ __device__ __forceinline__ Share list_share(int nact)
 // LDS ring of W rows, sliding granule by granule through its tile, so every
 // vector row is read from memory once per tile (plus the 2h halo rows) and
 // the column gathers are LDS reads.  Other systems gather from memory.
+// x += alpha p of the previous update (per right-hand side) for rows
+// [r0, r1), in row layout.
+template <int NR>
+__device__ __forceinline__ void x_update_rows(double *__restrict__ x, const double *__restrict__ p, int r0, int r1,
+                                              const double (&al)[NR])
+{
+    for (int row = r0 + (int)threadIdx.x; row < r1; row += kWG) {
+        double xv[NR], pv[NR];
+        ld_row<NR>(x, row, xv);
+        ld_row<NR>(p, row, pv);
+#pragma unroll
+        for (int j = 0; j < NR; ++j)
+            if (al[j] != 0.0) xv[j] = xv[j] + al[j] * pv[j];
+        st_row<NR>(x, row, xv);
+    }
+}
+
 template <int NR, int U, int MODE, bool ALL_STAGED>
 __global__ __launch_bounds__(kWG) void k_bspmv(BMat M, BTiles T, BState S, const double *__restrict__ pin,
                                                const double *__restrict__ r, double *__restrict__ pout,
-                                               double *__restrict__ q, double *__restrict__ part_a,
-                                               const double *__restrict__ part_b, int slot)
+                                               double *__restrict__ q, double *__restrict__ x,
+                                               double *__restrict__ part_a, const double *__restrict__ part_b,
+                                               int slot)
 {
     constexpr bool CG = MODE != M_PLAIN;
     constexpr int W = kRingBytes / (8 * NR);  // ring rows (power of two)
@@ -253,8 +273,23 @@ __global__ __launch_bounds__(kWG) void k_bspmv(BMat M, BTiles T, BState S, const
         double beta[NR];
 #pragma unroll
         for (int j = 0; j < NR; ++j) beta[j] = 0.0;
+        // alpha of the previous update (0 for a pair that did not run in it):
+        // the x += alpha p that update left to this step
+        double al[NR];
+        bool xupd = false;
+#pragma unroll
+        for (int j = 0; j < NR; ++j) {
+            al[j] = MODE == M_STEP ? S.alpha[s * NR + j] : 0.0;
+            xupd = xupd || al[j] != 0.0;
+        }
+        const int own0 = M.crow[T.gran_c0[T.tile_g0[t]]], own1 = M.crow[T.gran_c0[T.tile_g0[t + 1]]];
         if (CG) {
-            if (!load_sys_status<NR>(S, s, sh_st)) continue;
+            // (the statuses may already show this step's stops, recorded by
+            // the system's first tile: the x update is owed all the same)
+            if (!load_sys_status<NR>(S, s, sh_st)) {
+                if (MODE == M_STEP && xupd) x_update_rows<NR>(x, pin, own0, own1, al);
+                continue;
+            }
             bool any = false;
             if (MODE == M_STEP) {
                 double rrn[NR];
@@ -295,7 +330,11 @@ __global__ __launch_bounds__(kWG) void k_bspmv(BMat M, BTiles T, BState S, const
             } else {
                 any = true;
             }
-            if (!any) continue;
+            if (!any) {
+                // every pair stops here: the previous update's x still lands
+                if (MODE == M_STEP && xupd) x_update_rows<NR>(x, pin, own0, own1, al);
+                continue;
+            }
         }
         const int g0 = T.tile_g0[t], g1 = T.tile_g0[t + 1];
         const int h = T.sys_h[s];
@@ -336,6 +375,14 @@ __global__ __launch_bounds__(kWG) void k_bspmv(BMat M, BTiles T, BState S, const
                         ld_row<NR>(pin, row, pv);
 #pragma unroll
                         for (int j = 0; j < NR; ++j) v[j] = rv[j] + beta[j] * pv[j];
+                        if (row >= own0 && row < own1) {
+                            double xv[NR];
+                            ld_row<NR>(x, row, xv);
+#pragma unroll
+                            for (int j = 0; j < NR; ++j)
+                                if (al[j] != 0.0) xv[j] = xv[j] + al[j] * pv[j];
+                            st_row<NR>(x, row, xv);
+                        }
                     }
                     st_row<NR>(ring, row & (W - 1), v);
                 }
@@ -418,6 +465,14 @@ __global__ __launch_bounds__(kWG) void k_bspmv(BMat M, BTiles T, BState S, const
                             ld_row<NR>(pin, row, pv);
 #pragma unroll
                             for (int j = 0; j < NR; ++j) pr[j] = rv[j] + beta[j] * pv[j];
+                            if (MODE == M_STEP) {
+                                double xv[NR];
+                                ld_row<NR>(x, row, xv);
+#pragma unroll
+                                for (int j = 0; j < NR; ++j)
+                                if (al[j] != 0.0) xv[j] = xv[j] + al[j] * pv[j];
+                                st_row<NR>(x, row, xv);
+                            }
                         }
                         st_row<NR>(pout, row, pr);
 #pragma unroll
@@ -436,8 +491,7 @@ __global__ __launch_bounds__(kWG) void k_bspmv(BMat M, BTiles T, BState S, const
 // ---- alpha + x / r update + (r, r) partials ----------------------------------
 
 template <int NR>
-__global__ __launch_bounds__(kWG) void k_bupdate(BMat M, BTiles T, BState S, double *__restrict__ x,
-                                                 const double *__restrict__ p, double *__restrict__ r,
+__global__ __launch_bounds__(kWG) void k_bupdate(BMat M, BTiles T, BState S, double *__restrict__ r,
                                                  const double *__restrict__ q, double *__restrict__ part_b,
                                                  const double *__restrict__ part_a, int slot)
 {
@@ -449,18 +503,20 @@ __global__ __launch_bounds__(kWG) void k_bupdate(BMat M, BTiles T, BState S, dou
     for (int i = sh.i; i < sh.end; i += sh.step) {
         const int t = T.list[i];
         const int s = T.tile_sys[t];
-        if (!load_sys_status<NR>(S, s, sh_st)) continue;
+        if (!load_sys_status<NR>(S, s, sh_st)) {
+            // nothing ran: the next step owes no x update for this system
+            if (T.tile_g0[t] == T.sys_g0[s] && threadIdx.x < NR) S.alpha[s * NR + threadIdx.x] = 0.0;
+            continue;
+        }
         const int g0 = T.tile_g0[t], g1 = T.tile_g0[t + 1];
         // operands of the first granule, loaded before alpha is known
-        double xv[NI], pv[NI], rv[NI], qv[NI];
+        double rv[NI], qv[NI];
         int e0 = M.crow[T.gran_c0[g0]] * NR, e1 = M.crow[T.gran_c0[g0 + 1]] * NR;
         bool full = e1 - e0 == kGranRows * NR;
         if (full) {
 #pragma unroll
             for (int k = 0; k < NI; ++k) {
                 const int e = e0 + (int)threadIdx.x + k * kWG;
-                xv[k] = x[e];
-                pv[k] = p[e];
                 rv[k] = r[e];
                 qv[k] = q[e];
             }
@@ -474,18 +530,21 @@ __global__ __launch_bounds__(kWG) void k_bupdate(BMat M, BTiles T, BState S, dou
         for (int j = 0; j < NR; ++j) {
             alpha[j] = 0.0;
             runv[j] = 0.0;
-            if (sh_st[j] != BS_RUNNING) continue;
-            const int pr = s * NR + j;
-            if (!(pAp[j] > 0.0) || !isfinite(pAp[j])) {
-                if (lead) {
-                    dev::flag_store(&S.status[pr], BS_BREAKDOWN);
-                    atomicSub(S.nrun, 1);
+            if (sh_st[j] == BS_RUNNING) {
+                const int pr = s * NR + j;
+                if (!(pAp[j] > 0.0) || !isfinite(pAp[j])) {
+                    if (lead) {
+                        dev::flag_store(&S.status[pr], BS_BREAKDOWN);
+                        atomicSub(S.nrun, 1);
+                    }
+                } else {
+                    alpha[j] = rrc[pr] / pAp[j];
+                    runv[j] = 1.0;
+                    any = true;
                 }
-                continue;
             }
-            alpha[j] = rrc[pr] / pAp[j];
-            runv[j] = 1.0;
-            any = true;
+            // the next CG step applies x += alpha p with these (0: no change)
+            if (lead) S.alpha[s * NR + j] = alpha[j];
         }
         if (!any) continue;
         const double a = pick<NR>(alpha, jt);
@@ -499,8 +558,6 @@ __global__ __launch_bounds__(kWG) void k_bupdate(BMat M, BTiles T, BState S, dou
 #pragma unroll
                     for (int k = 0; k < NI; ++k) {
                         const int e = e0 + (int)threadIdx.x + k * kWG;
-                        xv[k] = x[e];
-                        pv[k] = p[e];
                         rv[k] = r[e];
                         qv[k] = q[e];
                     }
@@ -512,7 +569,6 @@ __global__ __launch_bounds__(kWG) void k_bupdate(BMat M, BTiles T, BState S, dou
 #pragma unroll
                     for (int k = 0; k < NI; ++k) {
                         const int e = e0 + (int)threadIdx.x + k * kWG;
-                        x[e] = xv[k] + a * pv[k];
                         const double rn = rv[k] - a * qv[k];
                         r[e] = rn;
                         accv = accv + rn * rn;
@@ -521,7 +577,6 @@ __global__ __launch_bounds__(kWG) void k_bupdate(BMat M, BTiles T, BState S, dou
             } else {
                 for (int e = e0 + (int)threadIdx.x; e < e1; e += kWG) {
                     if (run) {
-                        x[e] = x[e] + a * p[e];
                         const double rn = r[e] - a * q[e];
                         r[e] = rn;
                         accv = accv + rn * rn;
@@ -757,6 +812,7 @@ struct ss_batch {
     double *rr0 = nullptr, *rr1 = nullptr, *bb = nullptr, *stop = nullptr, *rr_last = nullptr;
     int32_t *it0 = nullptr, *it1 = nullptr, *it_last = nullptr, *status = nullptr, *restarts = nullptr;
     int32_t *nrun = nullptr, *kmax = nullptr;
+    double *alpha = nullptr;
     int32_t *pinned = nullptr;  // host: polled running counts
     hipEvent_t ev[2] = {nullptr, nullptr};
     ss_batch_tuning tun{};
@@ -772,7 +828,7 @@ struct ss_batch {
     }
     BState state() const
     {
-        return BState{rr0, rr1, it0, it1, bb, stop, rr_last, it_last, status, restarts, nrun, kmax};
+        return BState{rr0, rr1, it0, it1, bb, stop, rr_last, it_last, status, restarts, nrun, kmax, alpha};
     }
     int grid() const { return tun.grid ? tun.grid : std::max(8, (ntiles + 7) / 8 * 8); }
 };
@@ -833,10 +889,10 @@ void spmv_t(ss_batch *b, hipStream_t st, bool full, const double *pin, const dou
 {
     if (b->max_halo <= staged_halo(NR))
         hipLaunchKernelGGL((k_bspmv<NR, U, MODE, true>), dim3(b->grid()), dim3(kWG), 0, st, b->bmat(),
-                           b->tiles(full), b->state(), pin, r, pout, q, b->part_a, b->part_b, slot);
+                           b->tiles(full), b->state(), pin, r, pout, q, b->x, b->part_a, b->part_b, slot);
     else
         hipLaunchKernelGGL((k_bspmv<NR, U, MODE, false>), dim3(b->grid()), dim3(kWG), 0, st, b->bmat(),
-                           b->tiles(full), b->state(), pin, r, pout, q, b->part_a, b->part_b, slot);
+                           b->tiles(full), b->state(), pin, r, pout, q, b->x, b->part_a, b->part_b, slot);
 }
 
 template <int NR, int MODE>
@@ -863,18 +919,18 @@ void spmv(ss_batch *b, hipStream_t st, bool full, const double *pin, const doubl
 }
 
 template <int NR>
-void update_t(ss_batch *b, hipStream_t st, const double *p, int slot)
+void update_t(ss_batch *b, hipStream_t st, int slot)
 {
     hipLaunchKernelGGL(k_bupdate<NR>, dim3(b->grid()), dim3(kWG), 0, st, b->bmat(), b->tiles(false), b->state(),
-                       b->x, p, b->r, b->q, b->part_b, b->part_a, slot);
+                       b->r, b->q, b->part_b, b->part_a, slot);
 }
 
-void update(ss_batch *b, hipStream_t st, const double *p, int slot)
+void update(ss_batch *b, hipStream_t st, int slot)
 {
     switch (b->nrhs) {
-    case 1: update_t<1>(b, st, p, slot); break;
-    case 2: update_t<2>(b, st, p, slot); break;
-    default: update_t<4>(b, st, p, slot); break;
+    case 1: update_t<1>(b, st, slot); break;
+    case 2: update_t<2>(b, st, slot); break;
+    default: update_t<4>(b, st, slot); break;
     }
 }
 
@@ -929,7 +985,7 @@ void enqueue_pair(ss_batch *b, hipStream_t st, int j)
     const int slot = j & 1;
     double *pcur = slot ? b->p0 : b->p1;
     double *pnext = slot ? b->p1 : b->p0;
-    update(b, st, pcur, slot);
+    update(b, st, slot);
     spmv<M_STEP>(b, st, false, pcur, b->r, pnext, b->q, slot);
 }
 
@@ -1150,7 +1206,7 @@ int ss_batch_setup(int32_t nsys, const ss_csr *systems, int32_t nrhs, const ss_o
         (rc = alloc_dev(b, &b->bb, np)) || (rc = alloc_dev(b, &b->stop, np)) || (rc = alloc_dev(b, &b->rr_last, np)) ||
         (rc = alloc_dev(b, &b->it0, np)) || (rc = alloc_dev(b, &b->it1, np)) || (rc = alloc_dev(b, &b->it_last, np)) ||
         (rc = alloc_dev(b, &b->status, np)) || (rc = alloc_dev(b, &b->restarts, np)) ||
-        (rc = alloc_dev(b, &b->nrun, 1)) || (rc = alloc_dev(b, &b->kmax, 1)))
+        (rc = alloc_dev(b, &b->nrun, 1)) || (rc = alloc_dev(b, &b->kmax, 1)) || (rc = alloc_dev(b, &b->alpha, np)))
         return bail(rc);
     // p0 / p1 are read (times beta = 0) before first written for stopped pairs
     if (hipMemsetAsync(b->p0, 0, sizeof(double) * nv, b->stream) != hipSuccess ||
