@@ -28,7 +28,9 @@ struct DevState {
     double bb;         // (b, b)
     double tol;        // relative tolerance of the run
     double stop;       // CG continues while sqrt(rr) > stop
-    double alpha, beta, pAp;  // last scalars (report only)
+    double alpha[2];   // alpha of the update of slot c, for the x update of the step of slot c
+                       // (0 when the run had stopped before that update)
+    double beta, pAp;  // last scalars (report only)
     double rr_last;    // latest (r, r) (report; read by the host and the next residual step)
     int32_t iter_last; // latest iteration count (same)
     int32_t kmax;      // iteration limit

@@ -242,22 +242,24 @@ __global__ __launch_bounds__(kBS) void k_spmv_sell(int32_t nrows, int32_t nchunk
             for (int u = 0; u < U; ++u) vv[u] = val[base + min(u, L - 1) * 64 + lane];
         }
     }
+    // x_k = x_{k-1} + alpha p_{k-1} is deferred to here.  It is owed whenever
+    // the update of this slot ran (alpha != 0), whatever the status shows by
+    // now: workgroup 0 may already have recorded this step's stop.
+    const double alpha = MODE == SPMV_STEP ? st->alpha[slot] : 0.0;
+    bool stop = false;
     if (CG) {
         __syncthreads();
-        if (s_flag != ST_RUNNING) return;
+        stop = s_flag != ST_RUNNING;
     }
-    double beta = 0.0, alpha = 0.0;
-    if (MODE == SPMV_STEP) {
-        alpha = st->alpha;  // x_k = x_{k-1} + alpha p_{k-1}, deferred to here
-        bool stop;
-        beta = finish_rr(part_b, part_b2, nb, slot, st, ws, &stop);
-        if (stop) {
+    double beta = 0.0;
+    if (MODE == SPMV_STEP && !stop) beta = finish_rr(part_b, part_b2, nb, slot, st, ws, &stop);
+    if (stop) {
+        if (MODE == SPMV_STEP && alpha != 0.0)
             for (int c2 = rb * cpb + w; c2 < cend; c2 += W) {
                 const int rr = cpos[c2] + lane;
                 if (rr < nrows) x[rr] = (XT)((double)x[rr] + alpha * (double)pin[rr]);
             }
-            return;
-        }
+        return;
     }
 
     double acc = 0.0;
@@ -328,21 +330,20 @@ __global__ __launch_bounds__(kBS) void k_spmv_csr(const int32_t *__restrict__ ro
     __shared__ double ws[2 * (kBS / 64) + 2];
     __shared__ int s_flag;
     if (gate && dev::flag_load(gate) == 0) return;
-    if (CG && !running(st, &s_flag)) return;
     const int rb = xcd_remap(blockIdx.x, gridDim.x);
     const int tpb = (ntiles + (int)gridDim.x - 1) / (int)gridDim.x;
     const int tend = min(rb * tpb + tpb, ntiles);
-    double beta = 0.0, alpha = 0.0;
-    if (MODE == SPMV_STEP) {
-        alpha = st->alpha;  // x_k = x_{k-1} + alpha p_{k-1}, deferred to here
-        bool stop;
-        beta = finish_rr(part_b, part_b2, nb, slot, st, ws, &stop);
-        if (stop) {
-            if (rb * tpb < tend)
-                for (int row = tile_row[rb * tpb] + (int)threadIdx.x; row < tile_row[tend]; row += kBS)
-                    x[row] = (XT)((double)x[row] + alpha * (double)pin[row]);
-            return;
-        }
+    // the deferred x update is owed whenever this slot's update ran (see the
+    // SELL kernel)
+    const double alpha = MODE == SPMV_STEP ? st->alpha[slot] : 0.0;
+    bool stop = CG && !running(st, &s_flag);
+    double beta = 0.0;
+    if (MODE == SPMV_STEP && !stop) beta = finish_rr(part_b, part_b2, nb, slot, st, ws, &stop);
+    if (stop) {
+        if (MODE == SPMV_STEP && alpha != 0.0 && rb * tpb < tend)
+            for (int row = tile_row[rb * tpb] + (int)threadIdx.x; row < tile_row[tend]; row += kBS)
+                x[row] = (XT)((double)x[row] + alpha * (double)pin[row]);
+        return;
     }
     double acc = 0.0;
     for (int tile = rb * tpb; tile < tend; ++tile) {
@@ -466,7 +467,11 @@ __global__ __launch_bounds__(kBS) void k_update(int32_t n_loc, int32_t n_own, in
         }
     }
     __syncthreads();
-    if (s_flag != ST_RUNNING) return;
+    if (s_flag != ST_RUNNING) {
+        // no update this slot: the next step owes no x update
+        if (blockIdx.x == 0 && threadIdx.x == 0) st->alpha[slot] = 0.0;
+        return;
+    }
 
     // finish (p, A p): alpha, or a breakdown when it is not positive
     const double pAp = block_sum_all(sum_partials_vec(part_a, na), ws);
@@ -474,7 +479,7 @@ __global__ __launch_bounds__(kBS) void k_update(int32_t n_loc, int32_t n_own, in
     const double alpha = st->rz[slot] / pAp;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         st->pAp = pAp;
-        st->alpha = alpha;
+        st->alpha[slot] = bad ? 0.0 : alpha;
         if (bad) store_status(st, ST_BREAKDOWN);
     }
     if (bad) return;
