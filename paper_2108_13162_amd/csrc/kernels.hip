@@ -198,19 +198,84 @@ __device__ __forceinline__ void load_cols(int (&cc)[U], int cb, int2 base, int j
     }
 }
 
-template <typename VT, typename XT, int MODE, int U>
-__global__ __launch_bounds__(kBS) void k_spmv_sell(int32_t nrows, int32_t nchunks, const int32_t *__restrict__ cptr,
-                                                   const int32_t *__restrict__ cpos,
-                                                   const uint8_t *__restrict__ clen,
-                                                   const uint8_t *__restrict__ rlen, const int32_t *__restrict__ ccol,
-                                                   const int32_t *__restrict__ col, const uint16_t *__restrict__ col16,
-                                                   const int2 *__restrict__ cbase,
-                                                   const VT *__restrict__ val, const XT *__restrict__ pin,
-                                                   const XT *__restrict__ r, XT *__restrict__ pout,
-                                                   XT *__restrict__ q, XT *__restrict__ x, double *__restrict__ part_a,
-                                                   const double *__restrict__ part_b,
-                                                   const double *__restrict__ part_b2, int32_t nb, int32_t slot,
-                                                   DevState *__restrict__ st, const int32_t *__restrict__ gate)
+// Length of chunk c (wave-uniform), read as the 32-bit word holding its
+// byte so that it comes through the scalar path (the length array is padded
+// to whole words).
+__device__ __forceinline__ int chunk_len(const uint8_t *__restrict__ clen, int c)
+{
+    const uint32_t wd = reinterpret_cast<const uint32_t *>(clen)[c >> 2];
+    return (int)((wd >> (8 * (c & 3))) & 0xffu);
+}
+
+// The raw column words and the values of entries j0 .. j0+U-1 of a chunk,
+// the last entry repeated past L; decoded at use (decode_cols), so that the
+// loads can stay in flight across other work.  Both column arrays are read
+// for every batch -- the one the chunk does not use at its first 64 (always
+// valid) entries -- so that the loads do not depend on the chunk's kind.
+template <typename VT, int U>
+__device__ __forceinline__ void load_batch(uint32_t (&c16)[U], uint32_t (&c32)[U], VT (&vv)[U], int cb, int base,
+                                           int j0, int L, int lane, const int32_t *__restrict__ col,
+                                           const uint16_t *__restrict__ col16, const VT *__restrict__ val)
+{
+    const bool narrow = cb >= 0;
+    const uint16_t *p16 = col16 + (narrow ? cb : 0);
+    const int32_t *p32 = col + (narrow ? 0 : ~cb);
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int off = max(min(j0 + u, L - 1), 0) * 64 + lane;
+        c16[u] = p16[narrow ? off : lane];
+        c32[u] = (uint32_t)p32[narrow ? lane : off];
+        vv[u] = val[base + off];
+    }
+}
+
+// A row's own length and operands (r, p_{k-1}, x), at a clamped position
+// for the lanes past the last row.
+template <typename XT, int MODE>
+__device__ __forceinline__ void load_row(int &len, XT &rv, XT &pv, XT &xv, int row, int nrows,
+                                         const uint8_t *__restrict__ rlen, const XT *__restrict__ r,
+                                         const XT *__restrict__ p, const XT *__restrict__ x)
+{
+    const int t = min(row, nrows - 1);
+    const int l = rlen[t];
+    len = row < nrows ? l : 0;
+    rv = pv = xv = XT(0);
+    if (MODE != SPMV_PLAIN) {
+        rv = r[t];
+        pv = p[t];
+    }
+    if (MODE == SPMV_STEP) xv = x[t];
+}
+
+template <int U>
+__device__ __forceinline__ void decode_cols(int (&cc)[U], const uint32_t (&c16)[U], const uint32_t (&c32)[U], int cb,
+                                            int2 base)
+{
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        // select by mask rather than by a branch of the wave
+        const uint32_t m = cb >= 0 ? 0xffffffffu : 0u;
+        cc[u] = (int)(((uint32_t)narrow_col(c16[u], base) & m) | (c32[u] & ~m));
+    }
+}
+
+// ONE: every chunk has at most U entries per row, so a chunk is one batch.
+// Then the wave software-pipelines its chunks: the gathers of chunk c are
+// issued first, then the loads of chunk c+W (header, values, columns, the
+// row's own r, p, x) -- always the same loads, at clamped indexes past the
+// wave's last chunk -- so that the products of chunk c wait for its gathers
+// only (vector loads return in issue order) while chunk c+W's loads stay in
+// flight.  Otherwise (rows longer than U) the batches of each chunk are
+// walked in turn, each batch's gathers waiting for its own loads.
+template <typename VT, typename XT, int MODE, int U, bool ONE>
+__global__ __launch_bounds__(kBS) __attribute__((amdgpu_waves_per_eu(1, 4))) void k_spmv_sell(
+    int32_t nrows, int32_t nchunks, const int32_t *__restrict__ cptr, const int32_t *__restrict__ cpos,
+    const uint8_t *__restrict__ clen, const uint8_t *__restrict__ rlen, const int32_t *__restrict__ ccol,
+    const int32_t *__restrict__ col, const uint16_t *__restrict__ col16, const int2 *__restrict__ cbase,
+    const VT *__restrict__ val, const XT *__restrict__ pin, const XT *__restrict__ r, XT *__restrict__ pout,
+    XT *__restrict__ q, XT *__restrict__ x, double *__restrict__ part_a, const double *__restrict__ part_b,
+    const double *__restrict__ part_b2, int32_t nb, int32_t slot, DevState *__restrict__ st,
+    const int32_t *__restrict__ gate)
 {
     constexpr bool CG = MODE != SPMV_PLAIN;
     constexpr int W = kBS / 64;
@@ -219,24 +284,31 @@ __global__ __launch_bounds__(kBS) void k_spmv_sell(int32_t nrows, int32_t nchunk
     if (gate && dev::flag_load(gate) == 0) return;
     // the status word is read while the first matrix loads are in flight
     if (CG && threadIdx.x == 0) s_flag = load_status(st);
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    // the wave index is uniform: chunk headers come through the scalar path
+    const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
     const int rb = xcd_remap(blockIdx.x, gridDim.x);
     const int cpb = (nchunks + (int)gridDim.x - 1) / (int)gridDim.x;
     const int cend = min(rb * cpb + cpb, nchunks);
     int c = rb * cpb + w;
 
-    // first batch of the first chunk, loaded before beta is known
+    // first batch of the first chunk (and, for ONE, the row's own operands),
+    // loaded before beta is known
     int cc[U];
+    uint32_t c16[U], c32[U];
     VT vv[U];
-    int base = 0, L = 0, cb = 0, row = 0;
+    int base = 0, L = 0, cb = 0, row = 0, len = 0;
     int2 wb = make_int2(0, 0);
+    XT rrow = XT(0), prow = XT(0), xrow = XT(0);
     if (c < cend) {
         base = cptr[c];
-        L = clen[c];
+        L = chunk_len(clen, c);
         cb = ccol[c];
         if (cb >= 0) wb = cbase[c];
         row = cpos[c] + lane;
-        if (L > 0) {
+        if constexpr (ONE) {
+            load_batch<VT, U>(c16, c32, vv, cb, base, 0, L, lane, col, col16, val);
+            load_row<XT, MODE>(len, rrow, prow, xrow, row, nrows, rlen, r, pin, x);
+        } else {
             load_cols<U>(cc, cb, wb, 0, L, lane, col, col16);
 #pragma unroll
             for (int u = 0; u < U; ++u) vv[u] = val[base + min(u, L - 1) * 64 + lane];
@@ -263,40 +335,103 @@ __global__ __launch_bounds__(kBS) void k_spmv_sell(int32_t nrows, int32_t nchunk
     }
 
     double acc = 0.0;
-    bool have = true;  // cc / vv hold batch 0 of chunk c
-    for (; c < cend; c += W) {
-        if (!have) {
-            base = cptr[c];
-            L = clen[c];
-            cb = ccol[c];
-            if (cb >= 0) wb = cbase[c];
-            row = cpos[c] + lane;
-        }
-        const int len = row < nrows ? (int)rlen[row] : 0;
-        XT sacc = XT(0);
-        for (int j0 = 0; j0 < L; j0 += U) {
-            if (!have) {
-                load_cols<U>(cc, cb, wb, j0, L, lane, col, col16);
+    if constexpr (ONE) {
+        while (c < cend) {
+            // drain the previous chunk's stores (and this chunk's loads, needed
+            // now): with stores outstanding the compiler can only wait for the
+            // gathers below by draining everything
+            __builtin_amdgcn_s_waitcnt(0x0f70);
+            XT rx[U], px[U];
+            decode_cols<U>(cc, c16, c32, cb, wb);
 #pragma unroll
-                for (int u = 0; u < U; ++u) vv[u] = val[base + min(j0 + u, L - 1) * 64 + lane];
+            for (int u = 0; u < U; ++u) {
+                if (CG) rx[u] = r[cc[u]];
+                px[u] = pin[cc[u]];
+            }
+            // keep the issue order: the scheduler would otherwise interleave
+            // the two groups of loads, and the products would wait for both
+            __builtin_amdgcn_sched_barrier(0);
+            // chunk c + W, or chunk c again past the wave's last one (unused)
+            const int lc = c + W < cend ? c + W : c;
+            const int nbase = cptr[lc], nL = chunk_len(clen, lc), ncb = ccol[lc];
+            const int2 nwb = cbase[lc];
+            const int nrow = cpos[lc] + lane;
+            uint32_t n16[U], n32[U];
+            VT nvv[U];
+            load_batch<VT, U>(n16, n32, nvv, ncb, nbase, 0, nL, lane, col, col16, val);
+            int nlen;
+            XT nr, np, nx;
+            load_row<XT, MODE>(nlen, nr, np, nx, nrow, nrows, rlen, r, pin, x);
+            __builtin_amdgcn_sched_barrier(0);
+            XT sacc = XT(0);
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const XT xx = CG ? pupd(rx[u], px[u], beta) : px[u];
+                if (u < len) sacc = sacc + (XT)vv[u] * xx;
+            }
+            // computed here, on every lane: otherwise the compiler sinks the
+            // products -- and the gathers with them -- into the store branch
+            asm volatile("" : "+v"(sacc));
+            if (row < nrows) {
+                q[row] = sacc;
+                if (CG) {
+                    const XT pr = pupd(rrow, prow, beta);
+                    pout[row] = pr;
+                    if (MODE == SPMV_STEP) x[row] = (XT)((double)xrow + alpha * (double)prow);
+                    acc = acc + (double)pr * (double)sacc;
+                }
+            }
+            c += W;
+            cb = ncb;
+            wb = nwb;
+            row = nrow;
+            len = nlen;
+            rrow = nr;
+            prow = np;
+            xrow = nx;
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                c16[u] = n16[u];
+                c32[u] = n32[u];
+                vv[u] = nvv[u];
+            }
+        }
+    } else {
+        bool have = true;  // cc / vv hold batch 0 of chunk c
+        for (; c < cend; c += W) {
+            if (!have) {
+                base = cptr[c];
+                L = chunk_len(clen, c);
+                cb = ccol[c];
+                if (cb >= 0) wb = cbase[c];
+                row = cpos[c] + lane;
+            }
+            len = row < nrows ? (int)rlen[row] : 0;
+            XT sacc = XT(0);
+            for (int j0 = 0; j0 < L; j0 += U) {
+                if (!have) {
+                    load_cols<U>(cc, cb, wb, j0, L, lane, col, col16);
+#pragma unroll
+                    for (int u = 0; u < U; ++u) vv[u] = val[base + min(j0 + u, L - 1) * 64 + lane];
+                }
+                have = false;
+                XT xx[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u) xx[u] = CG ? pupd(r[cc[u]], pin[cc[u]], beta) : pin[cc[u]];
+#pragma unroll
+                for (int u = 0; u < U; ++u)
+                    if (j0 + u < len) sacc = sacc + (XT)vv[u] * xx[u];
             }
             have = false;
-            XT xx[U];
-#pragma unroll
-            for (int u = 0; u < U; ++u) xx[u] = CG ? pupd(r[cc[u]], pin[cc[u]], beta) : pin[cc[u]];
-#pragma unroll
-            for (int u = 0; u < U; ++u)
-                if (j0 + u < len) sacc = sacc + (XT)vv[u] * xx[u];
-        }
-        have = false;
-        if (row < nrows) {
-            q[row] = sacc;
-            if (CG) {
-                const XT pold = pin[row];
-                const XT pr = pupd(r[row], pold, beta);
-                pout[row] = pr;
-                if (MODE == SPMV_STEP) x[row] = (XT)((double)x[row] + alpha * (double)pold);
-                acc = acc + (double)pr * (double)sacc;
+            if (row < nrows) {
+                q[row] = sacc;
+                if (CG) {
+                    const XT pold = pin[row];
+                    const XT pr = pupd(r[row], pold, beta);
+                    pout[row] = pr;
+                    if (MODE == SPMV_STEP) x[row] = (XT)((double)x[row] + alpha * (double)pold);
+                    acc = acc + (double)pr * (double)sacc;
+                }
             }
         }
     }
@@ -899,15 +1034,24 @@ void spmv_dispatch(hipStream_t s, const Mat &A, const XT *pin, const XT *r, XT *
     if (A.nrows == 0) return;
     const dim3 grid(A.grid), block(kBS);
     if (A.fmt == FMT_SELL) {
-#define SS_SELL(U)                                                                                               \
-    hipLaunchKernelGGL((k_spmv_sell<VT, XT, MODE, U>), grid, block, 0, s, A.nrows, A.nchunks, A.cptr, A.cpos,    \
+#define SS_SELL(U, ONE)                                                                                          \
+    hipLaunchKernelGGL((k_spmv_sell<VT, XT, MODE, U, ONE>), grid, block, 0, s, A.nrows, A.nchunks, A.cptr, A.cpos, \
                        A.clen, A.rlen, A.ccol, A.col, A.col16, A.cbase, (const VT *)A.val, pin, r, pout, q, x, P.a, \
                        (const double *)P.b, (const double *)P.b2, P.nb, slot, st, gate)
-        switch (A.unroll) {
-        case 5: SS_SELL(5); break;
-        case 7: SS_SELL(7); break;
-        case 9: SS_SELL(9); break;
-        default: SS_SELL(8); break;
+        if (A.one_batch) {
+            switch (A.unroll) {
+            case 5: SS_SELL(5, true); break;
+            case 7: SS_SELL(7, true); break;
+            case 9: SS_SELL(9, true); break;
+            default: SS_SELL(8, true); break;
+            }
+        } else {
+            switch (A.unroll) {
+            case 5: SS_SELL(5, false); break;
+            case 7: SS_SELL(7, false); break;
+            case 9: SS_SELL(9, false); break;
+            default: SS_SELL(8, false); break;
+            }
         }
 #undef SS_SELL
         return;

@@ -41,6 +41,7 @@ struct Layout {
     std::vector<uint8_t> clen, rlen;
     int32_t nchunks = 0, ntiles = 0, tile_nnz = 2048;
     int32_t unroll = 8;               // SELL: entries per lane loaded before use
+    int32_t one_batch = 0;            // SELL: no chunk longer than unroll
     int64_t stored = 0;  // entries incl. padding
 };
 
@@ -133,6 +134,9 @@ void build_matrix(const ss_part *p, Layout &L, int32_t tile_nnz, int32_t force)
             const int32_t id = order[i];
             int32_t m = 0;
             for (int32_t t = id * 64; t < std::min(nl, id * 64 + 64); ++t) m = std::max(m, (int32_t)L.rlen[t]);
+            // at least one stored entry per chunk (padding for a chunk of
+            // empty rows), so every batch of a chunk has entries to gather
+            m = std::max(m, (int32_t)1);
             L.cpos[i] = id * 64;
             L.clen[i] = (uint8_t)m;
             L.cptr[i + 1] = L.cptr[i] + 64 * m;
@@ -149,6 +153,10 @@ void build_matrix(const ss_part *p, Layout &L, int32_t tile_nnz, int32_t force)
                 L.unroll = u;
             }
         }
+        // every chunk one batch: the SpMV pipelines chunk to chunk
+        L.one_batch = 1;
+        for (int32_t i = 0; i < nch; ++i)
+            if (L.clen[i] > L.unroll) L.one_batch = 0;
         // padding points at a valid position (the row itself, or 0 past the
         // last row) and is masked out by the row length
         L.col.assign((size_t)L.stored, 0);
@@ -307,14 +315,21 @@ struct ss_solver {
 
 namespace {
 
+// count elements from the host, followed by pad zero elements
 template <typename T>
-int upload(ss_solver *s, T **dst, const T *src, size_t count)
+int upload(ss_solver *s, T **dst, const T *src, size_t count, size_t pad = 0)
 {
-    *dst = (T *)s->mem.get(sizeof(T) * std::max<size_t>(count, 1));
+    *dst = (T *)s->mem.get(sizeof(T) * std::max<size_t>(count + pad, 1));
     if (!*dst) return fail(SS_ENOMEM, "device allocation failed");
     if (count) SS_HIP(hipMemcpyAsync(*dst, src, sizeof(T) * count, hipMemcpyHostToDevice, s->stream));
+    if (pad) SS_HIP(hipMemsetAsync(*dst + count, 0, sizeof(T) * pad, s->stream));
     return SS_OK;
 }
+
+// The SELL kernels read a whole batch of 64 entries at clamped indexes (a
+// chunk without entries reads just past its array), and the chunk lengths
+// as 32-bit words: those arrays end with this many zero elements.
+constexpr size_t kSellPad = 64;
 
 template <typename T>
 int alloc_dev(ss_solver *s, T **dst, size_t count)
@@ -561,6 +576,7 @@ int ss_cg_setup(const ss_csr *A, const ss_part *p, const ss_opts *o, void *hip_s
     M.nrows = s->n_loc;
     M.nchunks = L.nchunks;
     M.unroll = L.unroll;
+    M.one_batch = L.one_batch;
     M.ntiles = L.ntiles;
     M.tile_nnz = L.tile_nnz;
     const int work = L.fmt == FMT_SELL ? (L.nchunks + kBS / 64 - 1) / (kBS / 64) : L.ntiles;
@@ -578,15 +594,15 @@ int ss_cg_setup(const ss_csr *A, const ss_part *p, const ss_opts *o, void *hip_s
     int32_t *d_cbase = nullptr;
     uint8_t *d_clen = nullptr, *d_rlen = nullptr;
     const size_t nl = (size_t)s->n_loc;
-    if ((rc = upload(s, &d_col, L.col.data(), L.col.size())) ||
-        (rc = upload(s, &d_col16, L.col16.data(), L.col16.size())) ||
+    if ((rc = upload(s, &d_col, L.col.data(), L.col.size(), kSellPad)) ||
+        (rc = upload(s, &d_col16, L.col16.data(), L.col16.size(), kSellPad)) ||
         (rc = upload(s, &d_ccol, L.ccol.data(), L.ccol.size())) ||
         (rc = upload(s, &d_cbase, L.cbase.data(), L.cbase.size())) ||
         (rc = upload(s, &s->nzmap, L.nzmap.data(), L.nzmap.size())) ||
-        (rc = upload(s, &s->val, val_st.data(), val_st.size())) ||
+        (rc = upload(s, &s->val, val_st.data(), val_st.size(), kSellPad)) ||
         (rc = upload(s, &d_cptr, L.cptr.data(), L.cptr.size())) ||
         (rc = upload(s, &d_cpos, L.cpos.data(), L.cpos.size())) ||
-        (rc = upload(s, &d_clen, L.clen.data(), L.clen.size())) ||
+        (rc = upload(s, &d_clen, L.clen.data(), L.clen.size(), kSellPad)) ||
         (rc = upload(s, &d_rlen, L.rlen.data(), L.rlen.size())) ||
         (rc = upload(s, &d_rowptr, L.rowptr.data(), L.rowptr.size())) ||
         (rc = upload(s, &d_tile, L.tile_row.data(), L.tile_row.size())) ||
@@ -611,7 +627,7 @@ int ss_cg_setup(const ss_csr *A, const ss_part *p, const ss_opts *o, void *hip_s
     if (opts.precision != SS_FP64) {
         std::vector<float> v32(val_st.size());
         for (size_t k = 0; k < v32.size(); ++k) v32[k] = (float)val_st[k];
-        if ((rc = upload(s, &s->val32, v32.data(), v32.size())) || (rc = alloc_dev(s, &s->d32, nl)) ||
+        if ((rc = upload(s, &s->val32, v32.data(), v32.size(), kSellPad)) || (rc = alloc_dev(s, &s->d32, nl)) ||
             (rc = alloc_dev(s, &s->r32, nl)) || (rc = alloc_dev(s, &s->p32a, nl)) ||
             (rc = alloc_dev(s, &s->p32b, nl)) || (rc = alloc_dev(s, &s->q32, nl)) || (rc = alloc_dev(s, &s->st_in, 1)))
             return bail(rc);
