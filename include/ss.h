@@ -136,7 +136,7 @@ int ss_part_export_local(const ss_part *p, int32_t *bd_rowptr, int32_t *bd_colid
 void ss_part_destroy(ss_part *p);
 
 /* --------------------------------------------------------------- solver */
-typedef void *(*ss_alloc_fn)(void *ctx, size_t bytes); /* returns device memory or NULL */
+typedef void *(*ss_alloc_fn)(void *ctx, size_t bytes); /* device memory, 256-byte aligned, or NULL */
 typedef void (*ss_free_fn)(void *ctx, void *ptr);
 
 enum { SS_FP64 = 0, SS_FP32_IR = 1, SS_FP32_RU = 2 };

@@ -48,6 +48,12 @@ def lib():
         L.orc_ss_ru.argtypes = [P, i64, P, P, P, P, P, dbl, i32, dbl, i32, P, P, P, P]
         L.orc_grad_vals.argtypes = [i64, P, P, P, P, P]
         L.orc_chol_solve.argtypes = [i64, P, P, P]
+        L.orc_band_size.argtypes = [i64, P, P, i32, i32, i32, P, P, P]
+        L.orc_band_extract.argtypes = [i64, P, P, P, i32, i32, i32, P, P, P]
+        L.orc_band_col_spmv.argtypes = [i64, P, P, P, i32, P, P, P]
+        L.orc_band_dot.argtypes = [i64, i32, P, P]
+        L.orc_band_dot.restype = dbl
+        L.orc_band_cg.argtypes = [i64, P, P, P, i32, i32, P, P, dbl, i32, P, P, P, P]
         _lib = L
     return _lib
 
@@ -239,6 +245,54 @@ def ss_ru(A, sd: SubDomains, b, x0=None, tol: float = 1e-10, maxit: int = 100000
     st = lib().orc_ss_ru(S.ref(), A.n, _p(_i32(A.rowptr)), _p(_i32(A.colidx)), _p(_f64(A.val)), _p(b), _p(x),
                          tol, maxit, delta, check_every, C.byref(it), C.byref(nref), C.byref(rel), C.byref(tr))
     return x, Result(st, it.value, rel.value, tr.value, None, nref.value)
+
+
+# ----------------------------------------------------------------------------
+# band splittings (Algorithms 1 and 2)
+# ----------------------------------------------------------------------------
+
+BAND_ROW, BAND_COL = 0, 1
+
+
+def band_extract(A, kind: int, nbands: int, p: int) -> tuple:
+    """Band p of nbands (kind BAND_ROW or BAND_COL) as (rowptr, colidx, val, ncols)."""
+    rp, ci, v = _i32(A.rowptr), _i32(A.colidx), _f64(A.val)
+    nr, nc, nz = C.c_int64(), C.c_int64(), C.c_int64()
+    st = lib().orc_band_size(A.n, _p(rp), _p(ci), kind, nbands, p, C.byref(nr), C.byref(nc), C.byref(nz))
+    if st != OK:
+        raise ValueError(f"band_extract: status {st}")
+    brp = np.empty(nr.value + 1, dtype=np.int32)
+    bci = np.empty(max(nz.value, 1), dtype=np.int32)
+    bv = np.empty(max(nz.value, 1))
+    lib().orc_band_extract(A.n, _p(rp), _p(ci), _p(v), kind, nbands, p, _p(brp), _p(bci), _p(bv))
+    return brp, bci[: nz.value], bv[: nz.value], nc.value
+
+
+def band_col_spmv(A, nbands: int, x) -> np.ndarray:
+    x = _f64(x)
+    y, tmp = np.empty(A.n), np.empty(A.n)
+    lib().orc_band_col_spmv(A.n, _p(_i32(A.rowptr)), _p(_i32(A.colidx)), _p(_f64(A.val)), nbands, _p(x), _p(y),
+                            _p(tmp))
+    return y
+
+
+def band_dot(nbands: int, u, v) -> float:
+    u, v = _f64(u), _f64(v)
+    return lib().orc_band_dot(len(u), nbands, _p(u), _p(v))
+
+
+def band_cg(A, kind: int, nbands: int, b, x0=None, tol: float = 1e-10, maxit: int = 10000,
+            hist: bool = True) -> tuple:
+    """CG (Algorithm 3, M = I) with the band-row or band-column splitting."""
+    b = _f64(b)
+    x = np.zeros(A.n) if x0 is None else _f64(x0).copy()
+    h = np.full(maxit + 1, np.nan)
+    it, rel, tr = C.c_int32(), C.c_double(), C.c_double()
+    st = lib().orc_band_cg(A.n, _p(_i32(A.rowptr)), _p(_i32(A.colidx)), _p(_f64(A.val)), kind, nbands, _p(b),
+                           _p(x), tol, maxit, _p(h), C.byref(it), C.byref(rel), C.byref(tr))
+    if st == EINVAL:
+        raise ValueError("band_cg: bad band count or kind")
+    return x, Result(st, it.value, rel.value, tr.value, h[: it.value + 1] if hist else None)
 
 
 def grad_vals(A, lam, x) -> np.ndarray:

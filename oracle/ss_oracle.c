@@ -15,6 +15,8 @@
  *     Section 4.4.2.
  *   - Dot products: weighted local sums then a global sum: Section 4.4.2.
  *   - CG: Algorithm 3 with M = I.
+ *   - Band-row and band-column splittings (Algorithms 1 and 2) with their
+ *     products and dot products: Sections 3.1, 3.2, 4.2 and 4.3.
  */
 #include <math.h>
 #include <stdint.h>
@@ -259,6 +261,152 @@ int orc_cg(int64_t n, const int32_t *rowptr, const int32_t *colidx, const double
     orc_op op = {n, glob_apply, glob_dot, &c};
     int st = cg_core(&op, b, x, tol, maxit, hist, iters, relres);
     *true_rr = true_relres(n, rowptr, colidx, val, b, x);
+    return st;
+}
+
+/* ---------------------------------------------------------------------- */
+/* Band splittings (Section 3.1, Algorithm 1; Section 3.2, Algorithm 2).   */
+/* n is cut into nb bands of m = n / nb consecutive indices, the last band */
+/* taking the remainder n - (nb-1) m.  A row band holds its rows with all  */
+/* (global) columns; a column band holds every row restricted to its       */
+/* columns, renumbered from the band's first column.                       */
+/* ---------------------------------------------------------------------- */
+
+static void band_range(int64_t n, int32_t nb, int32_t p, int64_t *lo, int64_t *np)
+{
+    const int64_t m = n / nb;
+    *lo = (int64_t)p * m;
+    *np = p == nb - 1 ? n - (int64_t)p * m : m;
+}
+
+/* Sizes of band p: rows, columns and stored entries.  kind 0 = row band,
+ * 1 = column band. */
+int orc_band_size(int64_t n, const int32_t *rowptr, const int32_t *colidx, int32_t kind, int32_t nb, int32_t p,
+                  int64_t *nrows, int64_t *ncols, int64_t *nnz)
+{
+    if (nb < 1 || nb > n || p < 0 || p >= nb || (kind != 0 && kind != 1)) return ORC_EINVAL;
+    int64_t lo, np;
+    band_range(n, nb, p, &lo, &np);
+    if (kind == 0) {
+        *nrows = np;
+        *ncols = n;
+        *nnz = rowptr[lo + np] - rowptr[lo];
+    } else {
+        int64_t c = 0;
+        for (int64_t i = 0; i < n; ++i)
+            for (int64_t k = rowptr[i]; k < rowptr[i + 1]; ++k)
+                if (colidx[k] >= lo && colidx[k] < lo + np) ++c;
+        *nrows = n;
+        *ncols = np;
+        *nnz = c;
+    }
+    return ORC_OK;
+}
+
+/* Band p as CSR (arrays sized by orc_band_size). */
+int orc_band_extract(int64_t n, const int32_t *rowptr, const int32_t *colidx, const double *val, int32_t kind,
+                     int32_t nb, int32_t p, int32_t *browptr, int32_t *bcolidx, double *bval)
+{
+    if (nb < 1 || nb > n || p < 0 || p >= nb || (kind != 0 && kind != 1)) return ORC_EINVAL;
+    int64_t lo, np;
+    band_range(n, nb, p, &lo, &np);
+    if (kind == 0) {
+        /* the rows lo .. lo+np-1 as they are, row pointers shifted to 0 */
+        const int32_t off = rowptr[lo];
+        for (int64_t i = 0; i <= np; ++i) browptr[i] = rowptr[lo + i] - off;
+        for (int64_t k = 0; k < browptr[np]; ++k) {
+            bcolidx[k] = colidx[off + k];
+            bval[k] = val[off + k];
+        }
+    } else {
+        /* every row, keeping the entries whose column lies in the band */
+        int32_t c = 0;
+        for (int64_t i = 0; i < n; ++i) {
+            browptr[i] = c;
+            for (int64_t k = rowptr[i]; k < rowptr[i + 1]; ++k)
+                if (colidx[k] >= lo && colidx[k] < lo + np) {
+                    bcolidx[c] = (int32_t)(colidx[k] - lo);
+                    bval[c] = val[k];
+                    ++c;
+                }
+        }
+        browptr[n] = c;
+    }
+    return ORC_OK;
+}
+
+/* Band-column product (Section 4.3.1): every band computes the full-length
+ * y_p = A_p x_p from its column band and its part of x; y is their sum, the
+ * bands added in ascending order (y = ((y_0 + y_1) + y_2) + ...). */
+void orc_band_col_spmv(int64_t n, const int32_t *rowptr, const int32_t *colidx, const double *val, int32_t nb,
+                       const double *x, double *y, double *yp)
+{
+    for (int32_t p = 0; p < nb; ++p) {
+        int64_t lo, np;
+        band_range(n, nb, p, &lo, &np);
+        for (int64_t i = 0; i < n; ++i) {
+            double s = 0.0;
+            for (int64_t k = rowptr[i]; k < rowptr[i + 1]; ++k)
+                if (colidx[k] >= lo && colidx[k] < lo + np) s = s + val[k] * x[colidx[k]];
+            yp[i] = s;
+        }
+        for (int64_t i = 0; i < n; ++i) y[i] = p == 0 ? yp[i] : y[i] + yp[i];
+    }
+}
+
+/* Dot product of the band splittings (Section 4.2.2): each band sums its
+ * own entries, then the band sums are added in ascending band order. */
+double orc_band_dot(int64_t n, int32_t nb, const double *u, const double *v)
+{
+    double t = 0.0;
+    for (int32_t p = 0; p < nb; ++p) {
+        int64_t lo, np;
+        band_range(n, nb, p, &lo, &np);
+        double s = 0.0;
+        for (int64_t i = lo; i < lo + np; ++i) s = s + u[i] * v[i];
+        t = t + s;
+    }
+    return t;
+}
+
+typedef struct { int64_t n; const int32_t *rowptr, *colidx; const double *val; int32_t nb; double *tmp; } band_ctx;
+
+/* Band-row product (Section 4.2.1): once x is complete on every band, each
+ * band forms its own rows of y -- row by row, the global CSR product. */
+static void band_row_apply(const void *c, const double *x, double *y)
+{
+    const band_ctx *B = (const band_ctx *)c;
+    for (int32_t p = 0; p < B->nb; ++p) {
+        int64_t lo, np;
+        band_range(B->n, B->nb, p, &lo, &np);
+        orc_csr_matvec(np, B->rowptr + lo, B->colidx, B->val, x, y + lo);
+    }
+}
+static void band_col_apply(const void *c, const double *x, double *y)
+{
+    const band_ctx *B = (const band_ctx *)c;
+    orc_band_col_spmv(B->n, B->rowptr, B->colidx, B->val, B->nb, x, y, B->tmp);
+}
+static double band_dot(const void *c, const double *u, const double *v)
+{
+    const band_ctx *B = (const band_ctx *)c;
+    return orc_band_dot(B->n, B->nb, u, v);
+}
+
+/* CG (Algorithm 3, M = I) with a band splitting: kind 0 = band-row,
+ * 1 = band-column; nb bands. */
+int orc_band_cg(int64_t n, const int32_t *rowptr, const int32_t *colidx, const double *val, int32_t kind,
+                int32_t nb, const double *b, double *x, double tol, int32_t maxit, double *hist, int32_t *iters,
+                double *relres, double *true_rr)
+{
+    if (nb < 1 || nb > n || (kind != 0 && kind != 1)) return ORC_EINVAL;
+    double *tmp = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    if (!tmp) return ORC_ENOMEM;
+    band_ctx c = {n, rowptr, colidx, val, nb, tmp};
+    orc_op op = {n, kind == 0 ? band_row_apply : band_col_apply, band_dot, &c};
+    int st = cg_core(&op, b, x, tol, maxit, hist, iters, relres);
+    *true_rr = true_relres(n, rowptr, colidx, val, b, x);
+    free(tmp);
     return st;
 }
 

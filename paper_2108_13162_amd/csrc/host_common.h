@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdint>
 #include <string>
 #include <vector>
 
@@ -25,6 +26,12 @@ struct DeviceMem {
         void *p = nullptr;
         if (alloc) {
             p = alloc(ctx, bytes);
+            // the kernels use 16-byte accesses: a caller's block must be
+            // aligned like hipMalloc's
+            if (p && (reinterpret_cast<uintptr_t>(p) & 255)) {
+                if (release) release(ctx, p);
+                p = nullptr;
+            }
         } else if (hipMalloc(&p, bytes) != hipSuccess) {
             (void)hipGetLastError();
             p = nullptr;

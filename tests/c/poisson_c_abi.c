@@ -30,6 +30,23 @@
         }                                                            \
     } while (0)
 
+/* An allocator whose blocks are 64 bytes past a 256-byte boundary: the
+ * library must refuse them (SS_ENOMEM) and hand every block back. */
+static int n_live = 0;
+static void *offset_alloc(void *ctx, size_t bytes)
+{
+    (void)ctx;
+    void *p = NULL;
+    if (hipMalloc(&p, bytes + 256) != hipSuccess) return NULL;
+    ++n_live;
+    return (char *)p + 64;
+}
+static void offset_free(void *ctx, void *p)
+{
+    (void)ctx;
+    if (p && hipFree((char *)p - 64) == hipSuccess) --n_live;
+}
+
 int main(int argc, char **argv)
 {
     const int m = argc > 1 ? atoi(argv[1]) : 48;
@@ -79,6 +96,15 @@ int main(int argc, char **argv)
     }
     const double rel = sqrt(rr / bb);
     printf("m=%d iterations=%d relres=%.3e host_relres=%.3e\n", m, res.iterations, res.relres, rel);
+
+    ss_opts o;
+    ss_opts_default(&o);
+    o.alloc = offset_alloc;
+    o.free = offset_free;
+    ss_solver *misaligned = NULL;
+    const int rc_mis = ss_cg_setup(&A, part, &o, NULL, &misaligned);
+    printf("misaligned allocator: %s, blocks left %d\n", ss_strerror(rc_mis), n_live);
+    if (rc_mis != SS_ENOMEM || misaligned != NULL || n_live != 0) return 3;
 
     ss_cg_destroy(solver);
     ss_part_destroy(part);

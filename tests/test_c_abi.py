@@ -35,3 +35,6 @@ def test_c_client_solves(tmp_path):
     print(r.stdout, r.stderr)
     assert r.returncode == 0, (r.stdout, r.stderr)
     assert "iterations=" in r.stdout
+    # a caller's allocator returning blocks off a 256-byte boundary is refused
+    # cleanly, every block handed back
+    assert "misaligned allocator: out of memory, blocks left 0" in r.stdout
