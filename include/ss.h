@@ -272,6 +272,49 @@ int ss_cg_info(const ss_solver *s, int32_t *n, int32_t *n_loc, int64_t *nnz, int
 
 void ss_cg_destroy(ss_solver *s);
 
+/* --------------------------------------------------------- band splittings */
+/*
+ * The paper's other two decompositions (Section 3.1, Algorithm 1; Section
+ * 3.2, Algorithm 2), for comparison with the sub-structuring.  n is cut into
+ * nbands bands of m = n / nbands consecutive indices, the last band taking
+ * the remainder n - (nbands-1) m.
+ *   SS_BAND_ROW: band p holds rows [p m, p m + N_p) with all (global) columns.
+ *   SS_BAND_COL: band p holds every row restricted to the columns
+ *                [p m, p m + N_p), renumbered from 0.
+ */
+#define SS_BAND_ROW 0
+#define SS_BAND_COL 1
+
+/* Shape of band p: *nrows, *ncols and *nnz (stored entries).  Any pointer may
+ * be NULL.  Errors: SS_EINVAL (invalid CSR, unknown kind, nbands outside
+ * [1, n], p outside [0, nbands)). */
+int ss_band_size(const ss_csr *A, int32_t kind, int32_t nbands, int32_t p, int32_t *nrows, int32_t *ncols,
+                 int64_t *nnz);
+
+/* Band p as CSR in caller-provided host arrays sized by ss_band_size:
+ * rowptr[nrows+1], colidx[nnz], val[nnz]; columns ascending inside each row
+ * as in A.  Errors as ss_band_size. */
+int ss_band_extract(const ss_csr *A, int32_t kind, int32_t nbands, int32_t p, int32_t *rowptr, int32_t *colidx,
+                    double *val);
+
+/*
+ * ss_band_setup -- CG (Algorithm 3) on A with the band splitting `kind` into
+ * nbands bands, all bands on the current HIP device; solved, applied, timed
+ * and released with the ss_cg_* calls of a solver from ss_cg_setup.
+ * On one device the band-row splitting's collection of the whole x before
+ * each product (Section 4.2.1) is the shared vector itself, so its product is
+ * the global one; the band-column product (Section 4.3.1) adds the bands'
+ * partial products y = sum_p A_p x_p, band by band in ascending order, which
+ * is done per row: each row's sum is split where its columns cross into the
+ * next band.  Dot products and the stopping rule as ss_cg_solve.
+ * o: SS_FP64 only (SS_EUNSUPPORTED otherwise); the band-column product needs
+ * the SELL layout (rows of at most 255 entries; SS_EUNSUPPORTED otherwise).
+ * Errors: SS_EINVAL (invalid CSR, unknown kind, nbands outside [1, n]),
+ * SS_EUNSUPPORTED, SS_ENOMEM, SS_EDEVICE.
+ */
+int ss_band_setup(const ss_csr *A, int32_t kind, int32_t nbands, const ss_opts *o, void *hip_stream,
+                  ss_solver **out);
+
 /* ------------------------------------------------------- batched solver */
 /*
  * Many independent SPD systems, each with nrhs right-hand sides, solved

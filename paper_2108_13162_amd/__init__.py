@@ -25,6 +25,7 @@ LIB_PATH = os.path.join(HERE, "libss.so")
 
 SS_OK, SS_NOT_CONVERGED, SS_EINVAL, SS_ENOMEM, SS_EDEVICE, SS_EBREAKDOWN, SS_EUNSUPPORTED = 0, 1, -1, -2, -3, -4, -5
 SS_PART_BOX, SS_PART_RCB, SS_PART_USER = 0, 1, 2
+SS_BAND_ROW, SS_BAND_COL = 0, 1
 SS_FP64, SS_FP32_IR, SS_FP32_RU = 0, 1, 2
 SS_MAT_AUTO, SS_MAT_SELL, SS_MAT_CSR = 0, 1, 2
 SS_PRECOND_NONE, SS_PRECOND_JACOBI = 0, 1
@@ -95,6 +96,9 @@ def lib() -> C.CDLL:
         "ss_cg_time_spmv": (C.c_int, [P, i32, P, P]),
         "ss_cg_info": (C.c_int, [P, P, P, P, P, P]),
         "ss_cg_destroy": (None, [P]),
+        "ss_band_size": (C.c_int, [P, i32, i32, i32, P, P, P]),
+        "ss_band_extract": (C.c_int, [P, i32, i32, i32, P, P, P]),
+        "ss_band_setup": (C.c_int, [P, i32, i32, P, P, P]),
         "ss_batch_setup": (C.c_int, [i32, P, i32, P, P, P]),
         "ss_batch_solve": (C.c_int, [P, P, P, dbl, i32, P, P]),
         "ss_batch_set_tuning": (C.c_int, [P, P]),
@@ -327,6 +331,42 @@ def ss_cg_setup(A, part: Partition, opts: Optional[ss_opts] = None, device=None)
     with torch.cuda.device(dev):
         _check(lib().ss_cg_setup(csr.ref(), part.h, C.byref(o), C.c_void_p(stream.cuda_stream), C.byref(out)),
                "ss_cg_setup")
+    return Solver(out, alloc, stream, int(A.n), int(csr.rowptr[-1]))
+
+
+def ss_band_extract(A, kind: int, nbands: int, p: int) -> tuple:
+    """Band p of nbands (SS_BAND_ROW / SS_BAND_COL) of host CSR A:
+    (rowptr, colidx, val, ncols)."""
+    csr = _HostCSR(A)
+    nr, nc, nz = C.c_int32(), C.c_int32(), C.c_int64()
+    _check(lib().ss_band_size(csr.ref(), int(kind), int(nbands), int(p), C.byref(nr), C.byref(nc), C.byref(nz)),
+           "ss_band_size")
+    rp = np.empty(nr.value + 1, dtype=np.int32)
+    ci = np.empty(max(nz.value, 1), dtype=np.int32)
+    v = np.empty(max(nz.value, 1))
+    _check(lib().ss_band_extract(csr.ref(), int(kind), int(nbands), int(p), _ptr(rp), _ptr(ci), _ptr(v)),
+           "ss_band_extract")
+    return rp, ci[: nz.value], v[: nz.value], nc.value
+
+
+def ss_band_setup(A, kind: int, nbands: int, opts: Optional[ss_opts] = None, device=None) -> Solver:
+    """CG on A with the band-row or band-column splitting into nbands bands
+    (all on one device); solve / apply / time with the ss_cg_* calls."""
+    torch = _torch()
+    if not torch.cuda.is_available():
+        raise RuntimeError("ss_band_setup needs a GPU")
+    dev = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+    o = default_opts() if opts is None else opts
+    alloc = _TorchAllocator(dev)
+    o.alloc = alloc.alloc_cb
+    o.free = alloc.free_cb
+    o.alloc_ctx = None
+    csr = _HostCSR(A)
+    stream = torch.cuda.current_stream(dev)
+    out = C.c_void_p()
+    with torch.cuda.device(dev):
+        _check(lib().ss_band_setup(csr.ref(), int(kind), int(nbands), C.byref(o), C.c_void_p(stream.cuda_stream),
+                                   C.byref(out)), "ss_band_setup")
     return Solver(out, alloc, stream, int(A.n), int(csr.rowptr[-1]))
 
 

@@ -399,4 +399,66 @@ int ss_part_export_local(const ss_part *p, int32_t *bd_rowptr, int32_t *bd_colid
 
 void ss_part_destroy(ss_part *p) { delete p; }
 
+// Bands (Algorithms 1 and 2): m = n / nbands indices per band, the last
+// band taking the remainder.
+static int band_check(const ss_csr *A, int32_t kind, int32_t nbands, int32_t p, int64_t *lo, int64_t *width)
+{
+    int rc = ss::validate_csr(A, false);
+    if (rc != SS_OK) return rc;
+    if (kind != SS_BAND_ROW && kind != SS_BAND_COL) return ss::fail(SS_EINVAL, "unknown band kind");
+    if (nbands < 1 || nbands > A->n) return ss::fail(SS_EINVAL, "nbands must be in [1, n]");
+    if (p < 0 || p >= nbands) return ss::fail(SS_EINVAL, "band index out of range");
+    const int64_t m = A->n / nbands;
+    *lo = (int64_t)p * m;
+    *width = p == nbands - 1 ? A->n - *lo : m;
+    return SS_OK;
+}
+
+int ss_band_size(const ss_csr *A, int32_t kind, int32_t nbands, int32_t p, int32_t *nrows, int32_t *ncols,
+                 int64_t *nnz)
+{
+    int64_t lo, w;
+    const int rc = band_check(A, kind, nbands, p, &lo, &w);
+    if (rc != SS_OK) return rc;
+    int64_t cnt = 0;
+    if (kind == SS_BAND_ROW) {
+        cnt = A->rowptr[lo + w] - A->rowptr[lo];
+    } else {
+        for (int64_t k = 0; k < A->nnz; ++k) cnt += A->colidx[k] >= lo && A->colidx[k] < lo + w;
+    }
+    if (nrows) *nrows = kind == SS_BAND_ROW ? (int32_t)w : A->n;
+    if (ncols) *ncols = kind == SS_BAND_ROW ? A->n : (int32_t)w;
+    if (nnz) *nnz = cnt;
+    return SS_OK;
+}
+
+int ss_band_extract(const ss_csr *A, int32_t kind, int32_t nbands, int32_t p, int32_t *rowptr, int32_t *colidx,
+                    double *val)
+{
+    int64_t lo, w;
+    const int rc = band_check(A, kind, nbands, p, &lo, &w);
+    if (rc != SS_OK) return rc;
+    if (!rowptr || !colidx || !val) return ss::fail(SS_EINVAL, "band arrays are NULL");
+    if (kind == SS_BAND_ROW) {
+        const int32_t first = A->rowptr[lo];
+        for (int64_t i = 0; i <= w; ++i) rowptr[i] = A->rowptr[lo + i] - first;
+        std::copy(A->colidx + first, A->colidx + A->rowptr[lo + w], colidx);
+        std::copy(A->val + first, A->val + A->rowptr[lo + w], val);
+    } else {
+        int32_t c = 0;
+        for (int32_t i = 0; i < A->n; ++i) {
+            rowptr[i] = c;
+            // columns ascend: the band's entries of a row are consecutive
+            const int32_t *b = A->colidx + A->rowptr[i], *e = A->colidx + A->rowptr[i + 1];
+            const int32_t *f = std::lower_bound(b, e, (int32_t)lo);
+            for (; f != e && *f < lo + w; ++f, ++c) {
+                colidx[c] = (int32_t)(*f - lo);
+                val[c] = A->val[f - A->colidx];
+            }
+        }
+        rowptr[A->n] = c;
+    }
+    return SS_OK;
+}
+
 }  // extern "C"

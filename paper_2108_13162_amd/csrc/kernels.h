@@ -75,6 +75,7 @@ struct Mat {
     int32_t nchunks;
     int32_t unroll;               // entries per lane loaded before use: 5, 7, 8 or 9
     int32_t one_batch;            // 1: no chunk longer than unroll (chunks pipelined)
+    int32_t band_m, nbands;       // nbands > 1: band-column product, bands of band_m columns
     const int32_t *cptr;          // [nchunks+1] start of each chunk in val
     const int32_t *ccol;          // [nchunks] >= 0: start in col16; < 0: ~start in col
     const uint16_t *col16;        // window offsets of the narrow chunks

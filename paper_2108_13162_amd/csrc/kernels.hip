@@ -23,7 +23,9 @@
 #include "device_common.h"
 
 #include <algorithm>
+#include <climits>
 #include <cmath>
+#include <type_traits>
 
 namespace ss {
 namespace {
@@ -259,6 +261,16 @@ __device__ __forceinline__ void decode_cols(int (&cc)[U], const uint32_t (&c16)[
     }
 }
 
+// Band-column product (one device): the row sum is split where the column
+// crosses into the next band of bm columns (the last band takes the rest);
+// the band partial sums are added in band order.  First column of the band
+// after the one holding column col (INT_MAX for the last band).
+__device__ __forceinline__ int band_next(int col, int bm, int nbands)
+{
+    const int b = col / bm;
+    return b >= nbands - 1 ? INT_MAX : (b + 1) * bm;
+}
+
 // ONE: every chunk has at most U entries per row, so a chunk is one batch.
 // Then the wave software-pipelines its chunks: the gathers of chunk c are
 // issued first, then the loads of chunk c+W (header, values, columns, the
@@ -267,7 +279,8 @@ __device__ __forceinline__ void decode_cols(int (&cc)[U], const uint32_t (&c16)[
 // only (vector loads return in issue order) while chunk c+W's loads stay in
 // flight.  Otherwise (rows longer than U) the batches of each chunk are
 // walked in turn, each batch's gathers waiting for its own loads.
-template <typename VT, typename XT, int MODE, int U, bool ONE>
+// BAND: the band-column product (positions are global ids, bands of bm).
+template <typename VT, typename XT, int MODE, int U, bool ONE, bool BAND>
 __global__ __launch_bounds__(kBS) __attribute__((amdgpu_waves_per_eu(1, 4))) void k_spmv_sell(
     int32_t nrows, int32_t nchunks, const int32_t *__restrict__ cptr, const int32_t *__restrict__ cpos,
     const uint8_t *__restrict__ clen, const uint8_t *__restrict__ rlen, const int32_t *__restrict__ ccol,
@@ -275,7 +288,7 @@ __global__ __launch_bounds__(kBS) __attribute__((amdgpu_waves_per_eu(1, 4))) voi
     const VT *__restrict__ val, const XT *__restrict__ pin, const XT *__restrict__ r, XT *__restrict__ pout,
     XT *__restrict__ q, XT *__restrict__ x, double *__restrict__ part_a, const double *__restrict__ part_b,
     const double *__restrict__ part_b2, int32_t nb, int32_t slot, DevState *__restrict__ st,
-    const int32_t *__restrict__ gate)
+    const int32_t *__restrict__ gate, int32_t bm, int32_t nbands)
 {
     constexpr bool CG = MODE != SPMV_PLAIN;
     constexpr int W = kBS / 64;
@@ -363,11 +376,31 @@ __global__ __launch_bounds__(kBS) __attribute__((amdgpu_waves_per_eu(1, 4))) voi
             XT nr, np, nx;
             load_row<XT, MODE>(nlen, nr, np, nx, nrow, nrows, rlen, r, pin, x);
             __builtin_amdgcn_sched_barrier(0);
-            XT sacc = XT(0);
+            XT prod[U];
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const XT xx = CG ? pupd(rx[u], px[u], beta) : px[u];
-                if (u < len) sacc = sacc + (XT)vv[u] * xx;
+            for (int u = 0; u < U; ++u) prod[u] = (XT)vv[u] * (CG ? pupd(rx[u], px[u], beta) : px[u]);
+            XT sacc = XT(0);
+            if constexpr (BAND) {
+                // the products exist before the band bookkeeping branches
+#pragma unroll
+                for (int u = 0; u < U; ++u) asm volatile("" : "+v"(prod[u]));
+                XT btot = XT(0);
+                int bnext = -1;  // the first entry opens the row's first band
+#pragma unroll
+                for (int u = 0; u < U; ++u)
+                    if (u < len) {
+                        if (cc[u] >= bnext) {
+                            btot = btot + sacc;
+                            sacc = XT(0);
+                            bnext = band_next(cc[u], bm, nbands);
+                        }
+                        sacc = sacc + prod[u];
+                    }
+                sacc = btot + sacc;
+            } else {
+#pragma unroll
+                for (int u = 0; u < U; ++u)
+                    if (u < len) sacc = sacc + prod[u];
             }
             // computed here, on every lane: otherwise the compiler sinks the
             // products -- and the gathers with them -- into the store branch
@@ -408,6 +441,8 @@ __global__ __launch_bounds__(kBS) __attribute__((amdgpu_waves_per_eu(1, 4))) voi
             }
             len = row < nrows ? (int)rlen[row] : 0;
             XT sacc = XT(0);
+            XT btot = XT(0);
+            int bnext = -1;
             for (int j0 = 0; j0 < L; j0 += U) {
                 if (!have) {
                     load_cols<U>(cc, cb, wb, j0, L, lane, col, col16);
@@ -420,8 +455,16 @@ __global__ __launch_bounds__(kBS) __attribute__((amdgpu_waves_per_eu(1, 4))) voi
                 for (int u = 0; u < U; ++u) xx[u] = CG ? pupd(r[cc[u]], pin[cc[u]], beta) : pin[cc[u]];
 #pragma unroll
                 for (int u = 0; u < U; ++u)
-                    if (j0 + u < len) sacc = sacc + (XT)vv[u] * xx[u];
+                    if (j0 + u < len) {
+                        if (BAND && cc[u] >= bnext) {
+                            btot = btot + sacc;
+                            sacc = XT(0);
+                            bnext = band_next(cc[u], bm, nbands);
+                        }
+                        sacc = sacc + (XT)vv[u] * xx[u];
+                    }
             }
+            if (BAND) sacc = btot + sacc;
             have = false;
             if (row < nrows) {
                 q[row] = sacc;
@@ -1034,25 +1077,34 @@ void spmv_dispatch(hipStream_t s, const Mat &A, const XT *pin, const XT *r, XT *
     if (A.nrows == 0) return;
     const dim3 grid(A.grid), block(kBS);
     if (A.fmt == FMT_SELL) {
-#define SS_SELL(U, ONE)                                                                                          \
-    hipLaunchKernelGGL((k_spmv_sell<VT, XT, MODE, U, ONE>), grid, block, 0, s, A.nrows, A.nchunks, A.cptr, A.cpos, \
-                       A.clen, A.rlen, A.ccol, A.col, A.col16, A.cbase, (const VT *)A.val, pin, r, pout, q, x, P.a, \
-                       (const double *)P.b, (const double *)P.b2, P.nb, slot, st, gate)
-        if (A.one_batch) {
-            switch (A.unroll) {
-            case 5: SS_SELL(5, true); break;
-            case 7: SS_SELL(7, true); break;
-            case 9: SS_SELL(9, true); break;
-            default: SS_SELL(8, true); break;
-            }
-        } else {
-            switch (A.unroll) {
-            case 5: SS_SELL(5, false); break;
-            case 7: SS_SELL(7, false); break;
-            case 9: SS_SELL(9, false); break;
-            default: SS_SELL(8, false); break;
+#define SS_SELL(U, ONE, BAND)                                                                                    \
+    hipLaunchKernelGGL((k_spmv_sell<VT, XT, MODE, U, ONE, BAND>), grid, block, 0, s, A.nrows, A.nchunks, A.cptr,  \
+                       A.cpos, A.clen, A.rlen, A.ccol, A.col, A.col16, A.cbase, (const VT *)A.val, pin, r, pout, q, x, \
+                       P.a, (const double *)P.b, (const double *)P.b2, P.nb, slot, st, gate, A.band_m, A.nbands)
+#define SS_SELL_U(ONE, BAND)                    \
+    switch (A.unroll) {                         \
+    case 5: SS_SELL(5, ONE, BAND); break;       \
+    case 7: SS_SELL(7, ONE, BAND); break;       \
+    case 9: SS_SELL(9, ONE, BAND); break;       \
+    default: SS_SELL(8, ONE, BAND); break;      \
+    }
+        // the band-column product exists in FP64 only (the setup refuses others)
+        if constexpr (std::is_same<VT, double>::value && std::is_same<XT, double>::value) {
+            if (A.nbands > 1) {
+                if (A.one_batch) {
+                    SS_SELL_U(true, true)
+                } else {
+                    SS_SELL_U(false, true)
+                }
+                return;
             }
         }
+        if (A.one_batch) {
+            SS_SELL_U(true, false)
+        } else {
+            SS_SELL_U(false, false)
+        }
+#undef SS_SELL_U
 #undef SS_SELL
         return;
     }

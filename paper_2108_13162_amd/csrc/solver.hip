@@ -457,41 +457,10 @@ int ensure_hist(ss_solver *s, int32_t cap)
     return SS_OK;
 }
 
-}  // namespace
-
-extern "C" {
-
-void ss_opts_default(ss_opts *o)
-{
-    if (!o) return;
-    std::memset(o, 0, sizeof(*o));
-    o->precision = SS_FP64;
-    o->inner_tol = 1e-6;
-    o->ru_delta = 0.1;
-    o->inner_maxit = 0;
-    o->max_outer = 50;
-    o->check_every = kDefaultCheck;
-    o->use_graph = 1;
-    o->tile_nnz = 0;
-    o->matrix_format = SS_MAT_AUTO;
-}
-
-void ss_cg_destroy(ss_solver *s)
-{
-    if (!s) return;
-    if (s->stream) (void)hipStreamSynchronize(s->stream);
-    destroy_graph(s->run64);
-    destroy_graph(s->run32);
-    for (auto &e : s->ev)
-        if (e) (void)hipEventDestroy(e);
-    if (s->st_pinned) (void)hipHostFree(s->st_pinned);
-    if (s->flag_pinned) (void)hipHostFree(s->flag_pinned);
-    if (s->cap) (void)hipStreamDestroy(s->cap);
-    s->mem.clear();
-    delete s;
-}
-
-int ss_cg_setup(const ss_csr *A, const ss_part *p, const ss_opts *o, void *hip_stream, ss_solver **out)
+// The setup of ss_cg_setup; band_kind >= 0: the band splitting band_kind into
+// nbands bands, p being the one-part partition of A.
+int setup_impl(const ss_csr *A, const ss_part *p, const ss_opts *o, void *hip_stream, ss_solver **out,
+               int32_t band_kind, int32_t nbands)
 {
     if (!out) return fail(SS_EINVAL, "out is NULL");
     *out = nullptr;
@@ -529,14 +498,28 @@ int ss_cg_setup(const ss_csr *A, const ss_part *p, const ss_opts *o, void *hip_s
     if (opts.precision == SS_FP32_IR && !(opts.inner_tol > 0.0 && opts.inner_tol < 1.0))
         return fail(SS_EINVAL, "inner_tol must be in (0, 1)");
 
+    const bool band_col = band_kind == SS_BAND_COL && nbands > 1;
+    if (band_kind >= 0 && opts.precision != SS_FP64)
+        return fail(SS_EUNSUPPORTED, "the band splittings are available with SS_FP64 only");
+    if (band_col && opts.matrix_format == SS_MAT_CSR)
+        return fail(SS_EUNSUPPORTED, "the band-column product needs the SELL layout");
+
     Layout L;
     try {
         build_order(p, L);
-        build_matrix(p, L, opts.tile_nnz ? opts.tile_nnz : 2048, opts.matrix_format);
+        build_matrix(p, L, opts.tile_nnz ? opts.tile_nnz : 2048, band_col ? SS_MAT_SELL : opts.matrix_format);
     } catch (const std::bad_alloc &) {
         return fail(SS_ENOMEM, "host allocation failed");
     }
     if (!L.encode_ok) return fail(SS_EINVAL, "internal: column encoding check failed");
+    if (band_kind >= 0) {
+        // one part: every position is the global index it holds, so a
+        // column position is a global column
+        for (size_t c = 0; c < L.l2g.size(); ++c)
+            if (L.l2g[c] != (int32_t)c) return fail(SS_EINVAL, "internal: one-part positions are not global ids");
+        if (band_col && L.fmt != FMT_SELL)
+            return fail(SS_EUNSUPPORTED, "the band-column product needs rows of at most 255 entries");
+    }
 
     ss_solver *s = new (std::nothrow) ss_solver;
     if (!s) return fail(SS_ENOMEM, "host allocation failed");
@@ -577,6 +560,8 @@ int ss_cg_setup(const ss_csr *A, const ss_part *p, const ss_opts *o, void *hip_s
     M.nchunks = L.nchunks;
     M.unroll = L.unroll;
     M.one_batch = L.one_batch;
+    M.band_m = band_kind >= 0 ? A->n / nbands : 0;
+    M.nbands = band_col ? nbands : 0;
     M.ntiles = L.ntiles;
     M.tile_nnz = L.tile_nnz;
     const int work = L.fmt == FMT_SELL ? (L.nchunks + kBS / 64 - 1) / (kBS / 64) : L.ntiles;
@@ -672,6 +657,69 @@ int ss_cg_setup(const ss_csr *A, const ss_part *p, const ss_opts *o, void *hip_s
         return bail(fail(SS_EDEVICE, "upload failed"));
     *out = s;
     return SS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void ss_opts_default(ss_opts *o)
+{
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->precision = SS_FP64;
+    o->inner_tol = 1e-6;
+    o->ru_delta = 0.1;
+    o->inner_maxit = 0;
+    o->max_outer = 50;
+    o->check_every = kDefaultCheck;
+    o->use_graph = 1;
+    o->tile_nnz = 0;
+    o->matrix_format = SS_MAT_AUTO;
+}
+
+void ss_cg_destroy(ss_solver *s)
+{
+    if (!s) return;
+    if (s->stream) (void)hipStreamSynchronize(s->stream);
+    destroy_graph(s->run64);
+    destroy_graph(s->run32);
+    for (auto &e : s->ev)
+        if (e) (void)hipEventDestroy(e);
+    if (s->st_pinned) (void)hipHostFree(s->st_pinned);
+    if (s->flag_pinned) (void)hipHostFree(s->flag_pinned);
+    if (s->cap) (void)hipStreamDestroy(s->cap);
+    s->mem.clear();
+    delete s;
+}
+
+
+int ss_cg_setup(const ss_csr *A, const ss_part *p, const ss_opts *o, void *hip_stream, ss_solver **out)
+{
+    return setup_impl(A, p, o, hip_stream, out, -1, 0);
+}
+
+int ss_band_setup(const ss_csr *A, int32_t kind, int32_t nbands, const ss_opts *o, void *hip_stream,
+                  ss_solver **out)
+{
+    if (!out) return fail(SS_EINVAL, "out is NULL");
+    *out = nullptr;
+    int rc = validate_csr(A, false);
+    if (rc != SS_OK) return rc;
+    if (kind != SS_BAND_ROW && kind != SS_BAND_COL) return fail(SS_EINVAL, "unknown band kind");
+    if (nbands < 1 || nbands > A->n) return fail(SS_EINVAL, "nbands must be in [1, n]");
+    std::vector<int32_t> zero;
+    try {
+        zero.assign((size_t)A->n, 0);
+    } catch (const std::bad_alloc &) {
+        return fail(SS_ENOMEM, "host allocation failed");
+    }
+    ss_part *p = nullptr;
+    rc = ss_partition(A, SS_PART_USER, 1, 0, nullptr, nullptr, nullptr, nullptr, zero.data(), &p);
+    if (rc != SS_OK) return rc;
+    rc = setup_impl(A, p, o, hip_stream, out, kind, nbands);
+    ss_part_destroy(p);
+    return rc;
 }
 
 int ss_cg_info(const ss_solver *s, int32_t *n, int32_t *n_loc, int64_t *nnz, int32_t *matrix_format,

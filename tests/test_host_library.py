@@ -170,3 +170,38 @@ def test_batch_setup_rejects_invalid_inputs_before_device_use():
     assert L.ss_batch_setup(1, arr, 4, None, None, C.byref(out)) == ss.SS_EUNSUPPORTED
     assert "255" in ss.last_error()
     assert not out.value
+
+
+# ----------------------------------------------------------------------------
+# band splittings (Algorithms 1 and 2): host extraction, bit-exact vs oracle
+# ----------------------------------------------------------------------------
+
+@pytest.mark.parametrize("kind", [ss.SS_BAND_ROW, ss.SS_BAND_COL])
+@pytest.mark.parametrize("which,nbands", [("cfg1", 1), ("cfg1", 4), ("cfg1", 7), ("random", 3), ("random", 61)])
+def test_band_extract_bit_exact(kind, which, nbands):
+    A = config(1).A if which == "cfg1" else random_spd_csr(61, 5.0, seed=4)
+    for p in range(nbands):
+        got = ss.ss_band_extract(A, kind, nbands, p)
+        want = O.band_extract(A, kind, nbands, p)
+        assert got[3] == want[3]
+        for g, w in zip(got[:3], want[:3]):
+            assert np.array_equal(g, w), (kind, which, nbands, p)
+
+
+def test_band_extract_paper_example(golden_dir):
+    from test_oracle_pins import _dense_to_csr, _read_golden
+    g = _read_golden(os.path.join(golden_dir, "paper_csr_example.txt"))
+    A = _dense_to_csr(np.array(g["matrix"]))  # not symmetric: extraction only needs a valid CSR
+    for kind in (ss.SS_BAND_ROW, ss.SS_BAND_COL):
+        for nb in range(1, 6):
+            for p in range(nb):
+                got, want = ss.ss_band_extract(A, kind, nb, p), O.band_extract(A, kind, nb, p)
+                assert all(np.array_equal(a, b) for a, b in zip(got[:3], want[:3])) and got[3] == want[3]
+
+
+def test_band_invalid_inputs_rejected():
+    A = random_spd_csr(10, 2.0, seed=1)
+    for kind, nb, p in [(2, 2, 0), (0, 0, 0), (0, 11, 0), (1, 3, 3), (1, 3, -1)]:
+        with pytest.raises(ss.SSError) as e:
+            ss.ss_band_extract(A, kind, nb, p)
+        assert e.value.code == ss.SS_EINVAL
