@@ -24,10 +24,13 @@ measurement (time to relative residual 1e-10, inputs resident):
   adjoint  -- 64^3 smoothed-GRF diffusion, 8 boxes: forward solve and
               forward + adjoint backward through torch.autograd;
   jacobi   -- the main line's system with the Jacobi preconditioner
-              (Algorithm 3 with M = diag A) vs plain CG.
+              (Algorithm 3 with M = diag A) vs plain CG;
+  splittings -- the main line's system cut three ways into 8 parts:
+              sub-structuring (8 boxes), band-row and band-column (8 bands),
+              with the values each would exchange per product across devices.
 
   python bench.py [--steps K] [--warmup W] [--gpus 1] [--config 2]
-                  [--variants mixed,batched,adjoint | none]
+                  [--variants mixed,batched,adjoint,jacobi,splittings | none]
 """
 from __future__ import annotations
 
@@ -252,6 +255,65 @@ def variant_jacobi(ss, torch, reps: int, tol: float) -> dict:
     return out
 
 
+def exchange_volumes(ss, A, part, nbands: int) -> dict:
+    """Values one CG product would move between parts if every part sat on its
+    own device (the least each scheme needs), per splitting of A:
+    sub-structuring: every copy of an interface node sends its partial sum to
+    the other holders; band-row: every band receives the x entries its rows
+    reference outside the band; band-column: every band sends the partial y
+    entries of rows outside the band."""
+    import numpy as np
+
+    n = A.n
+    m = n // nbands
+    rows = np.repeat(np.arange(n, dtype=np.int64), np.diff(A.rowptr))
+    cols = A.colidx.astype(np.int64)
+    brow = np.minimum(rows // m, nbands - 1)
+    bcol = np.minimum(cols // m, nbands - 1)
+    off = brow != bcol
+    row_x = np.unique(brow[off] * n + cols[off]).size   # (band, x entry) pairs
+    col_y = np.unique(bcol[off] * n + rows[off]).size   # (band, y entry) pairs
+    e = ss.ss_part_export(part)
+    mult = np.diff(e["copy_ptr"]).astype(np.int64)
+    return {"sub_structuring": int(np.sum(mult * (mult - 1))), "band_row": int(row_x), "band_col": int(col_y),
+            "band_row_allgather": int((nbands - 1) * n), "band_col_allreduce": int(nbands * n)}
+
+
+def variant_splittings(ss, torch, reps: int, tol: float) -> dict:
+    """The paper's three decompositions of the same system into 8 parts
+    (Sections 3.1, 3.2, 3.4), all parts on this device: sub-structuring (the
+    8 boxes of the main line), band-row and band-column (8 bands): time to the
+    tolerance, the CG-step product's bandwidth, and the values each would
+    exchange per product across devices."""
+    from workloads import config
+
+    w = config(2)
+    part = ss.partition_workload(w)
+    b = torch.tensor(w.b, dtype=torch.float64, device="cuda")
+    out = {"workload": w.name, "parts": 8}
+    makers = (("sub_structuring", lambda: ss.ss_cg_setup(w.A, part)),
+              ("band_row", lambda: ss.ss_band_setup(w.A, ss.SS_BAND_ROW, 8)),
+              ("band_col", lambda: ss.ss_band_setup(w.A, ss.SS_BAND_COL, 8)))
+    for name, make in makers:
+        s = make()
+        x = torch.zeros_like(b)
+
+        def run():
+            x.zero_()
+            return ss.ss_cg_solve(s, b, x, tol=tol, maxit=100000)
+
+        ms, r = _timed(torch, run, reps)
+        spmv_ms, spmv_bytes = ss.ss_cg_time_spmv(s, 50)
+        out[name] = {"ms": round(ms, 3), "status": r.status, "iterations": r.iterations,
+                     "true_relres": r.true_relres, "ms_per_iteration": round(ms / max(r.iterations, 1), 5),
+                     "step_spmv_us": round(spmv_ms * 1e3, 2),
+                     "step_spmv_gbps": round(spmv_bytes / (spmv_ms * 1e-3) / 1e9, 1)}
+        print(f"# splittings/{name}: {ms:.3f} ms, {r.iterations} iterations", file=sys.stderr, flush=True)
+        del s
+    out["exchange_values_per_product"] = exchange_volumes(ss, w.A, part, 8)
+    return out
+
+
 def variant_adjoint(ss, torch, reps: int, tol: float) -> dict:
     from workloads import config
 
@@ -371,8 +433,8 @@ def main() -> int:
     ap.add_argument("--tol", type=float, default=1e-10)
     ap.add_argument("--cpu-iters", type=int, default=150)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--variants", default="mixed,batched,adjoint,jacobi",
-                    help="comma list of mixed, batched, adjoint, jacobi; 'none' to skip")
+    ap.add_argument("--variants", default="mixed,batched,adjoint,jacobi,splittings",
+                    help="comma list of mixed, batched, adjoint, jacobi, splittings; 'none' to skip")
     ap.add_argument("--variant-steps", type=int, default=3)
     ap.add_argument("--no-main", action="store_true",
                     help="profiling aid: skip the main measurement, print only the variants")
@@ -399,7 +461,8 @@ def main() -> int:
     if out is None:
         return 1
     chosen = [v for v in args.variants.split(",") if v and v != "none"]
-    funcs = {"mixed": variant_mixed, "batched": variant_batched, "adjoint": variant_adjoint, "jacobi": variant_jacobi}
+    funcs = {"mixed": variant_mixed, "batched": variant_batched, "adjoint": variant_adjoint, "jacobi": variant_jacobi,
+             "splittings": variant_splittings}
     if chosen:
         out["variants"] = {}
         for v in chosen:
