@@ -26,8 +26,9 @@ measurement (time to relative residual 1e-10, inputs resident):
   jacobi   -- the main line's system with the Jacobi preconditioner
               (Algorithm 3 with M = diag A) vs plain CG;
   splittings -- the main line's system cut three ways into 8 parts:
-              sub-structuring (8 boxes), band-row and band-column (8 bands),
-              with the values each would exchange per product across devices.
+              sub-structuring (8 boxes, and 8 parts of the matrix graph
+              without coordinates), band-row and band-column (8 bands), with
+              the values each would exchange per product across devices.
 
   python bench.py [--steps K] [--warmup W] [--gpus 1] [--config 2]
                   [--variants mixed,batched,adjoint,jacobi,splittings | none]
@@ -287,11 +288,17 @@ def variant_splittings(ss, torch, reps: int, tol: float) -> dict:
     exchange per product across devices."""
     from workloads import config
 
+    import numpy as np
+
     w = config(2)
     part = ss.partition_workload(w)
+    t0 = time.perf_counter()
+    gpart = ss.ss_partition(w.A, ss.SS_PART_GRAPH, 8)   # no coordinates: the adjacency graph only
+    graph_s = time.perf_counter() - t0
     b = torch.tensor(w.b, dtype=torch.float64, device="cuda")
     out = {"workload": w.name, "parts": 8}
     makers = (("sub_structuring", lambda: ss.ss_cg_setup(w.A, part)),
+              ("sub_structuring_graph", lambda: ss.ss_cg_setup(w.A, gpart)),
               ("band_row", lambda: ss.ss_band_setup(w.A, ss.SS_BAND_ROW, 8)),
               ("band_col", lambda: ss.ss_band_setup(w.A, ss.SS_BAND_COL, 8)))
     for name, make in makers:
@@ -311,6 +318,10 @@ def variant_splittings(ss, torch, reps: int, tol: float) -> dict:
         print(f"# splittings/{name}: {ms:.3f} ms, {r.iterations} iterations", file=sys.stderr, flush=True)
         del s
     out["exchange_values_per_product"] = exchange_volumes(ss, w.A, part, 8)
+    mult = np.diff(ss.ss_part_export(gpart)["copy_ptr"]).astype(np.int64)
+    out["exchange_values_per_product"]["sub_structuring_graph"] = int(np.sum(mult * (mult - 1)))
+    out["graph_partition"] = {"host_seconds": round(graph_s, 3), **{k: v for k, v in ss.ss_part_sizes(gpart).items()
+                                                                   if k in ("n_loc", "n_gamma", "n_copies")}}
     return out
 
 

@@ -67,7 +67,8 @@ typedef struct {
 enum {
     SS_PART_BOX = 0,  /* structured grid cut into boxes                    */
     SS_PART_RCB = 1,  /* weighted recursive coordinate bisection           */
-    SS_PART_USER = 2  /* node -> sub-domain array given by the caller      */
+    SS_PART_USER = 2, /* node -> sub-domain array given by the caller      */
+    SS_PART_GRAPH = 3 /* multilevel bisection of the adjacency graph of A  */
 };
 
 typedef struct ss_part ss_part;     /* opaque, host memory */
@@ -90,6 +91,13 @@ typedef struct ss_solver ss_solver; /* opaque, owns device buffers */
  *          floor(|S| * W[lo,mid) / W[lo,hi) + 0.5) go to [lo, mid),
  *          mid = (lo+hi)/2; weight sums are sequential left to right.
  *    USER: user_part[n] with values in [0, nparts).
+ *    GRAPH: no geometry needed: multilevel recursive bisection of the
+ *          adjacency graph of A (off-diagonal entries = edges of weight 1):
+ *          heavy-edge coarsening, a grown bisection of the coarsest graph,
+ *          Fiduccia-Mattheyses refinement on the way back; each bisection
+ *          splits the part range [lo,hi) at mid = lo + (hi-lo)/2 with target
+ *          weights W[lo,mid) : W[mid,hi) (weights as RCB) and lets a side
+ *          exceed its target by 1%.  Deterministic.
  *    Unused pointer arguments may be NULL.
  * 2. Split of the matrix into local matrices A_s (the paper's S_s, whose
  *    interface block is a partial sum, S_33 = sum_s S_33^(s)): every stored

@@ -24,7 +24,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libss.so")
 
 SS_OK, SS_NOT_CONVERGED, SS_EINVAL, SS_ENOMEM, SS_EDEVICE, SS_EBREAKDOWN, SS_EUNSUPPORTED = 0, 1, -1, -2, -3, -4, -5
-SS_PART_BOX, SS_PART_RCB, SS_PART_USER = 0, 1, 2
+SS_PART_BOX, SS_PART_RCB, SS_PART_USER, SS_PART_GRAPH = 0, 1, 2, 3
 SS_BAND_ROW, SS_BAND_COL = 0, 1
 SS_FP64, SS_FP32_IR, SS_FP32_RU = 0, 1, 2
 SS_MAT_AUTO, SS_MAT_SELL, SS_MAT_CSR = 0, 1, 2

@@ -332,6 +332,7 @@ int ss_partition(const ss_csr *A, int32_t method, int32_t nparts, int32_t dim, c
         switch (method) {
         case SS_PART_BOX: rc = ss::partition_box(A->n, dim, grid, boxes, nparts, p->part); break;
         case SS_PART_RCB: rc = ss::partition_rcb(A->n, dim, coords, weights, nparts, p->part); break;
+        case SS_PART_GRAPH: rc = ss::partition_graph(A, weights, nparts, p->part); break;
         case SS_PART_USER:
             if (!user_part) { rc = ss::fail(SS_EINVAL, "USER partition needs user_part"); break; }
             p->part.assign(user_part, user_part + A->n);

@@ -20,6 +20,7 @@ int partition_box(int32_t n, int32_t dim, const int32_t *grid, const int32_t *bo
                   std::vector<int32_t> &part);
 int partition_rcb(int32_t n, int32_t dim, const double *coords, const double *weights, int32_t nparts,
                   std::vector<int32_t> &part);
+int partition_graph(const ss_csr *A, const double *weights, int32_t nparts, std::vector<int32_t> &part);
 
 }  // namespace ss
 
