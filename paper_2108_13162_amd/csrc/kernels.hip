@@ -5,12 +5,15 @@
 //   k_update: finishes (p, A p) -> alpha, assembles the interface values of
 //             q = A_bd p (Algorithms 4 and 5: every copy of an interface node
 //             reads all copies and adds them in ascending sub-domain order),
-//             x += alpha p, r -= alpha q, and writes partials of the weighted
-//             local (r, r) (Section 4.4.2);
-//   k_spmv_*: finishes (r, r) -> beta and the stopping test, p = r + beta p
-//             recomputed on the fly, the local SpMV of every sub-domain on the
-//             block-diagonal matrix (Section 4.4.1, first step) and partials
-//             of (p, A_s p).
+//             r -= alpha q, and writes partials of the weighted local (r, r)
+//             (Section 4.4.2);
+//   k_spmv_*: finishes (r, r) -> beta and the stopping test, applies the
+//             previous update's x += alpha p to its own rows, forms
+//             p = r + beta p on the fly, runs the local SpMV of every
+//             sub-domain on the block-diagonal matrix (Section 4.4.1, first
+//             step) and writes partials of (p, A_s p).
+// The SELL kernel also computes the band-column product of the band
+// splitting (Section 4.3.1) when instantiated with BAND.
 // "Finishes" means: every workgroup adds up the previous kernel's
 // per-workgroup partials itself, in one fixed order, so all workgroups obtain
 // bitwise the same scalar without a grid-wide barrier or a separate launch;
