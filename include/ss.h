@@ -263,13 +263,15 @@ int ss_cg_set_values(ss_solver *s, const double *val_dev);
  * device.  dL/db equals lambda itself. */
 int ss_cg_grad_vals(ss_solver *s, const double *lambda_dev, const double *x_dev, double *dvals_dev);
 
-/* Average duration in milliseconds of one launch of the local SpMV kernel
- * (the CG-step variant; the FP32 inner step for an SS_FP32_IR solver),
- * timed with one HIP event pair around `reps` back-to-back launches on the
- * solver stream.  Leaves the solver state unchanged except for scratch
- * vectors.  Also reports the algorithmic bytes that launch moves (values and
- * column data of the stored entries, row structure, one read of r, p and x,
- * writes of p, q and x). */
+/* Average duration in milliseconds of one CG step (beta, p = r + beta p,
+ * the local SpMV, (p, A p); the FP32 inner step for the SS_FP32_* modes):
+ * one launch, or for matrices whose rows take several load batches (rows of
+ * more than 9 entries) two launches -- p formed, then the SpMV on it -- timed
+ * with one HIP event pair around `reps` back-to-back steps on the solver
+ * stream.  Leaves the solver state unchanged except for scratch vectors.
+ * Also reports the algorithmic bytes a step moves (values and column data of
+ * the stored entries, row structure, one read of r, p and x, writes of p, q
+ * and x; the two-launch step also reads p back). */
 int ss_cg_time_spmv(ss_solver *s, int32_t reps, double *ms_per_launch, double *bytes_per_launch);
 
 /* Sizes of the device problem (any pointer may be NULL): matrix_format is

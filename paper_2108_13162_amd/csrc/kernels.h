@@ -89,6 +89,11 @@ struct Mat {
     int32_t ntiles, tile_nnz;
 };
 
+// The CG step is split (p formed by k_pstep, then the SpMV on it) for SELL
+// storage whose rows take several load batches; one-batch matrices keep the
+// fused, pipelined step.
+inline bool split_step(const Mat &A) { return A.fmt == FMT_SELL && !A.one_batch; }
+
 // Device position order: [0, n_own) owned interface copies, [n_own, n_if)
 // the other interface copies, [n_if, n_loc) the interior positions of every
 // sub-domain.  pos_grp[c] = interface node of copy c (c < n_if).  The update

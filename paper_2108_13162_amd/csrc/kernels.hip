@@ -131,7 +131,11 @@ __device__ __forceinline__ XT pupd(XT r, XT p, double beta)
     return (XT)((double)r + beta * (double)p);
 }
 
-enum { SPMV_PLAIN = 0, SPMV_FIRST = 1, SPMV_STEP = 2 };
+// PLAIN: q = A x.  FIRST / STEP: p = r + beta p formed on the fly at every
+// gathered column (beta = 0 for FIRST), q = A p, (p, A p) partials; STEP also
+// finishes (r, r) and applies the previous x update.  PQ: q = A p for a p
+// already formed (k_pstep), (p, A p) partials.
+enum { SPMV_PLAIN = 0, SPMV_FIRST = 1, SPMV_STEP = 2, SPMV_PQ = 3 };
 
 // The CG-step prologue: finish (r, r) [and (r, z)] of the previous update,
 // record iteration k+1 (workgroup 0), stopping test on ||r||.  Returns
@@ -245,10 +249,8 @@ __device__ __forceinline__ void load_row(int &len, XT &rv, XT &pv, XT &xv, int r
     const int l = rlen[t];
     len = row < nrows ? l : 0;
     rv = pv = xv = XT(0);
-    if (MODE != SPMV_PLAIN) {
-        rv = r[t];
-        pv = p[t];
-    }
+    if (MODE == SPMV_FIRST || MODE == SPMV_STEP) rv = r[t];
+    if (MODE != SPMV_PLAIN) pv = p[t];
     if (MODE == SPMV_STEP) xv = x[t];
 }
 
@@ -293,7 +295,8 @@ __global__ __launch_bounds__(kBS) __attribute__((amdgpu_waves_per_eu(1, 4))) voi
     const double *__restrict__ part_b2, int32_t nb, int32_t slot, DevState *__restrict__ st,
     const int32_t *__restrict__ gate, int32_t bm, int32_t nbands)
 {
-    constexpr bool CG = MODE != SPMV_PLAIN;
+    constexpr bool CG = MODE != SPMV_PLAIN;                        // status, (p, A p)
+    constexpr bool PUPD = MODE == SPMV_FIRST || MODE == SPMV_STEP;  // p formed here
     constexpr int W = kBS / 64;
     __shared__ double ws[2 * (kBS / 64) + 2];
     __shared__ int s_flag;
@@ -361,7 +364,7 @@ __global__ __launch_bounds__(kBS) __attribute__((amdgpu_waves_per_eu(1, 4))) voi
             decode_cols<U>(cc, c16, c32, cb, wb);
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                if (CG) rx[u] = r[cc[u]];
+                if (PUPD) rx[u] = r[cc[u]];
                 px[u] = pin[cc[u]];
             }
             // keep the issue order: the scheduler would otherwise interleave
@@ -381,7 +384,7 @@ __global__ __launch_bounds__(kBS) __attribute__((amdgpu_waves_per_eu(1, 4))) voi
             __builtin_amdgcn_sched_barrier(0);
             XT prod[U];
 #pragma unroll
-            for (int u = 0; u < U; ++u) prod[u] = (XT)vv[u] * (CG ? pupd(rx[u], px[u], beta) : px[u]);
+            for (int u = 0; u < U; ++u) prod[u] = (XT)vv[u] * (PUPD ? pupd(rx[u], px[u], beta) : px[u]);
             XT sacc = XT(0);
             if constexpr (BAND) {
                 // the products exist before the band bookkeeping branches
@@ -411,8 +414,8 @@ __global__ __launch_bounds__(kBS) __attribute__((amdgpu_waves_per_eu(1, 4))) voi
             if (row < nrows) {
                 q[row] = sacc;
                 if (CG) {
-                    const XT pr = pupd(rrow, prow, beta);
-                    pout[row] = pr;
+                    const XT pr = PUPD ? pupd(rrow, prow, beta) : prow;
+                    if (PUPD) pout[row] = pr;
                     if (MODE == SPMV_STEP) x[row] = (XT)((double)xrow + alpha * (double)prow);
                     acc = acc + (double)pr * (double)sacc;
                 }
@@ -455,7 +458,7 @@ __global__ __launch_bounds__(kBS) __attribute__((amdgpu_waves_per_eu(1, 4))) voi
                 have = false;
                 XT xx[U];
 #pragma unroll
-                for (int u = 0; u < U; ++u) xx[u] = CG ? pupd(r[cc[u]], pin[cc[u]], beta) : pin[cc[u]];
+                for (int u = 0; u < U; ++u) xx[u] = PUPD ? pupd(r[cc[u]], pin[cc[u]], beta) : pin[cc[u]];
 #pragma unroll
                 for (int u = 0; u < U; ++u)
                     if (j0 + u < len) {
@@ -473,8 +476,8 @@ __global__ __launch_bounds__(kBS) __attribute__((amdgpu_waves_per_eu(1, 4))) voi
                 q[row] = sacc;
                 if (CG) {
                     const XT pold = pin[row];
-                    const XT pr = pupd(r[row], pold, beta);
-                    pout[row] = pr;
+                    const XT pr = PUPD ? pupd(r[row], pold, beta) : pold;
+                    if (PUPD) pout[row] = pr;
                     if (MODE == SPMV_STEP) x[row] = (XT)((double)x[row] + alpha * (double)pold);
                     acc = acc + (double)pr * (double)sacc;
                 }
@@ -484,6 +487,52 @@ __global__ __launch_bounds__(kBS) __attribute__((amdgpu_waves_per_eu(1, 4))) voi
     if (CG) {
         const double part = block_sum_all(acc, ws);
         if (threadIdx.x == 0) part_a[blockIdx.x] = part;
+    }
+}
+
+// ---- the p-update of the split CG step ------------------------------------
+//
+// For matrices whose rows take several batches (27-point stencils), forming
+// p = r + beta p at every gathered column doubles the gathers of the SpMV;
+// there the step is split: this kernel finishes (r, r) -> beta and the
+// stopping test (as the fused step's prologue), writes p_k = r + beta p_(k-1)
+// (the same expression, so the same bits) and applies the previous update's
+// x += alpha p_(k-1); the SpMV (mode PQ) then gathers p_k alone.  Batches of
+// kUI * kBS positions per workgroup.
+template <typename XT>
+__global__ __launch_bounds__(kBS) void k_pstep(int32_t n, const XT *__restrict__ r, const XT *__restrict__ pin,
+                                               XT *__restrict__ pout, XT *__restrict__ x,
+                                               const double *__restrict__ part_b,
+                                               const double *__restrict__ part_b2, int32_t nb, int32_t slot,
+                                               DevState *__restrict__ st)
+{
+    constexpr int B = kUI * kBS;
+    __shared__ double ws[2 * (kBS / 64) + 2];
+    __shared__ int s_flag;
+    if (threadIdx.x == 0) s_flag = load_status(st);
+    const int b0 = (int)blockIdx.x * B;
+    // operands loaded before beta is known
+    XT rv[kUI], pv[kUI], xv[kUI];
+#pragma unroll
+    for (int i = 0; i < kUI; ++i) {
+        const int c = min(b0 + (int)threadIdx.x + i * kBS, n - 1);
+        rv[i] = r[c];
+        pv[i] = pin[c];
+        xv[i] = x[c];
+    }
+    // the x update is owed whenever this slot's update ran (see k_spmv_sell)
+    const double alpha = st->alpha[slot];
+    __syncthreads();
+    bool stop = s_flag != ST_RUNNING;
+    double beta = 0.0;
+    if (!stop) beta = finish_rr(part_b, part_b2, nb, slot, st, ws, &stop);
+#pragma unroll
+    for (int i = 0; i < kUI; ++i) {
+        const int c = b0 + (int)threadIdx.x + i * kBS;
+        if (c < n) {
+            if (!stop) pout[c] = pupd(rv[i], pv[i], beta);
+            if (alpha != 0.0) x[c] = (XT)((double)xv[i] + alpha * (double)pv[i]);
+        }
     }
 }
 
@@ -1072,6 +1121,7 @@ __global__ __launch_bounds__(kBS) void k_set_values(int64_t len, const int32_t *
 }
 
 inline int nblocks(int64_t n) { return (int)((n + kBS - 1) / kBS); }
+inline int nblocks(int64_t n, int per) { return (int)((n + per - 1) / per); }
 
 template <typename VT, typename XT, int MODE>
 void spmv_dispatch(hipStream_t s, const Mat &A, const XT *pin, const XT *r, XT *pout, XT *q, XT *x, Partials P,
@@ -1123,6 +1173,34 @@ void spmv_dispatch(hipStream_t s, const Mat &A, const XT *pin, const XT *r, XT *
 #undef SS_SPMV
 }
 
+// q = A p and the (p, A p) partials for a p already formed (split step).
+template <typename VT, typename XT>
+void spmv_pq_dispatch(hipStream_t s, const Mat &A, const XT *p, XT *q, Partials P, DevState *st)
+{
+    const dim3 grid(A.grid), block(kBS);
+#define SS_PQ(U, BAND)                                                                                              \
+    hipLaunchKernelGGL((k_spmv_sell<VT, XT, SPMV_PQ, U, false, BAND>), grid, block, 0, s, A.nrows, A.nchunks,      \
+                       A.cptr, A.cpos, A.clen, A.rlen, A.ccol, A.col, A.col16, A.cbase, (const VT *)A.val, p,       \
+                       (const XT *)nullptr, (XT *)nullptr, q, (XT *)nullptr, P.a, (const double *)nullptr,          \
+                       (const double *)nullptr, 0, 0, st, (const int32_t *)nullptr, A.band_m, A.nbands)
+#define SS_PQ_U(BAND)                      \
+    switch (A.unroll) {                    \
+    case 5: SS_PQ(5, BAND); break;         \
+    case 7: SS_PQ(7, BAND); break;         \
+    case 9: SS_PQ(9, BAND); break;         \
+    default: SS_PQ(8, BAND); break;        \
+    }
+    if constexpr (std::is_same<VT, double>::value && std::is_same<XT, double>::value) {
+        if (A.nbands > 1) {
+            SS_PQ_U(true)
+            return;
+        }
+    }
+    SS_PQ_U(false)
+#undef SS_PQ_U
+#undef SS_PQ
+}
+
 }  // namespace
 
 // ---- launchers -----------------------------------------------------------------
@@ -1157,7 +1235,15 @@ template <typename VT, typename XT>
 void launch_spmv_step(hipStream_t s, const Mat &A, const XT *pin, const XT *r, XT *pout, XT *q, XT *x, Partials P,
                       DevState *st, int slot)
 {
-    spmv_dispatch<VT, XT, SPMV_STEP>(s, A, pin, r, pout, q, x, P, st, slot);
+    if (A.nrows == 0) return;
+    if (!split_step(A)) {
+        spmv_dispatch<VT, XT, SPMV_STEP>(s, A, pin, r, pout, q, x, P, st, slot);
+        return;
+    }
+    // rows of several batches: p formed once per position, then the SpMV on it
+    hipLaunchKernelGGL(k_pstep<XT>, dim3(nblocks(A.nrows, kUI * kBS)), dim3(kBS), 0, s, A.nrows, r, pin, pout, x,
+                       (const double *)P.b, (const double *)P.b2, P.nb, slot, st);
+    spmv_pq_dispatch<VT, XT>(s, A, pout, q, P, st);
 }
 
 template <typename XT>

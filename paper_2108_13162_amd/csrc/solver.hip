@@ -954,11 +954,12 @@ int ss_cg_time_spmv(ss_solver *s, int32_t reps, double *ms_per_launch, double *b
     if (err != hipSuccess) return fail(SS_EDEVICE, std::string("SpMV timing: ") + hipGetErrorString(err));
     *ms_per_launch = total / reps;
     // values and column data of the stored entries, row structure (4 B per
-    // row), one read of r, p_(k-1) and x, writes of p_k, q and x
+    // row), one read of r, p_(k-1) and x, writes of p_k, q and x (the split
+    // step also reads p_k back for the SpMV)
     const double sv = f32 ? 4.0 : 8.0;
     if (bytes_per_launch)
         *bytes_per_launch = sv * (double)s->nnz + (double)s->col_bytes + 4.0 * (double)(s->n_loc + 1) +
-                            6.0 * sv * (double)s->n_loc;
+                            (split_step(f32 ? s->mat32 : s->mat) ? 7.0 : 6.0) * sv * (double)s->n_loc;
     std::memcpy(s->st_pinned, &saved, sizeof(DevState));
     SS_HIP(hipMemcpyAsync(st, s->st_pinned, sizeof(DevState), hipMemcpyHostToDevice, s->stream));
     SS_HIP(hipStreamSynchronize(s->stream));
