@@ -324,6 +324,9 @@ std::vector<uint8_t> bisect(const Graph &G0, double f0, Rng &rng)
         for (int64_t v : G.vw) vmax = std::max(vmax, v);
         maxw[0] = std::max<int64_t>((int64_t)(kImbalance * (double)t0), t0 + vmax);
         maxw[1] = std::max<int64_t>((int64_t)(kImbalance * (double)t1), t1 + vmax);
+        // a side with a positive target keeps some weight (vertex weights >= 1)
+        if (t1 > 0) maxw[0] = std::min<int64_t>(maxw[0], G.total - 1);
+        if (t0 > 0) maxw[1] = std::min<int64_t>(maxw[1], G.total - 1);
     };
     // initial bisection of the coarsest graph: several seeds, the best kept
     const Graph &Cg = levels.back();

@@ -128,3 +128,12 @@ def test_split_of_graph_partition_matches_oracle(k):
     sd = O.split(A.rowptr, A.colidx, part, k)
     for key in ("sub_off", "n_int", "n_own", "l2g", "gamma", "copy_ptr", "copy_pos"):
         assert np.array_equal(e[key], getattr(sd, key)), key
+
+
+def test_one_node_per_part_and_single_node():
+    A = poisson2d(4)
+    _, part = _graph_part(A, A.n)
+    assert sorted(part.tolist()) == list(range(A.n))
+    one = CSR(1, np.array([0, 1], dtype=np.int32), np.array([0], dtype=np.int32), np.array([2.0]))
+    p, part = _graph_part(one, 1)
+    assert part.tolist() == [0] and ss.ss_part_sizes(p)["n_gamma"] == 0
