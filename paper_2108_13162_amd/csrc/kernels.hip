@@ -216,24 +216,24 @@ __device__ __forceinline__ int chunk_len(const uint8_t *__restrict__ clen, int c
     return (int)((wd >> (8 * (c & 3))) & 0xffu);
 }
 
-// The raw column words and the values of entries j0 .. j0+U-1 of a chunk,
-// the last entry repeated past L; decoded at use (decode_cols), so that the
-// loads can stay in flight across other work.  Both column arrays are read
-// for every batch -- the one the chunk does not use at its first 64 (always
-// valid) entries -- so that the loads do not depend on the chunk's kind.
+// The column words and the values of entries j0 .. j0+U-1 of a chunk, the
+// last entry repeated past L; decoded at use (decode_cols), so that the loads
+// can stay in flight across other work.  One 32-bit load per entry for either
+// kind of chunk: a wide chunk's int32 position, or the aligned word holding
+// the 16-bit offsets of lanes 2l and 2l+1 of a narrow chunk (every chunk's
+// offsets start at an even index, chunks being 64 entries a slot).
 template <typename VT, int U>
-__device__ __forceinline__ void load_batch(uint32_t (&c16)[U], uint32_t (&c32)[U], VT (&vv)[U], int cb, int base,
-                                           int j0, int L, int lane, const int32_t *__restrict__ col,
-                                           const uint16_t *__restrict__ col16, const VT *__restrict__ val)
+__device__ __forceinline__ void load_batch(uint32_t (&cw)[U], VT (&vv)[U], int cb, int base, int j0, int L, int lane,
+                                           const int32_t *__restrict__ col, const uint16_t *__restrict__ col16,
+                                           const VT *__restrict__ val)
 {
     const bool narrow = cb >= 0;
-    const uint16_t *p16 = col16 + (narrow ? cb : 0);
-    const int32_t *p32 = col + (narrow ? 0 : ~cb);
+    const uint32_t *w32 = narrow ? reinterpret_cast<const uint32_t *>(col16 + cb)
+                                 : reinterpret_cast<const uint32_t *>(col + ~cb);
 #pragma unroll
     for (int u = 0; u < U; ++u) {
         const int off = max(min(j0 + u, L - 1), 0) * 64 + lane;
-        c16[u] = p16[narrow ? off : lane];
-        c32[u] = (uint32_t)p32[narrow ? lane : off];
+        cw[u] = w32[narrow ? off >> 1 : off];
         vv[u] = val[base + off];
     }
 }
@@ -255,15 +255,14 @@ __device__ __forceinline__ void load_row(int &len, XT &rv, XT &pv, XT &xv, int r
 }
 
 template <int U>
-__device__ __forceinline__ void decode_cols(int (&cc)[U], const uint32_t (&c16)[U], const uint32_t (&c32)[U], int cb,
-                                            int2 base)
+__device__ __forceinline__ void decode_cols(int (&cc)[U], const uint32_t (&cw)[U], int cb, int2 base, int lane)
 {
+    // select by mask rather than by a branch of the wave
+    const uint32_t m = cb >= 0 ? 0xffffffffu : 0u;
+    const int sh = (lane & 1) * 16;
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-        // select by mask rather than by a branch of the wave
-        const uint32_t m = cb >= 0 ? 0xffffffffu : 0u;
-        cc[u] = (int)(((uint32_t)narrow_col(c16[u], base) & m) | (c32[u] & ~m));
-    }
+    for (int u = 0; u < U; ++u)
+        cc[u] = (int)(((uint32_t)narrow_col((cw[u] >> sh) & 0xffffu, base) & m) | (cw[u] & ~m));
 }
 
 // Band-column product (one device): the row sum is split where the column
@@ -313,7 +312,7 @@ __global__ __launch_bounds__(kBS) __attribute__((amdgpu_waves_per_eu(1, 4))) voi
     // first batch of the first chunk (and, for ONE, the row's own operands),
     // loaded before beta is known
     int cc[U];
-    uint32_t c16[U], c32[U];
+    uint32_t cw[U];  // ONE: column words of chunk c, decoded at use
     VT vv[U];
     int base = 0, L = 0, cb = 0, row = 0, len = 0;
     int2 wb = make_int2(0, 0);
@@ -325,7 +324,7 @@ __global__ __launch_bounds__(kBS) __attribute__((amdgpu_waves_per_eu(1, 4))) voi
         if (cb >= 0) wb = cbase[c];
         row = cpos[c] + lane;
         if constexpr (ONE) {
-            load_batch<VT, U>(c16, c32, vv, cb, base, 0, L, lane, col, col16, val);
+            load_batch<VT, U>(cw, vv, cb, base, 0, L, lane, col, col16, val);
             load_row<XT, MODE>(len, rrow, prow, xrow, row, nrows, rlen, r, pin, x);
         } else {
             load_cols<U>(cc, cb, wb, 0, L, lane, col, col16);
@@ -361,7 +360,7 @@ __global__ __launch_bounds__(kBS) __attribute__((amdgpu_waves_per_eu(1, 4))) voi
             // gathers below by draining everything
             __builtin_amdgcn_s_waitcnt(0x0f70);
             XT rx[U], px[U];
-            decode_cols<U>(cc, c16, c32, cb, wb);
+            decode_cols<U>(cc, cw, cb, wb, lane);
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 if (PUPD) rx[u] = r[cc[u]];
@@ -375,9 +374,9 @@ __global__ __launch_bounds__(kBS) __attribute__((amdgpu_waves_per_eu(1, 4))) voi
             const int nbase = cptr[lc], nL = chunk_len(clen, lc), ncb = ccol[lc];
             const int2 nwb = cbase[lc];
             const int nrow = cpos[lc] + lane;
-            uint32_t n16[U], n32[U];
+            uint32_t ncw[U];
             VT nvv[U];
-            load_batch<VT, U>(n16, n32, nvv, ncb, nbase, 0, nL, lane, col, col16, val);
+            load_batch<VT, U>(ncw, nvv, ncb, nbase, 0, nL, lane, col, col16, val);
             int nlen;
             XT nr, np, nx;
             load_row<XT, MODE>(nlen, nr, np, nx, nrow, nrows, rlen, r, pin, x);
@@ -430,8 +429,7 @@ __global__ __launch_bounds__(kBS) __attribute__((amdgpu_waves_per_eu(1, 4))) voi
             xrow = nx;
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                c16[u] = n16[u];
-                c32[u] = n32[u];
+                cw[u] = ncw[u];
                 vv[u] = nvv[u];
             }
         }

@@ -205,7 +205,10 @@ void build_matrix(const ss_part *p, Layout &L, int32_t tile_nnz, int32_t force)
                 if (L.cpos[i] + lane < nl) real += L.rlen[L.cpos[i] + lane];
             L.col_bytes += real * (narrow ? 2 : 4);
             if (narrow) {
+                // the SpMV reads 16-bit offsets in aligned pairs: each chunk's
+                // start is even (64 entries per slot)
                 L.ccol[i] = (int32_t)L.col16.size();
+                if (L.ccol[i] & 1) L.encode_ok = false;
                 L.cbase[2 * (size_t)i] = b1;
                 L.cbase[2 * (size_t)i + 1] = b2;
                 for (int64_t k = k0; k < k1; ++k) {
