@@ -13,6 +13,7 @@ from .generators import (  # noqa: F401
     CSR,
     Workload,
     poisson2d,
+    poisson3d,
     diffusion2d_lognormal,
     diffusion3d_lognormal,
     diffusion3d_grf,

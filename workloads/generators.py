@@ -150,6 +150,29 @@ def poisson2d(m: int, my: Optional[int] = None) -> CSR:
     return _faces_to_csr2d(cx, cy)
 
 
+def poisson3d(m: int) -> CSR:
+    """7-point Laplacian on an m^3 interior grid: a_ii = 6, a_ij = -1 (integer
+    valued, x fastest), assembled directly for large grids."""
+    N = m * m * m
+    ids = np.arange(N, dtype=np.int64)
+    x, y, z = ids % m, (ids // m) % m, ids // (m * m)
+    # the seven offsets in ascending column order
+    offs = [(-m * m, z > 0), (-m, y > 0), (-1, x > 0), (0, None), (1, x < m - 1), (m, y < m - 1),
+            (m * m, z < m - 1)]
+    mask = np.ones((N, 7), dtype=bool)
+    cols = np.empty((N, 7), dtype=np.int32)
+    for k, (d, ok) in enumerate(offs):
+        if ok is not None:
+            mask[:, k] = ok
+        cols[:, k] = ids + d
+    vals = np.broadcast_to(np.array([-1.0, -1.0, -1.0, 6.0, -1.0, -1.0, -1.0]), (N, 7))
+    rowptr = np.zeros(N + 1, dtype=np.int64)
+    np.cumsum(mask.sum(axis=1), out=rowptr[1:])
+    if rowptr[-1] >= 2**31:
+        raise ValueError("nnz does not fit int32")
+    return CSR(N, rowptr.astype(np.int32), cols[mask], vals[mask])
+
+
 def diffusion2d_lognormal(m: int, rng: np.random.Generator, my: Optional[int] = None) -> CSR:
     """5-point variable-coefficient diffusion; faces exp(N(0,1)) drawn x-faces first."""
     my = m if my is None else my
