@@ -252,3 +252,28 @@ def test_wide_systems_take_the_direct_gather_path(nrhs):
     X2, res2, _ = _solve(bt, B)
     assert all(np.array_equal(a, c) for a, c in zip(X, X2))
     assert [r.iterations for r in res] == [r.iterations for r in res2]
+
+
+def test_many_small_systems():
+    # 6000 systems of 1x1 .. 12x12 grids, 2 right-hand sides: 12,000 pairs, far
+    # more tiles than workgroups, and systems leaving the running list at
+    # every polled chunk
+    S = batch2d_lognormal(6000, 1, 12, seed=41)
+    bt = ss.ss_batch_setup(S, nrhs=2)
+    B = _rhs(S, 2, 42)
+    X, res, summ = _solve(bt, B, maxit=2000)
+    assert summ.status == ss.SS_OK
+    for s, A in enumerate(S):
+        for j in range(2):
+            r = res[s * 2 + j]
+            b = B[s][:, j]
+            xo, ro = O.cg(A, b, tol=1e-10, maxit=2000, hist=False)
+            assert r.status == ss.SS_OK
+            assert abs(r.iterations - ro.iterations) <= max(2, 0.05 * ro.iterations), (s, j, r, ro)
+            x = X[s][:, j]
+            true = np.linalg.norm(b - O.csr_matvec(A, x)) / np.linalg.norm(b)
+            assert true <= 1e-10, (s, j, true)
+            xr = O.solve_reference(A, b)
+            err = np.linalg.norm(x - xr) / np.linalg.norm(xr)
+            err_o = np.linalg.norm(xo - xr) / np.linalg.norm(xr)
+            assert err <= max(1e-9, 10 * err_o), (s, j, err, err_o)
