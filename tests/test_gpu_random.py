@@ -43,3 +43,27 @@ def test_random_apply_bitwise(seed):
         y = ss.ss_cg_apply(s, torch.tensor(x, device=DEV)).cpu().numpy()
         want = O.ss_spmv(A, sd, x)
         assert np.array_equal(y, want), (seed, A.n, P, fmt, float(np.max(np.abs(y - want))))
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_random_solve(seed):
+    # CG to 1e-10 on the same random systems and partitions: the oracle's
+    # sub-structured CG on the same partition sets the iteration count (the
+    # two differ only in dot-product summation order) and the error floor
+    A, P, part, fmt = _case(seed)
+    p = ss.ss_partition(A, ss.SS_PART_USER, P, user_part=part)
+    s = ss.ss_cg_setup(A, p, ss.default_opts(matrix_format=fmt))
+    sd = O.split(A.rowptr, A.colidx, part, P)
+    b = np.random.default_rng(100 + seed).uniform(-1.0, 1.0, A.n)
+    x = torch.zeros(A.n, dtype=torch.float64, device=DEV)
+    r = ss.ss_cg_solve(s, torch.tensor(b, device=DEV), x, tol=1e-10, maxit=5000)
+    xo, ro = O.ss_cg(A, sd, b, tol=1e-10, maxit=5000, hist=False)
+    assert r.status == ss.SS_OK and ro.status == O.OK
+    assert abs(r.iterations - ro.iterations) <= 2, (r.iterations, ro.iterations)
+    xg = x.cpu().numpy()
+    true = np.linalg.norm(b - O.csr_matvec(A, xg)) / np.linalg.norm(b)
+    assert true <= 1e-10, true
+    xr = O.solve_reference(A, b)
+    err = np.linalg.norm(xg - xr) / np.linalg.norm(xr)
+    err_o = np.linalg.norm(xo - xr) / np.linalg.norm(xr)
+    assert err <= max(1e-9, 10 * err_o), (err, err_o)
