@@ -100,6 +100,24 @@ def stream_copy_gbps(torch, nbytes: int = 1 << 30, reps: int = 10) -> float:
     return 2.0 * nbytes / (ms * 1e-3) / 1e9
 
 
+def host_cpu() -> dict:
+    """The host the CPU baseline ran on: CPU model and the cores this process may use."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        avail = os.cpu_count()
+    return {"model": model, "cores_available": avail}
+
+
 def cpu_baseline(w, iters_gpu: int, sample_iters: int) -> dict:
     import numpy as np
 
@@ -115,6 +133,7 @@ def cpu_baseline(w, iters_gpu: int, sample_iters: int) -> dict:
         "value": round(per_iter * iters_gpu * 1e3, 3),
         "unit": "ms",
         "cores": 1,
+        "host": host_cpu(),
         "kind": "oracle",
         "sample": (f"sequential FP64 oracle, sub-structured CG on the same system: first {res.iterations} iterations "
                    f"timed ({dt:.2f} s, {per_iter * 1e3:.2f} ms/iteration), scaled to the GPU's {iters_gpu} iterations"),
