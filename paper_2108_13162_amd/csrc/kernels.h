@@ -83,6 +83,14 @@ struct Mat {
     const int32_t *cpos;          // [nchunks] first row position of each chunk
     const uint8_t *clen;          // [nchunks] entries per row slot of the chunk
     const uint8_t *rlen;          // [nrows] entries of each row (by position)
+    // offset dictionaries (one-batch matrices of at most 8 entries a row):
+    // cdict[c] >= 0 names chunk c's block b, whose 16 column - row offsets are
+    // dtab[16 b ..] and whose lane l holds the 4-bit offset indices of slots
+    // 0..7 in dword[64 b + l]; inside each SpMV workgroup's range these chunks
+    // come first.  nullptr: none.
+    const int32_t *cdict;
+    const int32_t *dtab;
+    const uint32_t *dword;
     // CSR tiles
     const int32_t *rowptr;        // [nrows+1]
     const int32_t *tile_row;      // [ntiles+1]

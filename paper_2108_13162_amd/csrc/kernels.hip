@@ -265,6 +265,24 @@ __device__ __forceinline__ void decode_cols(int (&cc)[U], const uint32_t (&cw)[U
         cc[u] = (int)(((uint32_t)narrow_col((cw[u] >> sh) & 0xffffu, base) & m) | (cw[u] & ~m));
 }
 
+// A dictionary chunk's lane word of offset indices and the lane's entry
+// (lane & 15) of the chunk's 16 offsets.
+__device__ __forceinline__ void load_dict(uint32_t &dw, int &tab, int blk, int lane,
+                                          const int32_t *__restrict__ dtab, const uint32_t *__restrict__ dword)
+{
+    dw = dword ? dword[blk * 64 + lane] : 0u;
+    tab = dtab ? dtab[blk * 16 + (lane & 15)] : 0;
+}
+
+// Columns of a dictionary chunk's slots 0..U-1: the row plus the offset its
+// 4-bit index names, fetched from the lane holding it.
+template <int U>
+__device__ __forceinline__ void decode_dict(int (&cc)[U], uint32_t dw, int tab, int row)
+{
+#pragma unroll
+    for (int u = 0; u < U; ++u) cc[u] = row + __shfl(tab, (int)((dw >> (4 * u)) & 15u), 64);
+}
+
 // Band-column product (one device): the row sum is split where the column
 // crosses into the next band of bm columns (the last band takes the rest);
 // the band partial sums are added in band order.  First column of the band
@@ -284,7 +302,7 @@ __device__ __forceinline__ int band_next(int col, int bm, int nbands)
 // flight.  Otherwise (rows longer than U) the batches of each chunk are
 // walked in turn, each batch's gathers waiting for its own loads.
 // BAND: the band-column product (positions are global ids, bands of bm).
-template <typename VT, typename XT, int MODE, int U, bool ONE, bool BAND>
+template <typename VT, typename XT, int MODE, int U, bool ONE, bool BAND, bool DICT_ON>
 __global__ __launch_bounds__(kBS) __attribute__((amdgpu_waves_per_eu(1, 4))) void k_spmv_sell(
     int32_t nrows, int32_t nchunks, const int32_t *__restrict__ cptr, const int32_t *__restrict__ cpos,
     const uint8_t *__restrict__ clen, const uint8_t *__restrict__ rlen, const int32_t *__restrict__ ccol,
@@ -292,7 +310,8 @@ __global__ __launch_bounds__(kBS) __attribute__((amdgpu_waves_per_eu(1, 4))) voi
     const VT *__restrict__ val, const XT *__restrict__ pin, const XT *__restrict__ r, XT *__restrict__ pout,
     XT *__restrict__ q, XT *__restrict__ x, double *__restrict__ part_a, const double *__restrict__ part_b,
     const double *__restrict__ part_b2, int32_t nb, int32_t slot, DevState *__restrict__ st,
-    const int32_t *__restrict__ gate, int32_t bm, int32_t nbands)
+    const int32_t *__restrict__ gate, int32_t bm, int32_t nbands, const int32_t *__restrict__ cdict,
+    const int32_t *__restrict__ dtab, const uint32_t *__restrict__ dword)
 {
     constexpr bool CG = MODE != SPMV_PLAIN;                        // status, (p, A p)
     constexpr bool PUPD = MODE == SPMV_FIRST || MODE == SPMV_STEP;  // p formed here
@@ -314,9 +333,11 @@ __global__ __launch_bounds__(kBS) __attribute__((amdgpu_waves_per_eu(1, 4))) voi
     int cc[U];
     uint32_t cw[U];  // ONE: column words of chunk c, decoded at use
     VT vv[U];
-    int base = 0, L = 0, cb = 0, row = 0, len = 0;
+    int base = 0, L = 0, cb = 0, row = 0, len = 0, blk = -1;
     int2 wb = make_int2(0, 0);
     XT rrow = XT(0), prow = XT(0), xrow = XT(0);
+    uint32_t dw = 0;  // ONE, dictionary chunk: the lane's 4-bit offset indices
+    int tab = 0;      // and offset (lane & 15) of the chunk's table
     if (c < cend) {
         base = cptr[c];
         L = chunk_len(clen, c);
@@ -324,6 +345,11 @@ __global__ __launch_bounds__(kBS) __attribute__((amdgpu_waves_per_eu(1, 4))) voi
         if (cb >= 0) wb = cbase[c];
         row = cpos[c] + lane;
         if constexpr (ONE) {
+            // both encodings (block 0 stands in when the chunk has none)
+            if (DICT_ON && U <= 8 && !BAND && cdict) {
+                blk = cdict[c];
+                load_dict(dw, tab, max(blk, 0), lane, dtab, dword);
+            }
             load_batch<VT, U>(cw, vv, cb, base, 0, L, lane, col, col16, val);
             load_row<XT, MODE>(len, rrow, prow, xrow, row, nrows, rlen, r, pin, x);
         } else {
@@ -354,13 +380,25 @@ __global__ __launch_bounds__(kBS) __attribute__((amdgpu_waves_per_eu(1, 4))) voi
 
     double acc = 0.0;
     if constexpr (ONE) {
-        while (c < cend) {
+        // Inside the workgroup's range the dictionary chunks come first: the
+        // wave runs them in a loop that reads one word of offset indices per
+        // lane and the chunk's offsets, then the others in the loop that reads
+        // one column word per entry.  The registers hold chunk c (`have`).
+        // (rows of at most 8 entries, not the band-column product; the other
+        // instantiations ignore the dictionaries)
+        constexpr bool USE_DICT = DICT_ON && U <= 8 && !BAND;
+        bool have = true;
+        auto run_chunk = [&](auto kind) {
+            constexpr bool DICT = decltype(kind)::value && USE_DICT;
             // drain the previous chunk's stores (and this chunk's loads, needed
             // now): with stores outstanding the compiler can only wait for the
             // gathers below by draining everything
             __builtin_amdgcn_s_waitcnt(0x0f70);
             XT rx[U], px[U];
-            decode_cols<U>(cc, cw, cb, wb, lane);
+            if constexpr (DICT)
+                decode_dict<U>(cc, dw, tab, row);
+            else
+                decode_cols<U>(cc, cw, cb, wb, lane);
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 if (PUPD) rx[u] = r[cc[u]];
@@ -369,14 +407,25 @@ __global__ __launch_bounds__(kBS) __attribute__((amdgpu_waves_per_eu(1, 4))) voi
             // keep the issue order: the scheduler would otherwise interleave
             // the two groups of loads, and the products would wait for both
             __builtin_amdgcn_sched_barrier(0);
-            // chunk c + W, or chunk c again past the wave's last one (unused)
-            const int lc = c + W < cend ? c + W : c;
+            // the wave's next chunk when it is of this kind, else chunk c again
+            // (unused)
+            const int nc = c + W;
+            const bool nxt = nc < cend && (!USE_DICT || ((cdict ? cdict[nc] : -1) >= 0) == DICT);
+            const int lc = nxt ? nc : c;
             const int nbase = cptr[lc], nL = chunk_len(clen, lc), ncb = ccol[lc];
             const int2 nwb = cbase[lc];
             const int nrow = cpos[lc] + lane;
-            uint32_t ncw[U];
+            const int nblk = USE_DICT && cdict ? cdict[lc] : -1;
+            uint32_t ncw[U], ndw = 0;
+            int ntab = 0;
             VT nvv[U];
-            load_batch<VT, U>(ncw, nvv, ncb, nbase, 0, nL, lane, col, col16, val);
+            if constexpr (DICT) {
+                load_dict(ndw, ntab, nblk, lane, dtab, dword);
+#pragma unroll
+                for (int u = 0; u < U; ++u) nvv[u] = val[nbase + min(u, nL - 1) * 64 + lane];
+            } else {
+                load_batch<VT, U>(ncw, nvv, ncb, nbase, 0, nL, lane, col, col16, val);
+            }
             int nlen;
             XT nr, np, nx;
             load_row<XT, MODE>(nlen, nr, np, nx, nrow, nrows, rlen, r, pin, x);
@@ -419,19 +468,49 @@ __global__ __launch_bounds__(kBS) __attribute__((amdgpu_waves_per_eu(1, 4))) voi
                     acc = acc + (double)pr * (double)sacc;
                 }
             }
-            c += W;
+            c = nc;
+            have = nxt;
             cb = ncb;
             wb = nwb;
             row = nrow;
             len = nlen;
+            blk = nblk;
             rrow = nr;
             prow = np;
             xrow = nx;
+            if constexpr (DICT) {
+                dw = ndw;
+                tab = ntab;
+            }
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                cw[u] = ncw[u];
+                if constexpr (!DICT) cw[u] = ncw[u];
                 vv[u] = nvv[u];
             }
+        };
+        if constexpr (!USE_DICT) {
+            while (c < cend) run_chunk(std::false_type{});
+        } else {
+        while (c < cend) {
+            if (!have) {
+                // a chunk of the other kind (once per wave with the host's order)
+                base = cptr[c];
+                L = chunk_len(clen, c);
+                cb = ccol[c];
+                if (cb >= 0) wb = cbase[c];
+                row = cpos[c] + lane;
+                blk = cdict ? cdict[c] : -1;
+                load_dict(dw, tab, max(blk, 0), lane, dtab, dword);
+                load_batch<VT, U>(cw, vv, cb, base, 0, L, lane, col, col16, val);
+                load_row<XT, MODE>(len, rrow, prow, xrow, row, nrows, rlen, r, pin, x);
+                have = true;
+            }
+            if (blk >= 0) {
+                while (have && c < cend) run_chunk(std::true_type{});
+            } else {
+                while (have && c < cend) run_chunk(std::false_type{});
+            }
+        }
         }
     } else {
         bool have = true;  // cc / vv hold batch 0 of chunk c
@@ -1129,9 +1208,15 @@ void spmv_dispatch(hipStream_t s, const Mat &A, const XT *pin, const XT *r, XT *
     const dim3 grid(A.grid), block(kBS);
     if (A.fmt == FMT_SELL) {
 #define SS_SELL(U, ONE, BAND)                                                                                    \
-    hipLaunchKernelGGL((k_spmv_sell<VT, XT, MODE, U, ONE, BAND>), grid, block, 0, s, A.nrows, A.nchunks, A.cptr,  \
+    hipLaunchKernelGGL((k_spmv_sell<VT, XT, MODE, U, ONE, BAND, false>), grid, block, 0, s, A.nrows, A.nchunks,   \
+                       A.cptr, A.cpos, A.clen, A.rlen, A.ccol, A.col, A.col16, A.cbase, (const VT *)A.val, pin, r,  \
+                       pout, q, x, P.a, (const double *)P.b, (const double *)P.b2, P.nb, slot, st, gate, A.band_m,  \
+                       A.nbands, nullptr, nullptr, nullptr)
+#define SS_SELL_D(U)                                                                                             \
+    hipLaunchKernelGGL((k_spmv_sell<VT, XT, MODE, U, true, false, true>), grid, block, 0, s, A.nrows, A.nchunks, A.cptr,  \
                        A.cpos, A.clen, A.rlen, A.ccol, A.col, A.col16, A.cbase, (const VT *)A.val, pin, r, pout, q, x, \
-                       P.a, (const double *)P.b, (const double *)P.b2, P.nb, slot, st, gate, A.band_m, A.nbands)
+                       P.a, (const double *)P.b, (const double *)P.b2, P.nb, slot, st, gate, A.band_m, A.nbands, A.cdict,  \
+                       A.dtab, A.dword)
 #define SS_SELL_U(ONE, BAND)                    \
     switch (A.unroll) {                         \
     case 5: SS_SELL(5, ONE, BAND); break;       \
@@ -1150,12 +1235,20 @@ void spmv_dispatch(hipStream_t s, const Mat &A, const XT *pin, const XT *r, XT *
                 return;
             }
         }
-        if (A.one_batch) {
+        if (A.one_batch && A.cdict && A.unroll <= 8) {
+            // offset dictionaries (rows of at most 8 entries)
+            switch (A.unroll) {
+            case 5: SS_SELL_D(5); break;
+            case 7: SS_SELL_D(7); break;
+            default: SS_SELL_D(8); break;
+            }
+        } else if (A.one_batch) {
             SS_SELL_U(true, false)
         } else {
             SS_SELL_U(false, false)
         }
 #undef SS_SELL_U
+#undef SS_SELL_D
 #undef SS_SELL
         return;
     }
@@ -1177,10 +1270,11 @@ void spmv_pq_dispatch(hipStream_t s, const Mat &A, const XT *p, XT *q, Partials 
 {
     const dim3 grid(A.grid), block(kBS);
 #define SS_PQ(U, BAND)                                                                                              \
-    hipLaunchKernelGGL((k_spmv_sell<VT, XT, SPMV_PQ, U, false, BAND>), grid, block, 0, s, A.nrows, A.nchunks,      \
+    hipLaunchKernelGGL((k_spmv_sell<VT, XT, SPMV_PQ, U, false, BAND, false>), grid, block, 0, s, A.nrows, A.nchunks, \
                        A.cptr, A.cpos, A.clen, A.rlen, A.ccol, A.col, A.col16, A.cbase, (const VT *)A.val, p,       \
                        (const XT *)nullptr, (XT *)nullptr, q, (XT *)nullptr, P.a, (const double *)nullptr,          \
-                       (const double *)nullptr, 0, 0, st, (const int32_t *)nullptr, A.band_m, A.nbands)
+                       (const double *)nullptr, 0, 0, st, (const int32_t *)nullptr, A.band_m, A.nbands,             \
+                       (const int32_t *)nullptr, (const int32_t *)nullptr, (const uint32_t *)nullptr)
 #define SS_PQ_U(BAND)                      \
     switch (A.unroll) {                    \
     case 5: SS_PQ(5, BAND); break;         \

@@ -28,6 +28,20 @@ constexpr int kSpmvGridSmall = 768;
 constexpr int kSmallChunks = 16384;
 constexpr int kGridLimit = 65536;       // upper bound accepted for a requested grid
 
+// Persistent SpMV grid: one workgroup per 4 chunks (or per CSR tile) at most.
+int32_t spmv_grid(bool sell, int32_t units, int32_t opt)
+{
+    const int32_t work = sell ? (units + kBS / 64 - 1) / (kBS / 64) : units;
+    const int32_t dflt = sell && units <= kSmallChunks ? kSpmvGridSmall : kSpmvGridMax;
+    return xcd_grid(std::max(1, std::min(work, opt ? opt : dflt)));
+}
+
+// Offset dictionary of a chunk: at most kDictOffsets distinct column - row
+// offsets, rows of at most kDictSlots entries (4-bit indices, 8 to a word).
+constexpr int kDictOffsets = 16;
+constexpr int kDictSlots = 8;
+constexpr int kDictMinPerWg = 24;  // chunks per SpMV workgroup for the dictionaries to pay
+
 // Host image of the device data of one partition.
 struct Layout {
     // device position of every concatenated local position
@@ -40,10 +54,13 @@ struct Layout {
     std::vector<int32_t> ccol;        // SELL: per chunk, start in col16 (>= 0) or ~start in col
     std::vector<uint16_t> col16;      // SELL: window offsets of the narrow chunks
     std::vector<int32_t> cbase;       // SELL: two window bases per chunk
-    int64_t col_bytes = 0;            // bytes of the column data of the stored (non-padding) entries
+    int64_t col_bytes = 0;            // column data the SpMV reads: 2 or 4 B per stored (non-padding) entry,
+                                      // a dictionary chunk's 4 B per row and 64 B table
     bool encode_ok = true;            // column encoding verified
     std::vector<int32_t> cptr, cpos, rowptr, tile_row;
     std::vector<uint8_t> clen, rlen;
+    std::vector<int32_t> cdict, dtab;  // SELL: dictionary block of each chunk (-1: none); 16 offsets a block
+    std::vector<uint32_t> dword;       // SELL: per block and lane, the 4-bit offset indices of slots 0..7
     int32_t nchunks = 0, ntiles = 0, tile_nnz = 2048;
     int32_t unroll = 8;               // SELL: entries per lane loaded before use
     int32_t one_batch = 0;            // SELL: no chunk longer than unroll
@@ -88,8 +105,9 @@ void build_order(const ss_part *p, Layout &L)
 
 // Matrix storage.  SELL-64 unless a row is longer than 255 entries or the
 // chunk padding would add more than a quarter to the stored entries; then
-// CSR row tiles.  `force` = SS_MAT_* selection from the options.
-void build_matrix(const ss_part *p, Layout &L, int32_t tile_nnz, int32_t force)
+// CSR row tiles.  `force` = SS_MAT_* selection from the options, `grid_opt`
+// the SpMV grid option (the chunk order depends on the grid).
+void build_matrix(const ss_part *p, Layout &L, int32_t tile_nnz, int32_t force, int32_t grid_opt)
 {
     const int32_t nl = p->n_loc();
     // rows in device order
@@ -130,6 +148,55 @@ void build_matrix(const ss_part *p, Layout &L, int32_t tile_nnz, int32_t force)
                 ++placed_if;
             } else {
                 order.push_back(next_in++);
+            }
+        }
+        // Offset dictionaries: with every chunk one batch of at most 8 entries
+        // (the unroll is chosen below from the same lengths), a chunk whose
+        // columns take at most 16 distinct offsets from their rows is stored
+        // once more as 4-bit indices into a table of those offsets; the
+        // pipelined SpMV then reads one word per lane instead of one per
+        // entry.  Inside each SpMV workgroup's range these chunks come first.
+        std::vector<char> dict_ok(nch, 0);
+        {
+            std::vector<int32_t> clen_id(nch, 0);
+            for (int32_t id = 0; id < nch; ++id)
+                for (int32_t t = id * 64; t < std::min(nl, id * 64 + 64); ++t)
+                    clen_id[id] = std::max(clen_id[id], std::max(row_len(t), 1));
+            int64_t best_u = INT64_MAX;
+            int32_t u_sel = 8;
+            for (int32_t u : {9, 8, 7, 5}) {
+                int64_t slots = 0;
+                for (int32_t id = 0; id < nch; ++id) slots += (int64_t)((clen_id[id] + u - 1) / u) * u;
+                if (slots < best_u) {
+                    best_u = slots;
+                    u_sel = u;
+                }
+            }
+            bool one = true;
+            for (int32_t id = 0; id < nch; ++id) one = one && clen_id[id] <= u_sel;
+            // only where a wave gets several chunks: the switch to the other
+            // kind costs a reload outside the pipeline (per iteration: 64^3,
+            // 1.3 chunks a wave, 4.5% slower; 96^3, 4.5 a wave, even; 128^3,
+            // 8 a wave, 2.8% faster; 160^3, 4.3% faster)
+            const int32_t g = spmv_grid(true, nch, grid_opt);
+            if (one && u_sel <= kDictSlots && nch >= kDictMinPerWg * g) {
+                std::vector<int32_t> offs;
+                for (int32_t id = 0; id < nch; ++id) {
+                    const int32_t c0 = id * 64;
+                    if (c0 + 64 > nl) continue;
+                    offs.assign(1, 0);  // padding entries point at the row itself
+                    for (int32_t t = c0; t < c0 + 64; ++t) {
+                        const int32_t u = src_row[t];
+                        for (int32_t e = p->bd_rowptr[u]; e < p->bd_rowptr[u + 1]; ++e)
+                            offs.push_back(L.dev_pos[p->bd_colidx[e]] - t);
+                    }
+                    std::sort(offs.begin(), offs.end());
+                    dict_ok[id] = std::unique(offs.begin(), offs.end()) - offs.begin() <= kDictOffsets;
+                }
+                const int32_t cpb = (nch + g - 1) / g;
+                for (int32_t lo = 0; lo < nch; lo += cpb)
+                    std::stable_partition(order.begin() + lo, order.begin() + std::min(nch, lo + cpb),
+                                          [&](int32_t id) { return dict_ok[id] != 0; });
             }
         }
         L.cptr.assign(nch + 1, 0);
@@ -234,6 +301,44 @@ void build_matrix(const ss_part *p, Layout &L, int32_t tile_nnz, int32_t force)
                 }
                 if (v != L.col[k] || v < 0 || v >= std::max(nl, 1)) L.encode_ok = false;
             }
+        // the offset dictionaries (processing order), checked entry by entry
+        L.cdict.assign(nch, -1);
+        for (int32_t i = 0; i < nch; ++i) {
+            if (!dict_ok[L.cpos[i] / 64]) continue;
+            const int32_t blk = (int32_t)(L.dtab.size() / kDictOffsets);
+            std::vector<int32_t> offs(1, 0);
+            for (int64_t k = L.cptr[i]; k < L.cptr[i + 1]; ++k)
+                offs.push_back(L.col[k] - (L.cpos[i] + (int32_t)((k - L.cptr[i]) % 64)));
+            std::sort(offs.begin(), offs.end());
+            offs.erase(std::unique(offs.begin(), offs.end()), offs.end());
+            if ((int)offs.size() > kDictOffsets || L.clen[i] > kDictSlots) {
+                L.encode_ok = false;
+                continue;
+            }
+            L.cdict[i] = blk;
+            // the pipelined SpMV reads a word per row and the table instead
+            int64_t real = 0;
+            for (int32_t lane = 0; lane < 64; ++lane) real += L.rlen[L.cpos[i] + lane];
+            L.col_bytes += 64 * 4 + kDictOffsets * 4 - real * (L.ccol[i] >= 0 ? 2 : 4);
+            for (int32_t q = 0; q < kDictOffsets; ++q) L.dtab.push_back(q < (int32_t)offs.size() ? offs[q] : 0);
+            const int32_t zero = (int32_t)(std::lower_bound(offs.begin(), offs.end(), 0) - offs.begin());
+            for (int32_t lane = 0; lane < 64; ++lane) {
+                const int32_t t = L.cpos[i] + lane;
+                uint32_t wd = 0;
+                for (int32_t j = 0; j < kDictSlots; ++j) {
+                    int32_t q = zero;  // slots past the chunk length decode to the row itself
+                    if (j < L.clen[i]) {
+                        const int32_t d = L.col[L.cptr[i] + (int64_t)j * 64 + lane] - t;
+                        q = (int32_t)(std::lower_bound(offs.begin(), offs.end(), d) - offs.begin());
+                    }
+                    wd |= (uint32_t)q << (4 * j);
+                    const int32_t back = t + L.dtab[(size_t)blk * kDictOffsets + q];
+                    if (j < L.clen[i] ? back != L.col[L.cptr[i] + (int64_t)j * 64 + lane] : back != t)
+                        L.encode_ok = false;
+                }
+                L.dword.push_back(wd);
+            }
+        }
         L.col.swap(wide);
     } else {
         L.fmt = FMT_CSR;
@@ -271,7 +376,7 @@ void build_matrix(const ss_part *p, Layout &L, int32_t tile_nnz, int32_t force)
 
 struct ss_solver {
     int device = 0;
-    int64_t col_bytes = 0;  // column data of the stored entries (2 or 4 B each)
+    int64_t col_bytes = 0;  // column data the SpMV reads (see Layout::col_bytes)
     hipStream_t stream = nullptr;
     hipStream_t cap = nullptr;  // private stream used only to capture graphs
     ss_opts opts{};
@@ -515,7 +620,8 @@ int setup_impl(const ss_csr *A, const ss_part *p, const ss_opts *o, void *hip_st
     Layout L;
     try {
         build_order(p, L);
-        build_matrix(p, L, opts.tile_nnz ? opts.tile_nnz : 2048, band_col ? SS_MAT_SELL : opts.matrix_format);
+        build_matrix(p, L, opts.tile_nnz ? opts.tile_nnz : 2048, band_col ? SS_MAT_SELL : opts.matrix_format,
+                     opts.spmv_grid);
     } catch (const std::bad_alloc &) {
         return fail(SS_ENOMEM, "host allocation failed");
     }
@@ -572,9 +678,7 @@ int setup_impl(const ss_csr *A, const ss_part *p, const ss_opts *o, void *hip_st
     M.nbands = band_col ? nbands : 0;
     M.ntiles = L.ntiles;
     M.tile_nnz = L.tile_nnz;
-    const int work = L.fmt == FMT_SELL ? (L.nchunks + kBS / 64 - 1) / (kBS / 64) : L.ntiles;
-    const int dflt = L.fmt == FMT_SELL && L.nchunks <= kSmallChunks ? kSpmvGridSmall : kSpmvGridMax;
-    M.grid = xcd_grid(std::max(1, std::min(work, opts.spmv_grid ? opts.spmv_grid : dflt)));
+    M.grid = spmv_grid(L.fmt == FMT_SELL, L.fmt == FMT_SELL ? L.nchunks : L.ntiles, opts.spmv_grid);
     Iface &I = s->ifc;
     I.n_loc = s->n_loc;
     I.n_own = L.n_own;
@@ -587,6 +691,8 @@ int setup_impl(const ss_csr *A, const ss_part *p, const ss_opts *o, void *hip_st
     uint16_t *d_col16 = nullptr;
     int32_t *d_cbase = nullptr;
     uint8_t *d_clen = nullptr, *d_rlen = nullptr;
+    int32_t *d_cdict = nullptr, *d_dtab = nullptr;
+    uint32_t *d_dword = nullptr;
     const size_t nl = (size_t)s->n_loc;
     if ((rc = upload(s, &d_col, L.col.data(), L.col.size(), kSellPad)) ||
         (rc = upload(s, &d_col16, L.col16.data(), L.col16.size(), kSellPad)) ||
@@ -598,6 +704,9 @@ int setup_impl(const ss_csr *A, const ss_part *p, const ss_opts *o, void *hip_st
         (rc = upload(s, &d_cpos, L.cpos.data(), L.cpos.size())) ||
         (rc = upload(s, &d_clen, L.clen.data(), L.clen.size(), kSellPad)) ||
         (rc = upload(s, &d_rlen, L.rlen.data(), L.rlen.size())) ||
+        (rc = upload(s, &d_cdict, L.cdict.data(), L.cdict.size())) ||
+        (rc = upload(s, &d_dtab, L.dtab.data(), L.dtab.size(), kSellPad)) ||
+        (rc = upload(s, &d_dword, L.dword.data(), L.dword.size(), kSellPad)) ||
         (rc = upload(s, &d_rowptr, L.rowptr.data(), L.rowptr.size())) ||
         (rc = upload(s, &d_tile, L.tile_row.data(), L.tile_row.size())) ||
         (rc = upload(s, &s->l2g, L.l2g.data(), L.l2g.size())) ||
@@ -635,6 +744,9 @@ int setup_impl(const ss_csr *A, const ss_part *p, const ss_opts *o, void *hip_st
     M.cpos = d_cpos;
     M.clen = d_clen;
     M.rlen = d_rlen;
+    M.cdict = L.dtab.empty() ? nullptr : d_cdict;
+    M.dtab = d_dtab;
+    M.dword = d_dword;
     M.rowptr = d_rowptr;
     M.tile_row = d_tile;
     I.pos_grp = d_pos_grp;
