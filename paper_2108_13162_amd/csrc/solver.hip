@@ -180,18 +180,27 @@ void build_matrix(const ss_part *p, Layout &L, int32_t tile_nnz, int32_t force, 
             // 8 a wave, 2.8% faster; 160^3, 4.3% faster)
             const int32_t g = spmv_grid(true, nch, grid_opt);
             if (one && u_sel <= kDictSlots && nch >= kDictMinPerWg * g) {
-                std::vector<int32_t> offs;
                 for (int32_t id = 0; id < nch; ++id) {
                     const int32_t c0 = id * 64;
                     if (c0 + 64 > nl) continue;
-                    offs.assign(1, 0);  // padding entries point at the row itself
-                    for (int32_t t = c0; t < c0 + 64; ++t) {
+                    int32_t tbl[kDictOffsets] = {0};  // padding entries point at the row itself
+                    int nt = 1;
+                    bool ok = true;
+                    for (int32_t t = c0; t < c0 + 64 && ok; ++t) {
                         const int32_t u = src_row[t];
-                        for (int32_t e = p->bd_rowptr[u]; e < p->bd_rowptr[u + 1]; ++e)
-                            offs.push_back(L.dev_pos[p->bd_colidx[e]] - t);
+                        for (int32_t e = p->bd_rowptr[u]; e < p->bd_rowptr[u + 1] && ok; ++e) {
+                            const int32_t d = L.dev_pos[p->bd_colidx[e]] - t;
+                            int q = 0;
+                            while (q < nt && tbl[q] != d) ++q;
+                            if (q == nt) {
+                                if (nt == kDictOffsets)
+                                    ok = false;
+                                else
+                                    tbl[nt++] = d;
+                            }
+                        }
                     }
-                    std::sort(offs.begin(), offs.end());
-                    dict_ok[id] = std::unique(offs.begin(), offs.end()) - offs.begin() <= kDictOffsets;
+                    dict_ok[id] = ok;
                 }
                 const int32_t cpb = (nch + g - 1) / g;
                 for (int32_t lo = 0; lo < nch; lo += cpb)
@@ -307,10 +316,12 @@ void build_matrix(const ss_part *p, Layout &L, int32_t tile_nnz, int32_t force, 
             if (!dict_ok[L.cpos[i] / 64]) continue;
             const int32_t blk = (int32_t)(L.dtab.size() / kDictOffsets);
             std::vector<int32_t> offs(1, 0);
-            for (int64_t k = L.cptr[i]; k < L.cptr[i + 1]; ++k)
-                offs.push_back(L.col[k] - (L.cpos[i] + (int32_t)((k - L.cptr[i]) % 64)));
+            for (int64_t k = L.cptr[i]; k < L.cptr[i + 1]; ++k) {
+                const int32_t d = L.col[k] - (L.cpos[i] + (int32_t)((k - L.cptr[i]) % 64));
+                if (std::find(offs.begin(), offs.end(), d) == offs.end()) offs.push_back(d);
+                if ((int)offs.size() > kDictOffsets) break;
+            }
             std::sort(offs.begin(), offs.end());
-            offs.erase(std::unique(offs.begin(), offs.end()), offs.end());
             if ((int)offs.size() > kDictOffsets || L.clen[i] > kDictSlots) {
                 L.encode_ok = false;
                 continue;
