@@ -302,6 +302,9 @@ __device__ __forceinline__ int band_next(int col, int bm, int nbands)
 // flight.  Otherwise (rows longer than U) the batches of each chunk are
 // walked in turn, each batch's gathers waiting for its own loads.
 // BAND: the band-column product (positions are global ids, bands of bm).
+// DICT_ON (ONE, U <= 8, no BAND): the chunks with an offset dictionary
+// (cdict, dtab, dword) come first in the workgroup's range and take their
+// columns from it.
 template <typename VT, typename XT, int MODE, int U, bool ONE, bool BAND, bool DICT_ON>
 __global__ __launch_bounds__(kBS) __attribute__((amdgpu_waves_per_eu(1, 4))) void k_spmv_sell(
     int32_t nrows, int32_t nchunks, const int32_t *__restrict__ cptr, const int32_t *__restrict__ cpos,
