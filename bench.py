@@ -455,6 +455,9 @@ def main_measurement(args, ss, torch, config):
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": traffic,
+            # the counter-measured bytes over the same launch time: what the
+            # kernel streams (algorithmic bytes shrink with the column encoding)
+            "traffic_gbps": round(traffic / (spmv_ms * 1e-3) / 1e9, 1) if traffic else None,
             "launch_ms": round(spmv_ms, 5),
             "algorithmic_bytes": int(spmv_bytes),
             "stream_copy_gbps": round(stream_copy_gbps(torch), 1),
