@@ -56,3 +56,19 @@ def test_dictionary_apply_and_solve(which, grid):
     assert abs(r.iterations - ro.iterations) <= max(2, 0.02 * ro.iterations), (r.iterations, ro.iterations)
     true = np.linalg.norm(b - O.csr_matvec(A, x.cpu().numpy())) / np.linalg.norm(b)
     assert true <= 1e-10, true
+
+
+@pytest.mark.parametrize("prec", [ss.SS_FP32_RU, ss.SS_FP32_IR])
+def test_dictionary_fp32_modes(prec):
+    # the FP32 inner CG runs the same dictionary chunks with FP32 values
+    name, A, part, P, g, boxes = _systems()[0]
+    p = ss.ss_partition(A, ss.SS_PART_BOX, P, grid=g, boxes=boxes)
+    s = ss.ss_cg_setup(A, p, ss.default_opts(spmv_grid=16, precision=prec))
+    b = uniform_rhs(A.n, 32)
+    x = torch.zeros(A.n, dtype=torch.float64, device=DEV)
+    r = ss.ss_cg_solve(s, torch.tensor(b, device=DEV), x, tol=1e-10, maxit=20000)
+    assert r.status == ss.SS_OK, r.status
+    true = np.linalg.norm(b - O.csr_matvec(A, x.cpu().numpy())) / np.linalg.norm(b)
+    assert true <= 1e-10, true
+    xr = O.solve_reference(A, b)
+    assert np.linalg.norm(x.cpu().numpy() - xr) / np.linalg.norm(xr) <= 1e-7
