@@ -86,8 +86,9 @@ struct Mat {
     // offset dictionaries (one-batch matrices of at most 8 entries a row):
     // cdict[c] >= 0 names chunk c's block b, whose 16 column - row offsets are
     // dtab[16 b ..] and whose lane l holds the 4-bit offset indices of slots
-    // 0..7 in dword[64 b + l]; inside each SpMV workgroup's range these chunks
-    // come first.  nullptr: none.
+    // 0..U-1 in dword[64 b + l] (with U <= 7 its top 4 bits hold the row's
+    // length); inside each SpMV workgroup's range these chunks come first.
+    // nullptr: none.
     const int32_t *cdict;
     const int32_t *dtab;
     const uint32_t *dword;

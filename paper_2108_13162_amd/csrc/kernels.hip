@@ -254,6 +254,18 @@ __device__ __forceinline__ void load_row(int &len, XT &rv, XT &pv, XT &xv, int r
     if (MODE == SPMV_STEP) xv = x[t];
 }
 
+// load_row for a dictionary chunk of at most 7 slots: the length comes with
+// the lane's index word (and every row of the chunk exists).
+template <typename XT, int MODE>
+__device__ __forceinline__ void load_row_nolen(XT &rv, XT &pv, XT &xv, int row, const XT *__restrict__ r,
+                                               const XT *__restrict__ p, const XT *__restrict__ x)
+{
+    rv = pv = xv = XT(0);
+    if (MODE == SPMV_FIRST || MODE == SPMV_STEP) rv = r[row];
+    if (MODE != SPMV_PLAIN) pv = p[row];
+    if (MODE == SPMV_STEP) xv = x[row];
+}
+
 template <int U>
 __device__ __forceinline__ void decode_cols(int (&cc)[U], const uint32_t (&cw)[U], int cb, int2 base, int lane)
 {
@@ -397,6 +409,9 @@ __global__ __launch_bounds__(kBS) __attribute__((amdgpu_waves_per_eu(1, 4))) voi
             // now): with stores outstanding the compiler can only wait for the
             // gathers below by draining everything
             __builtin_amdgcn_s_waitcnt(0x0f70);
+            // a dictionary chunk of at most 7 slots: the row length is the top
+            // 4 bits of the index word
+            if constexpr (DICT && U < 8) len = (int)(dw >> 28);
             XT rx[U], px[U];
             if constexpr (DICT)
                 decode_dict<U>(cc, dw, tab, row);
@@ -429,9 +444,15 @@ __global__ __launch_bounds__(kBS) __attribute__((amdgpu_waves_per_eu(1, 4))) voi
             } else {
                 load_batch<VT, U>(ncw, nvv, ncb, nbase, 0, nL, lane, col, col16, val);
             }
-            int nlen;
+            int nlen = 0;
             XT nr, np, nx;
-            load_row<XT, MODE>(nlen, nr, np, nx, nrow, nrows, rlen, r, pin, x);
+            // a dictionary chunk's rows all exist; with at most 7 slots their
+            // lengths come with the index words
+            constexpr bool LEN_IN_WORD = DICT && U < 8;
+            if constexpr (LEN_IN_WORD)
+                load_row_nolen<XT, MODE>(nr, np, nx, nrow, r, pin, x);
+            else
+                load_row<XT, MODE>(nlen, nr, np, nx, nrow, nrows, rlen, r, pin, x);
             __builtin_amdgcn_sched_barrier(0);
             XT prod[U];
 #pragma unroll
@@ -476,7 +497,7 @@ __global__ __launch_bounds__(kBS) __attribute__((amdgpu_waves_per_eu(1, 4))) voi
             cb = ncb;
             wb = nwb;
             row = nrow;
-            len = nlen;
+            if constexpr (!LEN_IN_WORD) len = nlen;
             blk = nblk;
             rrow = nr;
             prow = np;

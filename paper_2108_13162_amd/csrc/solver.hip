@@ -342,11 +342,13 @@ void build_matrix(const ss_part *p, Layout &L, int32_t tile_nnz, int32_t force, 
                         const int32_t d = L.col[L.cptr[i] + (int64_t)j * 64 + lane] - t;
                         q = (int32_t)(std::lower_bound(offs.begin(), offs.end(), d) - offs.begin());
                     }
-                    wd |= (uint32_t)q << (4 * j);
+                    if (j < L.unroll) wd |= (uint32_t)q << (4 * j);
                     const int32_t back = t + L.dtab[(size_t)blk * kDictOffsets + q];
                     if (j < L.clen[i] ? back != L.col[L.cptr[i] + (int64_t)j * 64 + lane] : back != t)
                         L.encode_ok = false;
                 }
+                // with at most 7 slots the top 4 bits hold the row's length
+                if (L.unroll < kDictSlots) wd |= (uint32_t)L.rlen[t] << (4 * (kDictSlots - 1));
                 L.dword.push_back(wd);
             }
         }
