@@ -56,6 +56,9 @@ struct Layout {
     std::vector<int32_t> cbase;       // SELL: two window bases per chunk
     int64_t col_bytes = 0;            // column data the SpMV reads: 2 or 4 B per stored (non-padding) entry,
                                       // a dictionary chunk's 4 B per row and 64 B table
+    int64_t struct_bytes = 0;         // row structure the SpMV reads: SELL a chunk's start, first row, length,
+                                      // column start, window bases (and dictionary block) and 1 B per row
+                                      // unless a dictionary word holds it; CSR the row pointers
     bool encode_ok = true;            // column encoding verified
     std::vector<int32_t> cptr, cpos, rowptr, tile_row;
     std::vector<uint8_t> clen, rlen;
@@ -352,6 +355,12 @@ void build_matrix(const ss_part *p, Layout &L, int32_t tile_nnz, int32_t force, 
                 L.dword.push_back(wd);
             }
         }
+        L.struct_bytes = 0;
+        for (int32_t i = 0; i < nch; ++i) {
+            L.struct_bytes += 4 + 4 + 1 + 4 + 8 + (L.dtab.empty() ? 0 : 4);
+            if (L.cdict[i] < 0 || L.unroll >= kDictSlots)
+                for (int32_t lane = 0; lane < 64; ++lane) L.struct_bytes += L.cpos[i] + lane < nl ? 1 : 0;
+        }
         L.col.swap(wide);
     } else {
         L.fmt = FMT_CSR;
@@ -361,6 +370,7 @@ void build_matrix(const ss_part *p, Layout &L, int32_t tile_nnz, int32_t force, 
         L.col.resize((size_t)L.stored);
         L.nzmap.resize((size_t)L.stored);
         L.col_bytes = 4 * L.stored;
+        L.struct_bytes = 4 * ((int64_t)nl + 1);
         for (int32_t t = 0; t < nl; ++t) {
             const int32_t u = src_row[t];
             for (int32_t e = p->bd_rowptr[u], k = L.rowptr[t]; e < p->bd_rowptr[u + 1]; ++e, ++k) {
@@ -389,7 +399,8 @@ void build_matrix(const ss_part *p, Layout &L, int32_t tile_nnz, int32_t force, 
 
 struct ss_solver {
     int device = 0;
-    int64_t col_bytes = 0;  // column data the SpMV reads (see Layout::col_bytes)
+    int64_t col_bytes = 0;     // column data the SpMV reads (see Layout::col_bytes)
+    int64_t struct_bytes = 0;  // row structure the SpMV reads (see Layout::struct_bytes)
     hipStream_t stream = nullptr;
     hipStream_t cap = nullptr;  // private stream used only to capture graphs
     ss_opts opts{};
@@ -676,6 +687,7 @@ int setup_impl(const ss_csr *A, const ss_part *p, const ss_opts *o, void *hip_st
     s->ngamma = (int32_t)p->gamma.size();
     s->stored = L.stored;
     s->col_bytes = L.col_bytes;
+    s->struct_bytes = L.struct_bytes;
 
     std::vector<double> val_st((size_t)L.stored, 0.0);
     for (int64_t k = 0; k < L.stored; ++k)
@@ -1087,12 +1099,12 @@ int ss_cg_time_spmv(ss_solver *s, int32_t reps, double *ms_per_launch, double *b
     for (auto &e : ev) (void)hipEventDestroy(e);
     if (err != hipSuccess) return fail(SS_EDEVICE, std::string("SpMV timing: ") + hipGetErrorString(err));
     *ms_per_launch = total / reps;
-    // values and column data of the stored entries, row structure (4 B per
-    // row), one read of r, p_(k-1) and x, writes of p_k, q and x (the split
-    // step also reads p_k back for the SpMV)
+    // values and column data of the stored entries, the row structure the
+    // format reads, one read of r, p_(k-1) and x, writes of p_k, q and x (the
+    // split step also reads p_k back for the SpMV)
     const double sv = f32 ? 4.0 : 8.0;
     if (bytes_per_launch)
-        *bytes_per_launch = sv * (double)s->nnz + (double)s->col_bytes + 4.0 * (double)(s->n_loc + 1) +
+        *bytes_per_launch = sv * (double)s->nnz + (double)s->col_bytes + (double)s->struct_bytes +
                             (split_step(f32 ? s->mat32 : s->mat) ? 7.0 : 6.0) * sv * (double)s->n_loc;
     std::memcpy(s->st_pinned, &saved, sizeof(DevState));
     SS_HIP(hipMemcpyAsync(st, s->st_pinned, sizeof(DevState), hipMemcpyHostToDevice, s->stream));
