@@ -251,6 +251,16 @@ int ss_cg_solve(ss_solver *s, const double *b_dev, double *x_dev, double tol, in
  * numbering, length n; y must not alias x. */
 int ss_cg_apply(ss_solver *s, const double *x_dev, double *y_dev);
 
+/* y_dev = A32 x_dev in FP32, the product the inner CG of the SS_FP32_*
+ * modes uses: A32 = the values rounded to FP32 (nearest even), every row
+ * summed left to right in column order with each product and sum rounded to
+ * FP32 (no fused multiply-add), then the interface copies added in ascending
+ * sub-domain order in FP32 (Section 4.4.1, Algorithms 4 and 5).  x_dev[n],
+ * y_dev[n]: device, FP32, global numbering; y must not alias x.
+ * Errors: SS_EINVAL (NULL argument), SS_EUNSUPPORTED (solver set up with
+ * SS_FP64: it holds no FP32 values), SS_EDEVICE. */
+int ss_cg_apply_f32(ss_solver *s, const float *x_dev, float *y_dev);
+
 /* Replaces the matrix values (same pattern): val_dev[nnz], device, global
  * stored-entry order.  The values must keep A symmetric positive-definite;
  * symmetry is not re-checked. */

@@ -35,6 +35,10 @@ def lib():
         L.orc_csr_matvec.argtypes = [i64, P, P, P, P, P]
         L.orc_csr_matvec_f32.argtypes = [i64, P, P, P, P, P]
         L.orc_iface_sum.argtypes = [i64, P, P, P]
+        L.orc_iface_sum_f32.argtypes = [i64, P, P, P]
+        L.orc_owned_dot_f32.argtypes = [i32, P, P, P, P, P]
+        L.orc_owned_dot_f32.restype = dbl
+        L.orc_ss_spmv_f32.argtypes = [P, P, P]
         L.orc_dot.argtypes = [i64, P, P]
         L.orc_dot.restype = dbl
         L.orc_owned_dot.argtypes = [i32, P, P, P, P, P]
@@ -133,6 +137,14 @@ def iface_sum(sd: SubDomains, q: np.ndarray) -> np.ndarray:
     return q
 
 
+def iface_sum_f32(copy_ptr, copy_pos, q32) -> np.ndarray:
+    """FP32 interface assembly on explicit copy lists (sequential, list order)."""
+    q = np.ascontiguousarray(q32, dtype=np.float32).copy()
+    cp = _i32(copy_ptr)
+    lib().orc_iface_sum_f32(len(cp) - 1, _p(cp), _p(_i32(copy_pos)), _p(q))
+    return q
+
+
 def dot(u, v) -> float:
     u, v = _f64(u), _f64(v)
     return lib().orc_dot(len(u), _p(u), _p(v))
@@ -141,6 +153,13 @@ def dot(u, v) -> float:
 def owned_dot(sd: SubDomains, u, v) -> float:
     u, v = _f64(u), _f64(v)
     return lib().orc_owned_dot(sd.nparts, _p(sd.sub_off), _p(sd.n_int), _p(sd.n_own), _p(u), _p(v))
+
+
+def owned_dot_f32(sd: SubDomains, u32, v32) -> float:
+    """Weighted local dot of FP32 vectors, accumulated in FP64."""
+    u = np.ascontiguousarray(u32, dtype=np.float32)
+    v = np.ascontiguousarray(v32, dtype=np.float32)
+    return lib().orc_owned_dot_f32(sd.nparts, _p(sd.sub_off), _p(sd.n_int), _p(sd.n_own), _p(u), _p(v))
 
 
 def gather(sd: SubDomains, v: np.ndarray) -> np.ndarray:
@@ -166,6 +185,19 @@ def ss_spmv_local(sd: SubDomains, val: np.ndarray, x_loc: np.ndarray) -> np.ndar
     q = np.empty(sd.n_loc)
     lib().orc_ss_spmv(S.ref(), _p(x_loc), _p(q))
     return q
+
+
+def ss_spmv_f32(A, sd: SubDomains, x32: np.ndarray) -> np.ndarray:
+    """y = A32 x32 in FP32 through the sub-structured path, global numbering:
+    the inner product of the FP32 modes (values rounded to FP32)."""
+    S = _Sub(sd, A.val)
+    xl = np.ascontiguousarray(np.asarray(x32, dtype=np.float32)[sd.l2g])
+    q = np.empty(sd.n_loc, dtype=np.float32)
+    lib().orc_ss_spmv_f32(S.ref(), _p(xl), _p(q))
+    out = np.empty(A.n, dtype=np.float32)
+    pos = owned_positions(sd)
+    out[sd.l2g[pos]] = q[pos]
+    return out
 
 
 def ss_spmv(A, sd: SubDomains, x: np.ndarray) -> np.ndarray:

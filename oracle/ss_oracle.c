@@ -137,7 +137,8 @@ void orc_ss_spmv(const orc_sub *S, const double *x, double *q)
     orc_iface_sum(S->ngamma, S->copy_ptr, S->copy_pos, q);
 }
 
-static void ss_spmv_f32(const orc_sub *S, const float *x, float *q)
+/* The same in FP32 (values rounded to FP32, every product and sum in FP32). */
+void orc_ss_spmv_f32(const orc_sub *S, const float *x, float *q)
 {
     orc_csr_matvec_f32(S->n_loc, S->bd_rowptr, S->bd_colidx, S->bd_val32, x, q);
     orc_iface_sum_f32(S->ngamma, S->copy_ptr, S->copy_pos, q);
@@ -617,7 +618,7 @@ int orc_ss_ir(const orc_sub *S, int64_t n, const int32_t *rowptr, const int32_t 
         const double stop_in = inner_tol * sqrt(rr_in);
         int32_t kin = 0;
         while (sqrt(rr_in) > stop_in && kin < inner_maxit && k < maxit) {
-            ss_spmv_f32(S, p, q);
+            orc_ss_spmv_f32(S, p, q);
             const double pq = orc_owned_dot_f32(S->P, S->sub_off, S->n_int, S->n_own, p, q);
             if (!(pq > 0.0) || !isfinite(pq)) { st = ORC_EBREAKDOWN; goto out; }
             const double alpha = rr_in / pq;
@@ -702,7 +703,7 @@ int orc_ss_ru(const orc_sub *S, int64_t n, const int32_t *rowptr, const int32_t 
         double rref = sqrt(rr64);
         const int32_t k0 = k;
         for (;;) {
-            ss_spmv_f32(S, p, q);
+            orc_ss_spmv_f32(S, p, q);
             const double pq = orc_owned_dot_f32(S->P, S->sub_off, S->n_int, S->n_own, p, q);
             if (!(pq > 0.0) || !isfinite(pq)) { st = ORC_EBREAKDOWN; goto out; }
             const double alpha = rr / pq;

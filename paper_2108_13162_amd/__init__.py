@@ -91,6 +91,7 @@ def lib() -> C.CDLL:
         "ss_cg_setup": (C.c_int, [P, P, P, P, P]),
         "ss_cg_solve": (C.c_int, [P, P, P, dbl, i32, P, P]),
         "ss_cg_apply": (C.c_int, [P, P, P]),
+        "ss_cg_apply_f32": (C.c_int, [P, P, P]),
         "ss_cg_set_values": (C.c_int, [P, P]),
         "ss_cg_grad_vals": (C.c_int, [P, P, P, P]),
         "ss_cg_time_spmv": (C.c_int, [P, i32, P, P]),
@@ -314,6 +315,15 @@ def _dev_f64(t, n: int, name: str):
     return C.c_void_p(t.data_ptr())
 
 
+def _dev_f32(t, n: int, name: str):
+    torch = _torch()
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float32 and t.is_contiguous()):
+        raise TypeError(f"{name} must be a contiguous float32 tensor on the GPU")
+    if t.numel() != n:
+        raise ValueError(f"{name} has {t.numel()} elements, expected {n}")
+    return C.c_void_p(t.data_ptr())
+
+
 def ss_cg_setup(A, part: Partition, opts: Optional[ss_opts] = None, device=None) -> Solver:
     """Uploads partition `part` of A to the current device; stream = torch's current stream."""
     torch = _torch()
@@ -385,6 +395,14 @@ def ss_cg_apply(s: Solver, x, y=None):
     torch = _torch()
     y = torch.empty_like(x) if y is None else y
     _check(lib().ss_cg_apply(s.h, _dev_f64(x, s.n, "x"), _dev_f64(y, s.n, "y")), "ss_cg_apply")
+    return y
+
+
+def ss_cg_apply_f32(s: Solver, x, y=None):
+    """y = A32 x in FP32 (solver set up with SS_FP32_IR or SS_FP32_RU)."""
+    torch = _torch()
+    y = torch.empty_like(x) if y is None else y
+    _check(lib().ss_cg_apply_f32(s.h, _dev_f32(x, s.n, "x"), _dev_f32(y, s.n, "y")), "ss_cg_apply_f32")
     return y
 
 

@@ -125,12 +125,13 @@ struct Partials {
 };
 
 // ---- launchers (all asynchronous on the given stream) ---------------------
-// Local copies of a global vector (each copy gets the node's value).
-template <typename XT>
-void launch_gather(hipStream_t s, int32_t n_loc, const int32_t *l2g, const double *src, XT *dst);
+// Local copies of a global vector (each copy gets the node's value, converted
+// to XT with round-to-nearest-even).
+template <typename ST, typename XT>
+void launch_gather(hipStream_t s, int32_t n_loc, const int32_t *l2g, const ST *src, XT *dst);
 // Global vector from the owned copies; writes zeros if `state` says b = 0.
-template <typename XT>
-void launch_scatter(hipStream_t s, int32_t n, const int32_t *g2own, const XT *src, double *dst,
+template <typename XT, typename DT>
+void launch_scatter(hipStream_t s, int32_t n, const int32_t *g2own, const XT *src, DT *dst,
                     const DevState *state);
 
 // q = A_bd x (no assembly).

@@ -1164,23 +1164,23 @@ __global__ __launch_bounds__(kBS) void k_ru_fold(int32_t n_loc, double *__restri
 
 // ---- gathers, scatters, gradient -------------------------------------------
 
-template <typename XT>
+template <typename ST, typename XT>
 __global__ __launch_bounds__(kBS) void k_gather(int32_t n_loc, const int32_t *__restrict__ l2g,
-                                                const double *__restrict__ src, XT *__restrict__ dst)
+                                                const ST *__restrict__ src, XT *__restrict__ dst)
 {
     const int c = blockIdx.x * kBS + threadIdx.x;
     if (c < n_loc) dst[c] = (XT)src[l2g[c]];
 }
 
-template <typename XT>
+template <typename XT, typename DT>
 __global__ __launch_bounds__(kBS) void k_scatter(int32_t n, const int32_t *__restrict__ g2own,
-                                                 const XT *__restrict__ src, double *__restrict__ dst,
+                                                 const XT *__restrict__ src, DT *__restrict__ dst,
                                                  const DevState *__restrict__ st)
 {
     const int i = blockIdx.x * kBS + threadIdx.x;
     if (i >= n) return;
     const bool zero = st && st->status == ST_ZERO_RHS;
-    dst[i] = zero ? 0.0 : (double)src[g2own[i]];
+    dst[i] = zero ? DT(0) : (DT)src[g2own[i]];
 }
 
 // one thread per row: SELL threads walk the stored chunks (lane = row of the
@@ -1321,16 +1321,17 @@ void spmv_pq_dispatch(hipStream_t s, const Mat &A, const XT *p, XT *q, Partials 
 
 // ---- launchers -----------------------------------------------------------------
 
-template <typename XT>
-void launch_gather(hipStream_t s, int32_t n_loc, const int32_t *l2g, const double *src, XT *dst)
+template <typename ST, typename XT>
+void launch_gather(hipStream_t s, int32_t n_loc, const int32_t *l2g, const ST *src, XT *dst)
 {
-    if (n_loc > 0) hipLaunchKernelGGL(k_gather<XT>, dim3(nblocks(n_loc)), dim3(kBS), 0, s, n_loc, l2g, src, dst);
+    if (n_loc > 0)
+        hipLaunchKernelGGL((k_gather<ST, XT>), dim3(nblocks(n_loc)), dim3(kBS), 0, s, n_loc, l2g, src, dst);
 }
 
-template <typename XT>
-void launch_scatter(hipStream_t s, int32_t n, const int32_t *g2own, const XT *src, double *dst, const DevState *st)
+template <typename XT, typename DT>
+void launch_scatter(hipStream_t s, int32_t n, const int32_t *g2own, const XT *src, DT *dst, const DevState *st)
 {
-    if (n > 0) hipLaunchKernelGGL(k_scatter<XT>, dim3(nblocks(n)), dim3(kBS), 0, s, n, g2own, src, dst, st);
+    if (n > 0) hipLaunchKernelGGL((k_scatter<XT, DT>), dim3(nblocks(n)), dim3(kBS), 0, s, n, g2own, src, dst, st);
 }
 
 template <typename VT, typename XT>
@@ -1455,8 +1456,9 @@ void launch_ru_fold(hipStream_t s, int32_t n_loc, double *x64, XT *d, const DevS
 
 // explicit instantiations
 #define SS_INST(XT)                                                                                                  \
-    template void launch_gather<XT>(hipStream_t, int32_t, const int32_t *, const double *, XT *);                    \
-    template void launch_scatter<XT>(hipStream_t, int32_t, const int32_t *, const XT *, double *, const DevState *); \
+    template void launch_gather<double, XT>(hipStream_t, int32_t, const int32_t *, const double *, XT *);            \
+    template void launch_scatter<XT, double>(hipStream_t, int32_t, const int32_t *, const XT *, double *,           \
+                                             const DevState *);                                                      \
     template void launch_spmv<XT, XT>(hipStream_t, const Mat &, const XT *, XT *);                                   \
     template void launch_spmv_first<XT, XT>(hipStream_t, const Mat &, const XT *, const XT *, XT *, XT *, Partials,  \
                                             DevState *);                                                             \
@@ -1477,5 +1479,9 @@ void launch_ru_fold(hipStream_t s, int32_t n_loc, double *x64, XT *d, const DevS
 SS_INST(double)
 SS_INST(float)
 #undef SS_INST
+// FP32 in and out (the FP32 product of ss_cg_apply_f32)
+template void launch_gather<float, float>(hipStream_t, int32_t, const int32_t *, const float *, float *);
+template void launch_scatter<float, float>(hipStream_t, int32_t, const int32_t *, const float *, float *,
+                                           const DevState *);
 
 }  // namespace ss

@@ -896,8 +896,8 @@ int ss_cg_solve(ss_solver *s, const double *b_dev, double *x_dev, double tol, in
     init.hist_cap = s->hist_cap;
     std::memcpy(s->st_pinned, &init, sizeof(DevState));
     SS_HIP(hipMemcpyAsync(s->st, s->st_pinned, sizeof(DevState), hipMemcpyHostToDevice, s->stream));
-    launch_gather<double>(s->stream, s->n_loc, s->l2g, b_dev, s->b);
-    launch_gather<double>(s->stream, s->n_loc, s->l2g, x_dev, s->x);
+    launch_gather<double, double>(s->stream, s->n_loc, s->l2g, b_dev, s->b);
+    launch_gather<double, double>(s->stream, s->n_loc, s->l2g, x_dev, s->x);
 
     int32_t status = ST_RUNNING;
     int32_t restarts = -1, outer = 0;
@@ -976,7 +976,7 @@ int ss_cg_solve(ss_solver *s, const double *b_dev, double *x_dev, double tol, in
             if (status == ST_BREAKDOWN) break;
         }
     }
-    launch_scatter<double>(s->stream, s->n, s->g2own, s->x, x_dev, s->st);
+    launch_scatter<double, double>(s->stream, s->n, s->g2own, s->x, x_dev, s->st);
     SS_HIP(hipGetLastError());
     SS_HIP(hipMemcpyAsync(s->st_pinned, s->st, sizeof(DevState), hipMemcpyDeviceToHost, s->stream));
     SS_HIP(hipStreamSynchronize(s->stream));
@@ -1010,10 +1010,23 @@ int ss_cg_solve(ss_solver *s, const double *b_dev, double *x_dev, double tol, in
 int ss_cg_apply(ss_solver *s, const double *x_dev, double *y_dev)
 {
     if (!s || !x_dev || !y_dev) return fail(SS_EINVAL, "NULL argument");
-    launch_gather<double>(s->stream, s->n_loc, s->l2g, x_dev, s->p0);
+    launch_gather<double, double>(s->stream, s->n_loc, s->l2g, x_dev, s->p0);
     launch_spmv<double, double>(s->stream, s->mat, s->p0, s->q);
     launch_iface_sum<double>(s->stream, s->ifc, s->q);
-    launch_scatter<double>(s->stream, s->n, s->g2own, s->q, y_dev, nullptr);
+    launch_scatter<double, double>(s->stream, s->n, s->g2own, s->q, y_dev, nullptr);
+    SS_HIP(hipGetLastError());
+    SS_HIP(hipStreamSynchronize(s->stream));
+    return SS_OK;
+}
+
+int ss_cg_apply_f32(ss_solver *s, const float *x_dev, float *y_dev)
+{
+    if (!s || !x_dev || !y_dev) return fail(SS_EINVAL, "NULL argument");
+    if (!s->val32) return fail(SS_EUNSUPPORTED, "the FP32 product needs a solver set up with an FP32 precision");
+    launch_gather<float, float>(s->stream, s->n_loc, s->l2g, x_dev, s->p32a);
+    launch_spmv<float, float>(s->stream, s->mat32, s->p32a, s->q32);
+    launch_iface_sum<float>(s->stream, s->ifc, s->q32);
+    launch_scatter<float, float>(s->stream, s->n, s->g2own, s->q32, y_dev, nullptr);
     SS_HIP(hipGetLastError());
     SS_HIP(hipStreamSynchronize(s->stream));
     return SS_OK;

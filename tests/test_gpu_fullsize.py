@@ -1,0 +1,151 @@
+"""Full-size accuracy parity with the oracle on the benchmarked systems.
+
+For each configuration the oracle's own results are computed once per module
+on the CPU (the sub-structured CG of Algorithm 3 to 1e-10, and the solution
+to its attainable floor, global CG to 1e-14); the GPU solves go through the
+C-ABI.  Checked per system:
+  - iteration count to ||r|| <= 1e-10 ||b|| within 2 of the oracle's;
+  - the true residual, recomputed with the oracle's product, <= 1e-10;
+  - the relative error against the floor solution, printed and bounded by
+    max(1e-9, 2x the oracle's own error at the same tolerance) (the error of
+    any x with residual 1e-10 is bounded only by cond(A) 1e-10);
+  - with the residual driven to 1e-13, the error <= 1e-9.
+The mixed-precision modes on the 96^3 Q1 system are held to max(1e-9, 10x
+the oracle FP64 CG's error), and their FP32 product is compared bit for bit.
+These need minutes of CPU time for the oracle side."""
+import time
+
+import numpy as np
+import pytest
+
+import oracle as O
+import paper_2108_13162_amd as ss
+from workloads import config
+
+torch = pytest.importorskip("torch")
+pytestmark = [pytest.mark.gpu, pytest.mark.slow, pytest.mark.timeout(1200)]
+DEV = "cuda:0"
+
+
+def _t(a):
+    return torch.tensor(np.ascontiguousarray(a, dtype=np.float64), device=DEV)
+
+
+def _err(x, ref):
+    return float(np.linalg.norm(x - ref) / np.linalg.norm(ref))
+
+
+def _true(A, b, x):
+    return float(np.linalg.norm(b - O.csr_matvec(A, x)) / np.linalg.norm(b))
+
+
+class _Ref:
+    """The oracle's results on one workload."""
+
+    def __init__(self, idx, pcg=False):
+        t0 = time.perf_counter()
+        self.w = config(idx)
+        A, b = self.w.A, self.w.b
+        self.sd = O.split(A.rowptr, A.colidx, O.partition_workload(self.w), self.w.nparts)
+        self.x10, self.r10 = O.ss_cg(A, self.sd, b, tol=1e-10, maxit=100000, hist=False)
+        self.xref = O.solve_reference(A, b)
+        self.err10 = _err(self.x10, self.xref)
+        if pcg:
+            self.xp, self.rp = O.ss_pcg(A, self.sd, b, tol=1e-10, maxit=100000, hist=False)
+            self.errp = _err(self.xp, self.xref)
+        print(f"\n# oracle {self.w.name}: {self.r10.iterations} iterations to 1e-10, error {self.err10:.2e} "
+              f"({time.perf_counter() - t0:.0f} s)", flush=True)
+
+
+def _solve(s, b, tol, n):
+    x = torch.zeros(n, dtype=torch.float64, device=DEV)
+    r = ss.ss_cg_solve(s, _t(b), x, tol=tol, maxit=100000)
+    return x.cpu().numpy(), r
+
+
+def _fp64_checks(ref, s, name):
+    A, b = ref.w.A, ref.w.b
+    x, r = _solve(s, b, 1e-10, A.n)
+    true, err = _true(A, b, x), _err(x, ref.xref)
+    print(f"{name}: {r.iterations} iterations (oracle {ref.r10.iterations}), true relres {true:.2e}, "
+          f"error {err:.2e} (oracle {ref.err10:.2e})")
+    assert r.status == ss.SS_OK and true <= 1e-10, (r, true)
+    assert abs(r.iterations - ref.r10.iterations) <= 2, (r.iterations, ref.r10.iterations)
+    assert err <= max(1e-9, 2 * ref.err10), (err, ref.err10)
+    x13, r13 = _solve(s, b, 1e-13, A.n)
+    err13 = _err(x13, ref.xref)
+    print(f"{name} at 1e-13: {r13.iterations} iterations, error {err13:.2e}")
+    assert r13.status == ss.SS_OK and err13 <= 1e-9, err13
+
+
+# ---------------------------------------------------------------- cfg2 -----
+
+@pytest.fixture(scope="module")
+def cfg2():
+    return _Ref(2, pcg=True)
+
+
+def test_cfg2_product_and_first_steps(cfg2):
+    # the benchmarked system: 128^3 lognormal diffusion, 8 boxes
+    A, b, sd = cfg2.w.A, cfg2.w.b, cfg2.sd
+    s = ss.ss_cg_setup(A, ss.partition_workload(cfg2.w))
+    xv = np.random.default_rng(77).uniform(-1.0, 1.0, A.n)
+    assert np.array_equal(ss.ss_cg_apply(s, _t(xv)).cpu().numpy(), O.ss_spmv(A, sd, xv))
+    # 10 CG steps: within 10x of the spread between the oracle's global and
+    # sub-structured CG (the two differ only in dot summation order)
+    x = torch.zeros(A.n, dtype=torch.float64, device=DEV)
+    ss.ss_cg_solve(s, _t(b), x, tol=0.0, maxit=10)
+    xo, _ = O.ss_cg(A, sd, b, tol=0.0, maxit=10, hist=False)
+    xgl, _ = O.cg(A, b, tol=0.0, maxit=10, hist=False)
+    spread = _err(xgl, xo)
+    assert _err(x.cpu().numpy(), xo) <= max(1e-12, 10 * spread)
+
+
+def test_cfg2_cg_accuracy(cfg2):
+    _fp64_checks(cfg2, ss.ss_cg_setup(cfg2.w.A, ss.partition_workload(cfg2.w)), "cfg2 CG")
+
+
+def test_cfg2_pcg_accuracy(cfg2):
+    A, b = cfg2.w.A, cfg2.w.b
+    s = ss.ss_cg_setup(A, ss.partition_workload(cfg2.w), ss.default_opts(precond=ss.SS_PRECOND_JACOBI))
+    x, r = _solve(s, b, 1e-10, A.n)
+    true, err = _true(A, b, x), _err(x, cfg2.xref)
+    print(f"cfg2 PCG: {r.iterations} iterations (oracle {cfg2.rp.iterations}), true relres {true:.2e}, "
+          f"error {err:.2e} (oracle {cfg2.errp:.2e})")
+    assert r.status == ss.SS_OK and true <= 1e-10
+    assert abs(r.iterations - cfg2.rp.iterations) <= 2, (r.iterations, cfg2.rp.iterations)
+    assert err <= max(1e-9, 2 * cfg2.errp)
+
+
+# ---------------------------------------------------------------- cfg5 -----
+
+def test_cfg5_forward_accuracy():
+    ref = _Ref(5)
+    _fp64_checks(ref, ss.ss_cg_setup(ref.w.A, ss.partition_workload(ref.w)), "cfg5 CG")
+
+
+# ---------------------------------------------------------------- cfg3 -----
+
+@pytest.fixture(scope="module")
+def cfg3():
+    return _Ref(3)
+
+
+def test_cfg3_fp64_accuracy(cfg3):
+    _fp64_checks(cfg3, ss.ss_cg_setup(cfg3.w.A, ss.partition_workload(cfg3.w)), "cfg3 CG")
+
+
+@pytest.mark.parametrize("prec", ["SS_FP32_IR", "SS_FP32_RU"])
+def test_cfg3_mixed_accuracy(cfg3, prec):
+    A, b = cfg3.w.A, cfg3.w.b
+    s = ss.ss_cg_setup(A, ss.partition_workload(cfg3.w), ss.default_opts(precision=getattr(ss, prec)))
+    # the FP32 product at full size: the oracle's, bit for bit
+    x32 = np.random.default_rng(11).uniform(-1.0, 1.0, A.n).astype(np.float32)
+    y32 = ss.ss_cg_apply_f32(s, torch.tensor(x32, device=DEV)).cpu().numpy()
+    assert np.array_equal(y32.view(np.uint32), O.ss_spmv_f32(A, cfg3.sd, x32).view(np.uint32))
+    x, r = _solve(s, b, 1e-10, A.n)
+    true, err = _true(A, b, x), _err(x, cfg3.xref)
+    print(f"cfg3 {prec}: {r.iterations} iterations ({r.outer_iterations} outer), true relres {true:.2e}, "
+          f"error {err:.2e} (oracle FP64 CG {cfg3.err10:.2e})")
+    assert r.status == ss.SS_OK and true <= 1e-10, (r, true)
+    assert err <= max(1e-9, 10 * cfg3.err10), (err, cfg3.err10)

@@ -46,8 +46,15 @@ def test_first_inner_steps_match_oracle(q1, k):
     assert r.status == ss.SS_NOT_CONVERGED and ro.status == O.NOT_CONVERGED
     assert r.iterations == ro.iterations == k and r.outer_iterations == ro.outer == 1
     xg = x.cpu().numpy()
-    # FP32 vectors: agreement up to a few FP32 roundings
-    assert np.linalg.norm(xg - xo) <= 1e-5 * np.linalg.norm(xo)
+    if k == 1:
+        # the FP32 product is the oracle's bit for bit; only the FP64 dot
+        # orders of ||r|| and (p, A p) differ, so each entry of d = fl32(alpha
+        # p) is at most one FP32 rounding (2^-23 relative) from the oracle's
+        # (x = ||r|| d); 2x covers a rare flip of fl32(r / ||r||) itself
+        assert np.linalg.norm(xg - xo) <= 2 * 2.0 ** -23 * np.linalg.norm(xo)
+    else:
+        # roundings that flip propagate through the FP32 recurrences
+        assert np.linalg.norm(xg - xo) <= 1e-5 * np.linalg.norm(xo)
 
 
 def test_ir_solve_reaches_fp64_residual(q1):
@@ -100,23 +107,3 @@ def test_ir_edge_cases():
     assert r.status == ss.SS_EBREAKDOWN
     with pytest.raises(ss.SSError):
         ss.ss_cg_setup(A, p, ss.default_opts(precision=ss.SS_FP32_IR, inner_tol=2.0))
-
-
-def test_full_size_cfg3_ir_and_fp64():
-    # Q1 hexahedra on 96^3 unknowns (23.4M entries), 16 uneven RCB parts
-    w = config(3)
-    A, b = w.A, w.b
-    p = ss.partition_workload(w)
-    out = {}
-    for prec in (ss.SS_FP64, ss.SS_FP32_IR):
-        s = ss.ss_cg_setup(A, p, ss.default_opts(precision=prec))
-        x = torch.zeros(A.n, dtype=torch.float64, device=DEV)
-        r = ss.ss_cg_solve(s, _t(b), x, tol=1e-10, maxit=100000)
-        xg = x.cpu().numpy()
-        true = np.linalg.norm(b - O.csr_matvec(A, xg)) / np.linalg.norm(b)
-        assert r.status == ss.SS_OK and true <= 1e-10, (prec, r, true)
-        out[prec] = (xg, r)
-        del s
-    d = np.linalg.norm(out[0][0] - out[1][0]) / np.linalg.norm(out[0][0])
-    print(f"cfg3: FP64 {out[0][1].iterations} its; IR {out[1][1].iterations} its / {out[1][1].outer_iterations} outer; "
-          f"IR vs FP64 solution {d:.2e}")

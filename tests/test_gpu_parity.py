@@ -302,31 +302,3 @@ def test_set_values_and_gradient_kernel():
     lam = uniform_rhs(A.n, 4)
     d = _np(ss.ss_cg_grad_vals(s, _t(lam), _t(x)))
     assert np.array_equal(d, O.grad_vals(A2, lam, x))
-
-
-def test_full_size_cfg2():
-    # the benchmarked system: 128^3 lognormal diffusion, 8 boxes
-    w = config(2)
-    A = w.A
-    p = ss.partition_workload(w)
-    sd = O.split(A.rowptr, A.colidx, O.box_partition(w.grid, w.boxes), 8)
-    s = _setup(A, p)
-    # SpMV + assembly at full size: bitwise
-    xv = uniform_rhs(A.n, 77)
-    assert np.array_equal(_np(ss.ss_cg_apply(s, _t(xv))), O.ss_spmv(A, sd, xv))
-    # 10 CG steps against the oracle
-    b = w.b
-    x = torch.zeros(A.n, dtype=torch.float64, device=DEV)
-    r = ss.ss_cg_solve(s, _t(b), x, tol=0.0, maxit=10, hist=True)
-    xo, ro = O.ss_cg(A, sd, b, tol=0.0, maxit=10)
-    dx_o, dh_o = _oracle_spread(A, sd, b, 10)
-    assert np.linalg.norm(_np(x) - xo) <= max(1e-12, 10 * dx_o) * np.linalg.norm(xo)
-    assert np.max(np.abs(r.hist - ro.hist) / ro.hist) <= max(1e-12, 10 * dh_o)
-    # full solve: the recomputed residual, checked with the oracle's SpMV
-    x = torch.zeros(A.n, dtype=torch.float64, device=DEV)
-    r = ss.ss_cg_solve(s, _t(b), x, tol=1e-10, maxit=20000)
-    xg = _np(x)
-    assert r.status == ss.SS_OK
-    true = np.linalg.norm(b - O.csr_matvec(A, xg)) / np.linalg.norm(b)
-    assert true <= 1e-10, true
-    print(f"cfg2: {r.iterations} iterations, true relres {true:.3e}, restarts {r.restarts}")

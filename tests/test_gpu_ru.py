@@ -44,7 +44,15 @@ def test_first_steps_match_oracle(q1, k):
     xo, ro = O.ss_ru(w.A, sd, w.b, tol=1e-10, maxit=k, check_every=CHUNK)
     assert r.status == ss.SS_NOT_CONVERGED and ro.status == O.NOT_CONVERGED
     assert r.iterations == ro.iterations == k
-    assert np.linalg.norm(x.cpu().numpy() - xo) <= 1e-5 * np.linalg.norm(xo)
+    xg = x.cpu().numpy()
+    if k == 1:
+        # r = fl32(b), p = r and q = A32 p are the oracle's bit for bit; alpha
+        # differs only by the FP64 dot orders, so each entry of x = d =
+        # fl32(alpha p) is the oracle's or one FP32 rounding (2^-23 relative) away
+        assert np.all(np.abs(xg - xo) <= 2.0 ** -23 * np.abs(xo)), np.max(np.abs(xg - xo) / np.abs(xo))
+    else:
+        # roundings that flip propagate through the FP32 recurrences
+        assert np.linalg.norm(xg - xo) <= 1e-5 * np.linalg.norm(xo)
 
 
 def test_ru_solve_matches_oracle(q1):

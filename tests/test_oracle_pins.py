@@ -450,6 +450,115 @@ def test_fp32_spmv_exact_on_small_integers():
     assert np.array_equal(y32.astype(np.int64), A.to_dense().astype(np.int64) @ x)
 
 
+def _f32(v: float) -> float:
+    """Round a Python float (FP64) to the nearest FP32 value, ties to even."""
+    return float(np.float32(v))
+
+
+def _matvec_f32_by_hand(rowptr, colidx, v32, x32):
+    """An independent FP32 CSR product: every product and every running sum
+    is computed in FP64 and rounded to FP32 at once.  FP64 holds the exact
+    product of two FP32 numbers, and rounding an FP64 sum of two FP32 numbers
+    to FP32 equals the FP32 sum (53 >= 2*24 + 2 bits: double rounding is
+    innocuous for +, -, *), so this is exact FP32 arithmetic written with
+    Python floats."""
+    y = np.empty(len(rowptr) - 1, dtype=np.float32)
+    for i in range(len(rowptr) - 1):
+        s = 0.0
+        for k in range(rowptr[i], rowptr[i + 1]):
+            s = _f32(s + _f32(float(v32[k]) * float(x32[colidx[k]])))
+        y[i] = s
+    return y
+
+
+def test_fp32_matvec_rounds_each_step_in_row_order():
+    # 27-point Q1 stiffness with lognormal element coefficients and a random
+    # FP32 vector: non-integer data, long rows, plenty of rounding
+    A = config(3, size=6).A
+    rng = np.random.default_rng(31)
+    v32 = A.val.astype(np.float32)
+    x32 = rng.uniform(-1.0, 1.0, A.n).astype(np.float32)
+    y = O.csr_matvec_f32(A.rowptr, A.colidx, v32, x32)
+    assert np.array_equal(y.view(np.uint32), _matvec_f32_by_hand(A.rowptr, A.colidx, v32, x32).view(np.uint32))
+    # it is FP32 arithmetic, not an FP64 row sum rounded once at the end
+    rows = A.row_of_nz()
+    prod64 = v32.astype(np.float64) * x32.astype(np.float64)[A.colidx]
+    y64 = np.array([math.fsum(prod64[A.rowptr[i]:A.rowptr[i + 1]]) for i in range(A.n)])
+    assert np.count_nonzero(y != y64.astype(np.float32)) > A.n // 10
+    # and it meets the recursive-summation bound gamma_k(2^-24) sum |a||x|
+    k = np.diff(A.rowptr).astype(np.float64)
+    u = 2.0 ** -24
+    gam = k * u / (1.0 - k * u)
+    absum = np.bincount(rows, weights=np.abs(prod64), minlength=A.n)
+    assert np.all(np.abs(y.astype(np.float64) - y64) <= gam * absum)
+
+
+def test_fp32_iface_sum_adds_copies_in_list_order():
+    # one interface node with three copies: (1 + 2^-24) + 2^-24 rounds to 1 at
+    # every step in FP32, 2^-24 + 2^-24 + 1 does not, and the FP64 sum of the
+    # three rounded once would give 1 + 2^-23
+    e = 2.0 ** -24
+    q = np.array([1.0, e, e, 7.0], dtype=np.float32)
+    out = O.iface_sum_f32([0, 3], [0, 1, 2], q)
+    assert np.array_equal(out, np.array([1.0, 1.0, 1.0, 7.0], dtype=np.float32))
+    back = O.iface_sum_f32([0, 3], [2, 1, 0], q)
+    assert np.array_equal(back, np.array([1.0 + 2 * e] * 3 + [7.0], dtype=np.float32))
+    assert np.float32(1.0 + 2 * e) != np.float32(1.0)
+    # two nodes, copies scattered: each node gets only its own copies' sum
+    q2 = np.array([0.5, 3.0, 0.25, 1.5], dtype=np.float32)
+    assert np.array_equal(O.iface_sum_f32([0, 2, 4], [0, 2, 3, 1], q2),
+                          np.array([0.75, 4.5, 0.75, 4.5], dtype=np.float32))
+
+
+def test_fp32_owned_dot_accumulates_in_fp64():
+    # FP32 inputs, FP64 products and FP64 sum over the owned positions: the
+    # 2^-26 terms vanish in an FP32 accumulation (1 + 2^-26 == 1 in FP32) but
+    # all stay in FP64, where this sum is exact
+    sd = O.split(poisson2d(4).rowptr, poisson2d(4).colidx, O.box_partition((4, 4), (2, 2)), 4)
+    own = O.owned_positions(sd)
+    u = np.zeros(sd.n_loc, dtype=np.float32)
+    u[own] = 2.0 ** -13
+    u[own[0]] = 1.0
+    u[np.setdiff1d(np.arange(sd.n_loc), own)] = 1e3   # ghost copies: not counted
+    got = O.owned_dot_f32(sd, u, u)
+    assert got == 1.0 + (len(own) - 1) * 2.0 ** -26
+    assert np.float32(1.0) + np.float32(2.0 ** -26) == np.float32(1.0)
+    # non-integer data: within gamma_n(2^-53) of the exact sum of the FP32 products
+    rng = np.random.default_rng(5)
+    a = rng.uniform(-1, 1, sd.n_loc).astype(np.float32)
+    b = rng.uniform(-1, 1, sd.n_loc).astype(np.float32)
+    prods = a[own].astype(np.float64) * b[own].astype(np.float64)
+    nn = len(own)
+    assert abs(O.owned_dot_f32(sd, a, b) - math.fsum(prods)) <= nn * 2.0 ** -53 / (1 - nn * 2.0 ** -53) * np.abs(prods).sum()
+
+
+def test_ss_spmv_f32_is_local_products_then_assembly():
+    # the FP32 sub-structured product: FP32 local row sums (pinned above), then
+    # FP32 sums of the interface copies in ascending sub-domain order
+    w = config(3, size=8)
+    part = O.rcb_partition(w.coords, w.weights)
+    sd = O.split(w.A.rowptr, w.A.colidx, part, 16)
+    x32 = np.random.default_rng(9).uniform(-1, 1, w.A.n).astype(np.float32)
+    y = O.ss_spmv_f32(w.A, sd, x32)
+    v32 = sd.bd_values(w.A.val).astype(np.float32)
+    ql = _matvec_f32_by_hand(sd.bd_rowptr, sd.bd_colidx, v32, x32[sd.l2g])
+    for g in range(len(sd.gamma)):
+        cps = sd.copy_pos[sd.copy_ptr[g]:sd.copy_ptr[g + 1]]
+        t = 0.0
+        for c in cps:
+            t = _f32(t + float(ql[c]))
+        ql[cps] = t
+    own = O.owned_positions(sd)
+    ref = np.empty(w.A.n, dtype=np.float32)
+    ref[sd.l2g[own]] = ql[own]
+    assert np.array_equal(y.view(np.uint32), ref.view(np.uint32))
+    # within FP32 rounding of the FP64 global product
+    y64 = O.csr_matvec(w.A, x32.astype(np.float64))
+    absum = O.csr_matvec(CSR(w.A.n, w.A.rowptr, w.A.colidx, np.abs(w.A.val)), np.abs(x32.astype(np.float64)))
+    k = 27 + 8
+    assert np.all(np.abs(y - y64) <= (k * 2.0 ** -24 / (1 - k * 2.0 ** -24)) * absum * 1.01 + 1e-30)
+
+
 def test_ir_reaches_fp64_accuracy():
     M = 10
     A = diffusion3d_lognormal(M, seed=3, sigma=0.5)
