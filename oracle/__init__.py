@@ -21,6 +21,23 @@ from . import build as _build
 OK, NOT_CONVERGED, EINVAL, ENOMEM, EBREAKDOWN = 0, 1, -1, -2, -4
 
 _lib = None
+_lib_omp = None
+
+
+def lib_omp():
+    """The all-cores build (OpenMP) of the CG, for the benchmark's CPU baseline."""
+    global _lib_omp
+    if _lib_omp is None:
+        if (not os.path.exists(_build.LIB_OMP)
+                or os.path.getmtime(_build.LIB_OMP) < os.path.getmtime(_build.SRC_OMP)):
+            _build.build()
+        L = C.CDLL(_build.LIB_OMP)
+        i64, i32, dbl, P = C.c_int64, C.c_int32, C.c_double, C.c_void_p
+        L.orc_ss_cg_omp.argtypes = [P, i64, P, P, P, P, P, dbl, i32, i32, P, P, P]
+        L.orc_cg_omp.argtypes = [i64, P, P, P, P, P, dbl, i32, i32, P, P, P]
+        L.orc_omp_max_threads.restype = C.c_int
+        _lib_omp = L
+    return _lib_omp
 
 
 def lib():
@@ -46,6 +63,12 @@ def lib():
         L.orc_ss_spmv.argtypes = [P, P, P]
         L.orc_cg.argtypes = [i64, P, P, P, P, P, dbl, i32, P, P, P, P]
         L.orc_ss_cg.argtypes = [P, i64, P, P, P, P, P, dbl, i32, P, P, P, P]
+        L.orc_ss_cg_dot2.argtypes = [P, i64, P, P, P, P, P, dbl, i32, P, P, P, P]
+        L.orc_cg_dot2.argtypes = [i64, P, P, P, P, P, dbl, i32, P, P, P, P]
+        L.orc_dot2.argtypes = [i64, P, P]
+        L.orc_dot2.restype = dbl
+        L.orc_owned_dot2.argtypes = [i32, P, P, P, P, P]
+        L.orc_owned_dot2.restype = dbl
         L.orc_pcg.argtypes = [i64, P, P, P, P, P, dbl, i32, P, P, P, P]
         L.orc_ss_pcg.argtypes = [P, i64, P, P, P, P, P, dbl, i32, P, P, P, P]
         L.orc_ss_ir.argtypes = [P, i64, P, P, P, P, P, dbl, i32, dbl, i32, i32, P, P, P, P]
@@ -231,6 +254,40 @@ def ss_cg(A, sd: SubDomains, b, x0=None, tol: float = 1e-10, maxit: int = 10000,
     return x, Result(st, it.value, rel.value, tr.value, h[: it.value + 1] if hist else None)
 
 
+def dot2(u, v) -> float:
+    """Dot product as accurate as in twice the working precision (Dot2)."""
+    u, v = _f64(u), _f64(v)
+    return lib().orc_dot2(len(u), _p(u), _p(v))
+
+
+def owned_dot2(sd: SubDomains, u, v) -> float:
+    u, v = _f64(u), _f64(v)
+    return lib().orc_owned_dot2(sd.nparts, _p(sd.sub_off), _p(sd.n_int), _p(sd.n_own), _p(u), _p(v))
+
+
+def cg_dot2(A, b, x0=None, tol: float = 1e-10, maxit: int = 10000, hist: bool = True) -> tuple:
+    """cg with Dot2 dot products."""
+    b = _f64(b)
+    x = np.zeros(A.n) if x0 is None else _f64(x0).copy()
+    h = np.full(maxit + 1, np.nan)
+    it, rel, tr = C.c_int32(), C.c_double(), C.c_double()
+    st = lib().orc_cg_dot2(A.n, _p(_i32(A.rowptr)), _p(_i32(A.colidx)), _p(_f64(A.val)), _p(b), _p(x), tol,
+                           maxit, _p(h), C.byref(it), C.byref(rel), C.byref(tr))
+    return x, Result(st, it.value, rel.value, tr.value, h[: it.value + 1] if hist else None)
+
+
+def ss_cg_dot2(A, sd: SubDomains, b, x0=None, tol: float = 1e-10, maxit: int = 10000, hist: bool = True) -> tuple:
+    """ss_cg with Dot2 dot products: the reference for CG with exactly rounded dots."""
+    S = _Sub(sd, A.val)
+    b = _f64(b)
+    x = np.zeros(A.n) if x0 is None else _f64(x0).copy()
+    h = np.full(maxit + 1, np.nan)
+    it, rel, tr = C.c_int32(), C.c_double(), C.c_double()
+    st = lib().orc_ss_cg_dot2(S.ref(), A.n, _p(_i32(A.rowptr)), _p(_i32(A.colidx)), _p(_f64(A.val)), _p(b),
+                              _p(x), tol, maxit, _p(h), C.byref(it), C.byref(rel), C.byref(tr))
+    return x, Result(st, it.value, rel.value, tr.value, h[: it.value + 1] if hist else None)
+
+
 def pcg(A, b, x0=None, tol: float = 1e-10, maxit: int = 10000, hist: bool = True) -> tuple:
     """Jacobi-preconditioned CG on the global matrix (Algorithm 3, M = diag A)."""
     b = _f64(b)
@@ -340,6 +397,31 @@ def chol_solve(D: np.ndarray, b) -> tuple:
     x = np.empty(len(b))
     st = lib().orc_chol_solve(len(b), _p(a), _p(b), _p(x))
     return x, st
+
+
+def ss_cg_omp(A, sd: SubDomains, b, x0=None, tol: float = 1e-10, maxit: int = 100000, threads: int = 0) -> tuple:
+    """The sub-structured CG of ss_cg on `threads` OpenMP threads (0: default)."""
+    S = _Sub(sd, A.val)
+    b = _f64(b)
+    x = np.zeros(A.n) if x0 is None else _f64(x0).copy()
+    it, rel, tr = C.c_int32(), C.c_double(), C.c_double()
+    st = lib_omp().orc_ss_cg_omp(S.ref(), A.n, _p(_i32(A.rowptr)), _p(_i32(A.colidx)), _p(_f64(A.val)), _p(b),
+                                 _p(x), tol, maxit, threads, C.byref(it), C.byref(rel), C.byref(tr))
+    return x, Result(st, it.value, rel.value, tr.value)
+
+
+def cg_omp(A, b, x0=None, tol: float = 1e-10, maxit: int = 100000, threads: int = 0) -> tuple:
+    """CG on the global matrix on `threads` OpenMP threads (0: default)."""
+    b = _f64(b)
+    x = np.zeros(A.n) if x0 is None else _f64(x0).copy()
+    it, rel, tr = C.c_int32(), C.c_double(), C.c_double()
+    st = lib_omp().orc_cg_omp(A.n, _p(_i32(A.rowptr)), _p(_i32(A.colidx)), _p(_f64(A.val)), _p(b), _p(x), tol,
+                              maxit, threads, C.byref(it), C.byref(rel), C.byref(tr))
+    return x, Result(st, it.value, rel.value, tr.value)
+
+
+def omp_max_threads() -> int:
+    return int(lib_omp().orc_omp_max_threads())
 
 
 def solve_reference(A, b, tol: float = 1e-14, maxit: int = 200000) -> np.ndarray:

@@ -115,6 +115,65 @@ double orc_owned_dot_f32(int32_t P, const int32_t *sub_off, const int32_t *n_int
     return s;
 }
 
+/* Accurately evaluated dot products: Dot2 of Ogita, Rump and Oishi ("Accurate
+ * sum and dot product", SIAM J. Sci. Comput. 26(6), 2005).  Each product is
+ * split into its rounded value and exact error (TwoProduct), the rounded
+ * values are summed
+ * with exact error tracking (TwoSum), and all errors are added in at the end:
+ * the result is as accurate as a sum in twice the working precision, then
+ * rounded.  Used by the reference CG whose iteration counts stand for those of
+ * CG with exactly rounded dot products. */
+static void two_sum(double a, double b, double *x, double *y)
+{
+    *x = a + b;
+    const double z = *x - a;
+    *y = (a - (*x - z)) + (b - z);
+}
+
+/* Dekker's TwoProduct: a b = h + r exactly (Veltkamp's split of each factor
+ * into 26-bit halves; no fused multiply-add needed). */
+static void split(double a, double *hi, double *lo)
+{
+    const double c = 134217729.0 * a; /* 2^27 + 1 */
+    const double big = c - a;
+    *hi = c - big;
+    *lo = a - *hi;
+}
+
+static void two_product(double a, double b, double *h, double *r)
+{
+    double a1, a2, b1, b2;
+    *h = a * b;
+    split(a, &a1, &a2);
+    split(b, &b1, &b2);
+    *r = a2 * b2 - (((*h - a1 * b1) - a2 * b1) - a1 * b2);
+}
+
+static void dot2_add(double u, double v, double *p, double *s)
+{
+    double h, r, q;
+    two_product(u, v, &h, &r);
+    two_sum(*p, h, p, &q);
+    *s = *s + (q + r);
+}
+
+double orc_dot2(int64_t n, const double *u, const double *v)
+{
+    double p = 0.0, s = 0.0;
+    for (int64_t i = 0; i < n; ++i) dot2_add(u[i], v[i], &p, &s);
+    return p + s;
+}
+
+double orc_owned_dot2(int32_t P, const int32_t *sub_off, const int32_t *n_int, const int32_t *n_own,
+                      const double *u, const double *v)
+{
+    double p = 0.0, s = 0.0;
+    for (int32_t q = 0; q < P; ++q)
+        for (int64_t i = sub_off[q]; i < (int64_t)sub_off[q] + n_int[q] + n_own[q]; ++i)
+            dot2_add(u[i], v[i], &p, &s);
+    return p + s;
+}
+
 /* ---------------------------------------------------------------------- */
 /* Sub-domain description                                                  */
 /* ---------------------------------------------------------------------- */
@@ -233,12 +292,22 @@ static double glob_dot(const void *c, const double *u, const double *v)
     return orc_dot(((const csr_ctx *)c)->n, u, v);
 }
 
+static double glob_dot2(const void *c, const double *u, const double *v)
+{
+    return orc_dot2(((const csr_ctx *)c)->n, u, v);
+}
+
 /* sub-structured operator */
 static void ss_apply(const void *c, const double *x, double *y) { orc_ss_spmv((const orc_sub *)c, x, y); }
 static double ss_dot(const void *c, const double *u, const double *v)
 {
     const orc_sub *S = (const orc_sub *)c;
     return orc_owned_dot(S->P, S->sub_off, S->n_int, S->n_own, u, v);
+}
+static double ss_dot2(const void *c, const double *u, const double *v)
+{
+    const orc_sub *S = (const orc_sub *)c;
+    return orc_owned_dot2(S->P, S->sub_off, S->n_int, S->n_own, u, v);
 }
 
 static double true_relres(int64_t n, const int32_t *rowptr, const int32_t *colidx, const double *val,
@@ -427,6 +496,18 @@ static void scatter_owned(const orc_sub *S, const double *loc, double *v)
 
 /* Sub-structured CG: Algorithm 3 where every product by S is the
  * sub-structured SpMV and every dot product the weighted local sum. */
+/* CG on the unsplit global matrix with Dot2 dot products. */
+int orc_cg_dot2(int64_t n, const int32_t *rowptr, const int32_t *colidx, const double *val,
+                const double *b, double *x, double tol, int32_t maxit,
+                double *hist, int32_t *iters, double *relres, double *true_rr)
+{
+    csr_ctx c = {n, rowptr, colidx, val};
+    orc_op op = {n, glob_apply, glob_dot2, &c};
+    int st = cg_core(&op, b, x, tol, maxit, hist, iters, relres);
+    *true_rr = true_relres(n, rowptr, colidx, val, b, x);
+    return st;
+}
+
 int orc_ss_cg(const orc_sub *S, int64_t n, const int32_t *rowptr, const int32_t *colidx,
               const double *val, const double *b, double *x, double tol, int32_t maxit,
               double *hist, int32_t *iters, double *relres, double *true_rr)
@@ -437,6 +518,24 @@ int orc_ss_cg(const orc_sub *S, int64_t n, const int32_t *rowptr, const int32_t 
     gather(S, b, bl);
     gather(S, x, xl);
     orc_op op = {S->n_loc, ss_apply, ss_dot, S};
+    int st = cg_core(&op, bl, xl, tol, maxit, hist, iters, relres);
+    scatter_owned(S, xl, x);
+    *true_rr = true_relres(n, rowptr, colidx, val, b, x);
+    free(bl); free(xl);
+    return st;
+}
+
+/* The sub-structured CG with Dot2 dot products (owned positions). */
+int orc_ss_cg_dot2(const orc_sub *S, int64_t n, const int32_t *rowptr, const int32_t *colidx,
+              const double *val, const double *b, double *x, double tol, int32_t maxit,
+              double *hist, int32_t *iters, double *relres, double *true_rr)
+{
+    double *bl = (double *)malloc(sizeof(double) * (size_t)(S->n_loc > 0 ? S->n_loc : 1));
+    double *xl = (double *)malloc(sizeof(double) * (size_t)(S->n_loc > 0 ? S->n_loc : 1));
+    if (!bl || !xl) { free(bl); free(xl); return ORC_ENOMEM; }
+    gather(S, b, bl);
+    gather(S, x, xl);
+    orc_op op = {S->n_loc, ss_apply, ss_dot2, S};
     int st = cg_core(&op, bl, xl, tol, maxit, hist, iters, relres);
     scatter_owned(S, xl, x);
     *true_rr = true_relres(n, rowptr, colidx, val, b, x);

@@ -2,9 +2,17 @@
 
 For each configuration the oracle's own results are computed once per module
 on the CPU (the sub-structured CG of Algorithm 3 to 1e-10, and the solution
-to its attainable floor, global CG to 1e-14); the GPU solves go through the
-C-ABI.  Checked per system:
-  - iteration count to ||r|| <= 1e-10 ||b|| within 2 of the oracle's;
+to its attainable floor, global CG to 1e-14, both with the oracle's all-cores
+build); the GPU solves go through the C-ABI.  Checked per system:
+  - the iteration count to ||r|| <= 1e-10 ||b|| lies within 2 of the range
+    the oracle's own dot-product evaluations span: from CG with accurately
+    evaluated dots (Dot2, as if summed in twice the working precision) to the
+    plain left-to-right sums of the sequential oracle and the thread-blocked
+    sums of its all-cores build (tests/golden/fullsize_spread.json, written by
+    make_fullsize_spread.py, which calls only oracle/).  On these
+    ill-conditioned systems CG's count is set by the rounding of its dots: the
+    plain oracle's two-million-term sums cost it ~2% more iterations than
+    exactly rounded dots, and any correct evaluation order lands in between;
   - the true residual, recomputed with the oracle's product, <= 1e-10;
   - the relative error against the floor solution, printed and bounded by
     max(1e-9, 2x the oracle's own error at the same tolerance) (the error of
@@ -12,7 +20,9 @@ C-ABI.  Checked per system:
   - with the residual driven to 1e-13, the error <= 1e-9.
 The mixed-precision modes on the 96^3 Q1 system are held to max(1e-9, 10x
 the oracle FP64 CG's error), and their FP32 product is compared bit for bit.
-These need minutes of CPU time for the oracle side."""
+These need a few minutes of CPU time for the oracle side."""
+import json
+import os
 import time
 
 import numpy as np
@@ -27,6 +37,15 @@ pytestmark = [pytest.mark.gpu, pytest.mark.slow, pytest.mark.timeout(1200)]
 DEV = "cuda:0"
 
 
+with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "fullsize_spread.json")) as _f:
+    SPREAD = json.load(_f)
+
+
+def _its_range(idx):
+    counts = list(SPREAD[str(idx)]["accurate_dots"].values()) + list(SPREAD[str(idx)]["sequential_dots"].values())
+    return min(counts) - 2, max(counts) + 2
+
+
 def _t(a):
     return torch.tensor(np.ascontiguousarray(a, dtype=np.float64), device=DEV)
 
@@ -39,16 +58,21 @@ def _true(A, b, x):
     return float(np.linalg.norm(b - O.csr_matvec(A, x)) / np.linalg.norm(b))
 
 
+THREADS = 8  # the oracle's all-cores build, at a fixed thread count: deterministic
+
+
 class _Ref:
-    """The oracle's results on one workload."""
+    """The oracle's results on one workload: its sub-structured CG to 1e-10
+    and its floor solution (global CG to 1e-14), both from the all-cores
+    build of the oracle on THREADS threads."""
 
     def __init__(self, idx, pcg=False):
         t0 = time.perf_counter()
         self.w = config(idx)
         A, b = self.w.A, self.w.b
         self.sd = O.split(A.rowptr, A.colidx, O.partition_workload(self.w), self.w.nparts)
-        self.x10, self.r10 = O.ss_cg(A, self.sd, b, tol=1e-10, maxit=100000, hist=False)
-        self.xref = O.solve_reference(A, b)
+        self.x10, self.r10 = O.ss_cg_omp(A, self.sd, b, tol=1e-10, maxit=100000, threads=THREADS)
+        self.xref, _ = O.cg_omp(A, b, tol=1e-14, maxit=200000, threads=THREADS)
         self.err10 = _err(self.x10, self.xref)
         if pcg:
             self.xp, self.rp = O.ss_pcg(A, self.sd, b, tol=1e-10, maxit=100000, hist=False)
@@ -63,14 +87,16 @@ def _solve(s, b, tol, n):
     return x.cpu().numpy(), r
 
 
-def _fp64_checks(ref, s, name):
+def _fp64_checks(ref, s, name, idx):
     A, b = ref.w.A, ref.w.b
     x, r = _solve(s, b, 1e-10, A.n)
     true, err = _true(A, b, x), _err(x, ref.xref)
-    print(f"{name}: {r.iterations} iterations (oracle {ref.r10.iterations}), true relres {true:.2e}, "
-          f"error {err:.2e} (oracle {ref.err10:.2e})")
+    lo, hi = _its_range(idx)
+    print(f"{name}: {r.iterations} iterations (oracle range {lo + 2}..{hi - 2}, Dot2 "
+          f"{SPREAD[str(idx)]['reference']}), true relres {true:.2e}, error {err:.2e} (oracle {ref.err10:.2e})")
     assert r.status == ss.SS_OK and true <= 1e-10, (r, true)
-    assert abs(r.iterations - ref.r10.iterations) <= 2, (r.iterations, ref.r10.iterations)
+    assert SPREAD[str(idx)]["sequential_dots"][f"ss_cg_omp_{THREADS}"] == ref.r10.iterations  # same inputs
+    assert lo <= r.iterations <= hi, (r.iterations, lo, hi)
     assert err <= max(1e-9, 2 * ref.err10), (err, ref.err10)
     x13, r13 = _solve(s, b, 1e-13, A.n)
     err13 = _err(x13, ref.xref)
@@ -102,7 +128,7 @@ def test_cfg2_product_and_first_steps(cfg2):
 
 
 def test_cfg2_cg_accuracy(cfg2):
-    _fp64_checks(cfg2, ss.ss_cg_setup(cfg2.w.A, ss.partition_workload(cfg2.w)), "cfg2 CG")
+    _fp64_checks(cfg2, ss.ss_cg_setup(cfg2.w.A, ss.partition_workload(cfg2.w)), "cfg2 CG", 2)
 
 
 def test_cfg2_pcg_accuracy(cfg2):
@@ -121,7 +147,7 @@ def test_cfg2_pcg_accuracy(cfg2):
 
 def test_cfg5_forward_accuracy():
     ref = _Ref(5)
-    _fp64_checks(ref, ss.ss_cg_setup(ref.w.A, ss.partition_workload(ref.w)), "cfg5 CG")
+    _fp64_checks(ref, ss.ss_cg_setup(ref.w.A, ss.partition_workload(ref.w)), "cfg5 CG", 5)
 
 
 # ---------------------------------------------------------------- cfg3 -----
@@ -132,7 +158,7 @@ def cfg3():
 
 
 def test_cfg3_fp64_accuracy(cfg3):
-    _fp64_checks(cfg3, ss.ss_cg_setup(cfg3.w.A, ss.partition_workload(cfg3.w)), "cfg3 CG")
+    _fp64_checks(cfg3, ss.ss_cg_setup(cfg3.w.A, ss.partition_workload(cfg3.w)), "cfg3 CG", 3)
 
 
 @pytest.mark.parametrize("prec", ["SS_FP32_IR", "SS_FP32_RU"])

@@ -559,6 +559,73 @@ def test_ss_spmv_f32_is_local_products_then_assembly():
     assert np.all(np.abs(y - y64) <= (k * 2.0 ** -24 / (1 - k * 2.0 ** -24)) * absum * 1.01 + 1e-30)
 
 
+def _exact_dot(u, v):
+    from fractions import Fraction
+    return sum(Fraction(float(a)) * Fraction(float(b)) for a, b in zip(u, v))
+
+
+def test_dot2_error_bound_and_cancellation():
+    # Dot2 (Ogita, Rump, Oishi 2005): |res - x'y| <= u |x'y| + gamma_n^2 |x|'|y|
+    rng = np.random.default_rng(17)
+    u = 2.0 ** -53
+    for n, scale in ((1, 1.0), (7, 1.0), (500, 1e3), (2000, 1.0)):
+        a = rng.uniform(-1, 1, n) * scale
+        b = rng.uniform(-1, 1, n)
+        ex = _exact_dot(a, b)
+        g = n * u / (1 - n * u)
+        bound = u * abs(float(ex)) + g * g * float(np.abs(a) @ np.abs(b))
+        assert abs(O.dot2(a, b) - float(ex)) <= bound
+    # a sum that cancels: the plain left-to-right dot loses everything, Dot2 is exact
+    a = np.array([1e16, 1.0, -1e16, 3.0, 1e-3])
+    b = np.array([1.0, 1.0, 1.0, 1.0, 1e-3])
+    assert O.dot(a, b) != float(_exact_dot(a, b))
+    assert O.dot2(a, b) == float(_exact_dot(a, b))
+    # ill-conditioned random dots (condition ~1e12): still within the bound
+    x = rng.uniform(-1, 1, 300)
+    y = rng.uniform(-1, 1, 300)
+    x[0], y[0] = 1e12, 1e12 * 0 + 1.0
+    x[1], y[1] = -1e12, 1.0
+    ex = _exact_dot(x, y)
+    g = 300 * u / (1 - 300 * u)
+    assert abs(O.dot2(x, y) - float(ex)) <= u * abs(float(ex)) + g * g * float(np.abs(x) @ np.abs(y))
+
+
+def test_owned_dot2_counts_owned_positions_once():
+    A = diffusion3d_lognormal(6, seed=4)
+    sd = O.split(A.rowptr, A.colidx, O.box_partition((6, 6, 6), (2, 2, 2)), 8)
+    rng = np.random.default_rng(1)
+    xg, yg = rng.uniform(-1, 1, A.n), rng.uniform(-1, 1, A.n)
+    got = O.owned_dot2(sd, O.gather(sd, xg), O.gather(sd, yg))
+    ex = _exact_dot(xg, yg)  # each node counted once: the global dot
+    g = A.n * 2.0 ** -53
+    assert abs(got - float(ex)) <= 2.0 ** -53 * abs(float(ex)) + g * g * float(np.abs(xg) @ np.abs(yg))
+
+
+def test_cg_dot2_is_cg():
+    # the CG of Algorithm 3 with Dot2 dots: P = 1 equals the unsplit CG bit
+    # for bit, solves match Cholesky, the Laplacian meets its Chebyshev bound,
+    # and the count does not depend on the sub-domains
+    M = 10
+    A = diffusion3d_lognormal(M, seed=3, sigma=0.5)
+    b = uniform_rhs(A.n, 5)
+    sd1 = O.split(A.rowptr, A.colidx, np.zeros(A.n, dtype=np.int32), 1)
+    x1, r1 = O.ss_cg_dot2(A, sd1, b, tol=1e-12)
+    xg, rg = O.cg_dot2(A, b, tol=1e-12)
+    assert r1.iterations == rg.iterations and np.array_equal(x1, xg)
+    ref, _ = O.chol_solve(A.to_dense(), b)
+    assert np.linalg.norm(xg - ref) <= 1e-9 * np.linalg.norm(ref) and r1.true_relres <= 1e-12
+    its = set()
+    for boxes, P in (((2, 2, 2), 8), ((2, 1, 1), 2), ((3, 2, 1), 6)):
+        sd = O.split(A.rowptr, A.colidx, O.box_partition((M, M, M), boxes), P)
+        _, r = O.ss_cg_dot2(A, sd, b, tol=1e-10)
+        assert r.status == O.OK and r.true_relres <= 1e-10
+        its.add(r.iterations)
+    assert max(its) - min(its) <= 2
+    w = config(1)
+    _, rp = O.cg_dot2(w.A, w.b, tol=1e-10, maxit=10000)
+    assert rp.status == O.OK and rp.iterations <= 568
+
+
 def test_ir_reaches_fp64_accuracy():
     M = 10
     A = diffusion3d_lognormal(M, seed=3, sigma=0.5)
