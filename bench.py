@@ -42,6 +42,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -118,26 +120,82 @@ def host_cpu() -> dict:
     return {"model": model, "cores_available": avail}
 
 
-def cpu_baseline(w, iters_gpu: int, sample_iters: int) -> dict:
-    import numpy as np
+def cpu_threads() -> int:
+    try:
+        return len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        return os.cpu_count() or 1
 
+
+def cpu_baseline(w, sd, tol: float, iters_gpu: int) -> dict:
+    """The oracle's sub-structured CG timed to the tolerance on the host: the
+    sequential oracle as it stands (one thread), then its all-cores OpenMP
+    build (the same CG with a static row partition and thread-ordered
+    partial dots) on every core this process may use."""
     import oracle as O
 
-    part = O.partition_workload(w)
-    sd = O.split(w.A.rowptr, w.A.colidx, part, w.nparts)
     t0 = time.perf_counter()
-    _, res = O.ss_cg(w.A, sd, w.b, tol=0.0, maxit=sample_iters, hist=False)
-    dt = time.perf_counter() - t0
-    per_iter = dt / max(res.iterations, 1)
+    _, r1 = O.ss_cg(w.A, sd, w.b, tol=tol, maxit=100000, hist=False)
+    t1 = time.perf_counter() - t0
+    nt = cpu_threads()
+    t0 = time.perf_counter()
+    _, rn = O.ss_cg_omp(w.A, sd, w.b, tol=tol, maxit=100000, threads=nt)
+    tn = time.perf_counter() - t0
+    print(f"# cpu baseline: 1 thread {t1 * 1e3:.0f} ms ({r1.iterations} iterations), {nt} threads "
+          f"{tn * 1e3:.0f} ms ({rn.iterations} iterations)", file=sys.stderr, flush=True)
     return {
-        "value": round(per_iter * iters_gpu * 1e3, 3),
+        "value": round(t1 * 1e3, 3),
         "unit": "ms",
         "cores": 1,
-        "host": host_cpu(),
         "kind": "oracle",
-        "sample": (f"sequential FP64 oracle, sub-structured CG on the same system: first {res.iterations} iterations "
-                   f"timed ({dt:.2f} s, {per_iter * 1e3:.2f} ms/iteration), scaled to the GPU's {iters_gpu} iterations"),
+        "sample": (f"the whole solve to relative residual {tol:g} on the bench system (measured, not scaled): "
+                   f"sequential FP64 oracle, sub-structured CG, {r1.iterations} iterations "
+                   f"({t1 * 1e3 / max(r1.iterations, 1):.2f} ms/iteration; GPU {iters_gpu} iterations)"),
+        "status": r1.status,
+        "iterations": r1.iterations,
+        "true_relres": r1.true_relres,
+        "all_cores": {"ms": round(tn * 1e3, 3), "threads": nt, "iterations": rn.iterations,
+                      "status": rn.status, "ms_per_iteration": round(tn * 1e3 / max(rn.iterations, 1), 4),
+                      "build": "OpenMP, static row partition, per-thread partial dots added in thread order"},
+        "host": host_cpu(),
     }
+
+
+def floor_solution(A, b):
+    """The oracle's solution at its attainable floor (global CG to 1e-14 on
+    all host cores), the reference of the error figures."""
+    import oracle as O
+
+    x, r = O.cg_omp(A, b, tol=1e-14, maxit=200000, threads=cpu_threads())
+    return x, r
+
+
+_REFS: dict = {}
+_ERRORS = {"on": True}
+
+
+def reference_for(w):
+    """Floor solution of workload w (cached by name); None when error figures are off."""
+    if not _ERRORS["on"]:
+        return None
+    if w.name not in _REFS:
+        t0 = time.perf_counter()
+        x, r = floor_solution(w.A, w.b)
+        print(f"# oracle floor solution {w.name}: {r.iterations} iterations, true relres {r.true_relres:.1e} "
+              f"({time.perf_counter() - t0:.1f} s)", file=sys.stderr, flush=True)
+        _REFS[w.name] = x
+    return _REFS[w.name]
+
+
+def error_vs_oracle(w, x_dev):
+    ref = reference_for(w)
+    return None if ref is None else rel_err(x_dev.cpu().numpy(), ref)
+
+
+def rel_err(x, ref) -> float:
+    import numpy as np
+
+    return float(np.linalg.norm(np.asarray(x) - ref) / np.linalg.norm(ref))
 
 
 def _timed(torch, fn, reps: int):
@@ -180,6 +238,7 @@ def variant_mixed(ss, torch, reps: int, tol: float) -> dict:
         if prec == ss.SS_FP32_RU:
             out[name]["residual_replacements"] = out[name].pop("outer_iterations")
         xs[name] = x.clone()
+        out[name]["error_vs_oracle"] = error_vs_oracle(w, x)
         print(f"# mixed/{name}: {ms:.3f} ms, {r.iterations} iterations ({r.outer_iterations} outer), "
               f"true relres {true:.2e}", file=sys.stderr, flush=True)
     for v in ("fp32_ir", "fp32_ru"):
@@ -227,6 +286,23 @@ def variant_batched(ss, torch, reps: int, tol: float, one_by_one: bool = True) -
     nbytes = sum(int(k) * (12 * A.nnz + A.n + 72 * nrhs * A.n) for k, A in zip(per_sys_its, S))
     out["algorithmic_bytes"] = nbytes
     out["effective_gbps"] = round(nbytes / (ms_b * 1e-3) / 1e9, 1)
+    if _ERRORS["on"]:
+        # error against the oracle's floor solution for a sample of pairs: the
+        # smallest and the largest system, and six seeded random ones
+        import oracle as O
+
+        sizes = np.array([A.n for A in S])
+        pick = sorted({int(np.argmin(sizes)), int(np.argmax(sizes)),
+                       *np.random.default_rng(4).choice(len(S), 6, replace=False).tolist()})
+        xh = x.cpu().numpy()
+        offs = np.concatenate([[0], np.cumsum(sizes)])
+        errs = []
+        for si in pick:
+            j = si % nrhs
+            xr, _ = O.cg_omp(S[si], np.ascontiguousarray(B[si][:, j]), tol=1e-14, maxit=200000,
+                             threads=cpu_threads())
+            errs.append(rel_err(xh[offs[si] * nrhs + j: offs[si + 1] * nrhs: nrhs], xr))
+        out["error_vs_oracle_sampled"] = {"max": max(errs), "pairs": [[int(si), int(si % nrhs)] for si in pick]}
     if not one_by_one:
         return out
     # one by one: one solver per system (set up outside the timing), every pair solved separately
@@ -268,7 +344,8 @@ def variant_jacobi(ss, torch, reps: int, tol: float) -> dict:
 
         ms, r = _timed(torch, run, reps)
         out[name] = {"ms": round(ms, 3), "status": r.status, "iterations": r.iterations, "relres": r.relres,
-                     "ms_per_iteration": round(ms / max(r.iterations, 1), 5)}
+                     "ms_per_iteration": round(ms / max(r.iterations, 1), 5),
+                     "error_vs_oracle": error_vs_oracle(w, x)}
         print(f"# jacobi/{name}: {ms:.3f} ms, {r.iterations} iterations", file=sys.stderr, flush=True)
         del s
     out["speedup_pcg_over_cg"] = round(out["cg"]["ms"] / out["pcg_jacobi"]["ms"], 3)
@@ -333,7 +410,8 @@ def variant_splittings(ss, torch, reps: int, tol: float) -> dict:
         out[name] = {"ms": round(ms, 3), "status": r.status, "iterations": r.iterations,
                      "true_relres": r.true_relres, "ms_per_iteration": round(ms / max(r.iterations, 1), 5),
                      "step_spmv_us": round(spmv_ms * 1e3, 2),
-                     "step_spmv_gbps": round(spmv_bytes / (spmv_ms * 1e-3) / 1e9, 1)}
+                     "step_spmv_gbps": round(spmv_bytes / (spmv_ms * 1e-3) / 1e9, 1),
+                     "error_vs_oracle": error_vs_oracle(w, x)}
         print(f"# splittings/{name}: {ms:.3f} ms, {r.iterations} iterations", file=sys.stderr, flush=True)
         del s
     out["exchange_values_per_product"] = exchange_volumes(ss, w.A, part, 8)
@@ -365,11 +443,96 @@ def variant_adjoint(ss, torch, reps: int, tol: float) -> dict:
         loss.backward()
         return vals.grad
 
-    ms_f, _ = _timed(torch, fwd, reps)
+    ms_f, xf = _timed(torch, fwd, reps)
     ms_fb, _ = _timed(torch, fwd_bwd, reps)
     print(f"# adjoint: forward {ms_f:.3f} ms, forward+backward {ms_fb:.3f} ms", file=sys.stderr, flush=True)
     return {"workload": w.name, "forward_ms": round(ms_f, 3), "forward_backward_ms": round(ms_fb, 3),
-            "backward_over_forward": round((ms_fb - ms_f) / ms_f, 3)}
+            "backward_over_forward": round((ms_fb - ms_f) / ms_f, 3),
+            "forward_error_vs_oracle": error_vs_oracle(w, xf)}
+
+
+def _solve_line(ss, torch, w, reps: int, tol: float, opts=None) -> dict:
+    """Time to tol of one workload (inputs resident), with its iteration
+    count, time per iteration, the kernels an iteration launches and the
+    error against the oracle's floor solution."""
+    A = w.A
+    part = ss.partition_workload(w)
+    s = ss.ss_cg_setup(A, part, opts)
+    b = torch.tensor(w.b, dtype=torch.float64, device="cuda")
+    x = torch.zeros_like(b)
+
+    def run():
+        x.zero_()
+        return ss.ss_cg_solve(s, b, x, tol=tol, maxit=100000)
+
+    ms, r = _timed(torch, run, reps)
+    bn = float(torch.linalg.norm(b))
+    true = float(torch.linalg.norm(b - ss.ss_cg_apply(s, x))) / bn
+    longest = int(np.max(np.diff(A.rowptr))) if A.n else 0
+    info = s.info()
+    out = {"workload": w.name, "n": int(A.n), "nnz": int(A.nnz), "n_loc": int(info["n_loc"]),
+           "ms": round(ms, 3), "status": r.status, "iterations": r.iterations, "true_relres": true,
+           "us_per_iteration": round(ms * 1e3 / max(r.iterations, 1), 2)}
+    if s.path() == ss.SS_PATH_SMALL:
+        out["path"] = "one launch per solve (one workgroup runs every iteration)"
+        out["kernel_launches_per_solve"] = 4   # gather b, gather x, the solve, scatter x
+    else:
+        out["path"] = "streaming kernels, graph chunks of 32 iterations"
+        out["kernels_per_iteration"] = (2 if (info["matrix_format"] == ss.SS_MAT_SELL and longest <= 9) else
+                                        (3 if info["matrix_format"] == ss.SS_MAT_SELL else 2))
+    out["error_vs_oracle"] = error_vs_oracle(w, x)
+    print(f"# {w.name}: {ms:.3f} ms, {r.iterations} iterations, {out['us_per_iteration']} us/iteration",
+          file=sys.stderr, flush=True)
+    del s
+    return out
+
+
+def variant_configs(ss, torch, reps: int, tol: float) -> dict:
+    """Time to tol of the two workloads not timed elsewhere: the 64 x 64
+    Poisson system in 2 x 2 boxes (latency bound: 4096 unknowns) and the 64^3
+    smoothed-GRF diffusion in 2 x 2 x 2 boxes."""
+    from workloads import config
+
+    w1 = config(1)
+    return {"poisson2d_64": _solve_line(ss, torch, w1, max(reps, 10), tol),
+            "poisson2d_64_streaming": _solve_line(ss, torch, w1, max(reps, 10), tol,
+                                                  ss.default_opts(small_solver=ss.SS_SMALL_OFF)),
+            "diffusion3d_grf_64": _solve_line(ss, torch, config(5), reps, tol)}
+
+
+def variant_beyond_mall(ss, torch, reps: int, tol: float) -> dict:
+    """The main line's recipe on a 192^3 grid (7.2M unknowns, 51.4M stored
+    entries, a ~900 MB working set: several times the 256 MB last-level
+    cache), so that the CG step streams from HBM: time to tol and the CG-step
+    roofline point."""
+    from workloads import config
+
+    w = config(2, size=192)
+    A = w.A
+    s = ss.ss_cg_setup(A, ss.partition_workload(w))
+    b = torch.tensor(w.b, dtype=torch.float64, device="cuda")
+    x = torch.zeros_like(b)
+
+    def run():
+        x.zero_()
+        return ss.ss_cg_solve(s, b, x, tol=tol, maxit=100000)
+
+    ms, r = _timed(torch, run, reps)
+    true = float(torch.linalg.norm(b - ss.ss_cg_apply(s, x))) / float(torch.linalg.norm(b))
+    spmv_ms, spmv_bytes = ss.ss_cg_time_spmv(s, 20)
+    n_loc = s.info()["n_loc"]
+    survey_bytes = 12.0 * A.nnz + 20.0 * n_loc
+    out = {"workload": w.name, "n": int(A.n), "nnz": int(A.nnz), "n_loc": int(n_loc), "ms": round(ms, 3),
+           "status": r.status, "iterations": r.iterations, "true_relres": true,
+           "us_per_iteration": round(ms * 1e3 / max(r.iterations, 1), 2),
+           "step_spmv_us": round(spmv_ms * 1e3, 2), "step_algorithmic_bytes": int(spmv_bytes),
+           "step_gbps": round(spmv_bytes / (spmv_ms * 1e-3) / 1e9, 1),
+           "frac": round(spmv_bytes / (spmv_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+           "frac_spmv_only": round(survey_bytes / (spmv_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+    print(f"# beyond MALL {w.name}: {ms:.3f} ms, {r.iterations} iterations, step {spmv_ms * 1e3:.1f} us "
+          f"({out['frac']:.3f} of 8 TB/s)", file=sys.stderr, flush=True)
+    del s
+    return out
 
 
 def main_measurement(args, ss, torch, config):
@@ -408,6 +571,7 @@ def main_measurement(args, ss, torch, config):
     per_step = sorted((b_ - a_) * 1e3 for a_, b_ in zip(marks, marks[1:]))
     ms_median = per_step[len(per_step) // 2] if per_step else ms_step
     r = results[-1] if results else ss.ss_cg_solve(solver, b, x, tol=args.tol, maxit=100000)
+    x_solved = x.clone()
     if any(q.status != ss.SS_OK for q in results):
         print(f"bench.py: solve did not converge: {[q.status for q in results]}", file=sys.stderr)
         return None
@@ -436,6 +600,9 @@ def main_measurement(args, ss, torch, config):
     achieved = spmv_bytes / (spmv_ms * 1e-3) / 1e9
     traffic = load_traffic(w.name)
     n_loc = info["n_loc"]
+    # the survey's SpMV-only count: 8 B value + 4 B column per stored entry,
+    # 4 B row pointer per row, x read and y written (8 B each) per row
+    survey_bytes = 12.0 * A.nnz + 4.0 * n_loc + 16.0 * n_loc
     iter_bytes = spmv_bytes + 24.0 * n_loc  # + update kernel: r, q read; r written
     ms_iter = ms_step / max(r.iterations, 1)
 
@@ -478,11 +645,24 @@ def main_measurement(args, ss, torch, config):
             "traffic_gbps": round(traffic / (spmv_ms * 1e-3) / 1e9, 1) if traffic else None,
             "launch_ms": round(spmv_ms, 5),
             "algorithmic_bytes": int(spmv_bytes),
+            "traffic_what": ("L2-miss bytes (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy), served by the "
+                             "last-level cache (MALL) or HBM: at this size most of the working set fits the "
+                             "256 MB MALL"),
+            "frac_spmv_only": round(survey_bytes / (spmv_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "spmv_only_bytes": int(survey_bytes),
+            "spmv_only_what": "12 B per stored entry + 4 B row pointer + 16 B (x read, y written) per row",
             "stream_copy_gbps": round(stream_copy_gbps(torch), 1),
         },
     }
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(w, r.iterations, args.cpu_iters)
+        import oracle as O
+
+        sd = O.split(A.rowptr, A.colidx, O.partition_workload(w), w.nparts)
+        out["cpu_baseline"] = cpu_baseline(w, sd, args.tol, r.iterations)
+        del sd
+        out["error_vs_oracle"] = error_vs_oracle(w, x_solved)
+        out["error_what"] = ("||x - x_ref|| / ||x_ref||, x_ref = the oracle's global CG run to 1e-14 "
+                             "(its attainable floor) on all host cores")
     return out
 
 
@@ -493,10 +673,11 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--config", type=int, default=2, choices=[1, 2, 5])
     ap.add_argument("--tol", type=float, default=1e-10)
-    ap.add_argument("--cpu-iters", type=int, default=150)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--variants", default="mixed,batched,adjoint,jacobi,splittings",
-                    help="comma list of mixed, batched, adjoint, jacobi, splittings; 'none' to skip")
+    ap.add_argument("--no-cpu-baseline", action="store_true",
+                    help="skip the CPU oracle legs (timed solves and the floor solutions of the error figures)")
+    ap.add_argument("--variants", default="configs,beyond_mall,mixed,batched,adjoint,jacobi,splittings",
+                    help="comma list of configs, beyond_mall, mixed, batched, adjoint, jacobi, splittings; "
+                         "'none' to skip")
     ap.add_argument("--variant-steps", type=int, default=3)
     ap.add_argument("--no-main", action="store_true",
                     help="profiling aid: skip the main measurement, print only the variants")
@@ -517,6 +698,7 @@ def main() -> int:
     import paper_2108_13162_amd as ss
     from workloads import config
 
+    _ERRORS["on"] = not args.no_cpu_baseline
     if args.copy_calibration:
         calibrate_copy(torch)
     out = {} if args.no_main else main_measurement(args, ss, torch, config)
@@ -524,7 +706,7 @@ def main() -> int:
         return 1
     chosen = [v for v in args.variants.split(",") if v and v != "none"]
     funcs = {"mixed": variant_mixed, "batched": variant_batched, "adjoint": variant_adjoint, "jacobi": variant_jacobi,
-             "splittings": variant_splittings}
+             "splittings": variant_splittings, "configs": variant_configs, "beyond_mall": variant_beyond_mall}
     if chosen:
         out["variants"] = {}
         for v in chosen:

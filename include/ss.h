@@ -157,6 +157,16 @@ enum {
                              SS_FP64 only                                        */
 };
 
+/* Solve of a small system in one launch (SS_FP64, M = I): one workgroup
+ * runs every CG iteration, with the matrix in registers and p in LDS, instead
+ * of two launches per iteration.  Used for systems whose local rows hold at
+ * most 7 entries and number at most 5120 (rows of at most 5 entries) or 3072
+ * (at most 7).  Same method, stopping rule and outputs as the general path. */
+enum {
+    SS_SMALL_AUTO = 0, /* use it when the system qualifies (default) */
+    SS_SMALL_OFF = 1   /* always the general path                    */
+};
+
 /* Device storage of the block-diagonal matrix of all local matrices. */
 enum {
     SS_MAT_AUTO = 0, /* SELL-64 unless rows are too uneven, else CSR row tiles */
@@ -186,6 +196,7 @@ typedef struct {
     ss_alloc_fn alloc;   /* device allocator; NULL = hipMalloc                 */
     ss_free_fn free;     /* matching release; NULL = hipFree                   */
     void *alloc_ctx;
+    int32_t small_solver; /* SS_SMALL_*                                        */
 } ss_opts;
 
 /* Fills *o with the defaults. */
@@ -203,8 +214,8 @@ typedef struct {
 /*
  * ss_cg_setup -- uploads the local matrices, maps and work vectors of
  * partition p of A to the current HIP device and prepares the kernels.
- * A must be the matrix p was built from (same n and nnz; values may differ,
- * the pattern may not).  hip_stream is a hipStream_t (NULL = default
+ * A must be the matrix p was built from (same n, nnz and pattern -- checked:
+ * SS_EINVAL otherwise; the values may differ).  hip_stream is a hipStream_t (NULL = default
  * stream).  o may be NULL (defaults).  Device memory comes from o->alloc
  * when given.  *out is released with ss_cg_destroy.
  * Errors: SS_EINVAL (A does not match p, bad options), SS_ENOMEM,
@@ -263,7 +274,10 @@ int ss_cg_apply_f32(ss_solver *s, const float *x_dev, float *y_dev);
 
 /* Replaces the matrix values (same pattern): val_dev[nnz], device, global
  * stored-entry order.  The values must keep A symmetric positive-definite;
- * symmetry is not re-checked. */
+ * symmetry is not re-checked.  Every copy the solver keeps follows: the FP64
+ * and FP32 values, the one-launch solve's values and, with
+ * SS_PRECOND_JACOBI, the inverse diagonal (a non-positive diagonal then ends
+ * the next solve with SS_EBREAKDOWN or a non-finite scalar). */
 int ss_cg_set_values(ss_solver *s, const double *val_dev);
 
 /* Adjoint gradient on the stored pattern: with x = A^{-1} b and
@@ -289,6 +303,12 @@ int ss_cg_time_spmv(ss_solver *s, int32_t reps, double *ms_per_launch, double *b
  * (SELL: including the chunk padding). */
 int ss_cg_info(const ss_solver *s, int32_t *n, int32_t *n_loc, int64_t *nnz, int32_t *matrix_format,
                int64_t *stored);
+
+/* How ss_cg_solve runs on this solver: SS_PATH_STREAM, two streaming
+ * launches per CG iteration replayed in graph chunks; SS_PATH_SMALL, the
+ * whole solve in one launch (see SS_SMALL_AUTO). */
+enum { SS_PATH_STREAM = 0, SS_PATH_SMALL = 1 };
+int ss_cg_path(const ss_solver *s, int32_t *path);
 
 void ss_cg_destroy(ss_solver *s);
 

@@ -29,6 +29,8 @@ SS_BAND_ROW, SS_BAND_COL = 0, 1
 SS_FP64, SS_FP32_IR, SS_FP32_RU = 0, 1, 2
 SS_MAT_AUTO, SS_MAT_SELL, SS_MAT_CSR = 0, 1, 2
 SS_PRECOND_NONE, SS_PRECOND_JACOBI = 0, 1
+SS_SMALL_AUTO, SS_SMALL_OFF = 0, 1
+SS_PATH_STREAM, SS_PATH_SMALL = 0, 1
 
 _ALLOC_T = C.CFUNCTYPE(C.c_void_p, C.c_void_p, C.c_size_t)
 _FREE_T = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
@@ -46,7 +48,7 @@ class ss_opts(C.Structure):
                 ("tile_nnz", C.c_int32), ("matrix_format", C.c_int32), ("spmv_grid", C.c_int32),
                 ("precond", C.c_int32),
                 ("alloc", _ALLOC_T), ("free", _FREE_T),
-                ("alloc_ctx", C.c_void_p)]
+                ("alloc_ctx", C.c_void_p), ("small_solver", C.c_int32)]
 
 
 class ss_result(C.Structure):
@@ -96,6 +98,7 @@ def lib() -> C.CDLL:
         "ss_cg_grad_vals": (C.c_int, [P, P, P, P]),
         "ss_cg_time_spmv": (C.c_int, [P, i32, P, P]),
         "ss_cg_info": (C.c_int, [P, P, P, P, P, P]),
+        "ss_cg_path": (C.c_int, [P, P]),
         "ss_cg_destroy": (None, [P]),
         "ss_band_size": (C.c_int, [P, i32, i32, i32, P, P, P]),
         "ss_band_extract": (C.c_int, [P, i32, i32, i32, P, P, P]),
@@ -300,6 +303,12 @@ class Solver:
     def close(self):
         self.__del__()
 
+    def path(self) -> int:
+        """SS_PATH_STREAM or SS_PATH_SMALL (the whole solve in one launch)."""
+        v = C.c_int32()
+        _check(lib().ss_cg_path(self.h, C.byref(v)), "ss_cg_path")
+        return v.value
+
     def info(self) -> dict:
         v = [C.c_int32(), C.c_int32(), C.c_int64(), C.c_int32(), C.c_int64()]
         _check(lib().ss_cg_info(self.h, *[C.byref(t) for t in v]), "ss_cg_info")
@@ -447,6 +456,12 @@ class Batch:
 
     def close(self):
         self.__del__()
+
+    def path(self) -> int:
+        """SS_PATH_STREAM or SS_PATH_SMALL (the whole solve in one launch)."""
+        v = C.c_int32()
+        _check(lib().ss_cg_path(self.h, C.byref(v)), "ss_cg_path")
+        return v.value
 
     def info(self) -> dict:
         v = [C.c_int32(), C.c_int32(), C.c_int64(), C.c_int64(), C.c_int64()]

@@ -20,6 +20,21 @@ __device__ __forceinline__ int xcd_remap(int b, int grid)
     return (b % kNumXcd) * per + b / kNumXcd;
 }
 
+// Immediate of s_waitcnt in the gfx9-family layout that gfx950 uses:
+// vmcnt in bits 3:0 (low part) and 15:14 (high part), expcnt in bits 6:4,
+// lgkmcnt in bits 11:8.  A counter at its field maximum is not waited for.
+constexpr unsigned waitcnt_imm(unsigned vmcnt, unsigned expcnt, unsigned lgkmcnt)
+{
+    return (vmcnt & 0xFu) | ((expcnt & 0x7u) << 4) | ((lgkmcnt & 0xFu) << 8) | (((vmcnt >> 4) & 0x3u) << 14);
+}
+// Wait until no vector memory operation (load or store) of the wave is
+// outstanding; LDS, scalar and export counters are left alone.
+constexpr unsigned kWaitVmcnt0 = waitcnt_imm(0, 7, 15);
+static_assert(kWaitVmcnt0 == 0x0F70u, "s_waitcnt vmcnt(0) expcnt(7) lgkmcnt(15) on gfx9");
+static_assert((kWaitVmcnt0 & 0xC00Fu) == 0, "both vmcnt fields are zero");
+static_assert(((kWaitVmcnt0 >> 4) & 0x7u) == 7 && ((kWaitVmcnt0 >> 8) & 0xFu) == 15,
+              "expcnt and lgkmcnt at their maxima");
+
 __device__ __forceinline__ int32_t flag_load(const int32_t *p)
 {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);

@@ -5,6 +5,8 @@
 
 #include <cstdint>
 
+#include "launch_shape.h"
+
 namespace ss {
 
 // Status of the device-resident CG run.
@@ -42,16 +44,9 @@ struct DevState {
     double delta;      // replace once sqrt(rr) <= delta * rref
     int32_t refresh;   // decision of the current chunk end
     int32_t nrefresh;  // replacements made
+    int32_t restarts;  // residual recomputations that restarted CG (one-launch solve)
 };
 
-constexpr int kBS = 256;    // workgroup size of every kernel
-constexpr int kUI = 2;      // positions per thread per batch in the update / residual kernels
-constexpr int kNumXcd = 8;  // MI355X: workgroups are dealt round-robin to 8 XCDs
-
-// Grid size for `work` items remapped so that each XCD gets a contiguous range.
-inline int xcd_grid(int work) { return ((work + kNumXcd - 1) / kNumXcd) * kNumXcd; }
-
-enum { FMT_SELL = 0, FMT_CSR = 1 };
 
 // The block-diagonal matrix of all local matrices in device position order.
 //  SELL-64: rows in chunks of 64 consecutive positions (one row per lane of a
@@ -197,11 +192,46 @@ void launch_ru_refresh(hipStream_t s, const Iface &I, const Mat &A64, double *x6
 template <typename XT>
 void launch_ru_fold(hipStream_t s, int32_t n_loc, double *x64, XT *d, const DevState *inner, DevState *outer);
 
+// ---- one-launch solve of a small system (small.hip) --------------------------
+// One workgroup of kSmallThreads threads runs the whole CG (M = I, FP64):
+// each thread owns `rows` rows (t, t + kSmallThreads, ...) of the
+// block-diagonal matrix, their `width` (5 or 7) value slots and column
+// positions held in registers; x, r, p, the interface products and the
+// interface copy lists live in LDS.
+constexpr int kSmallThreads = 512;
+
+struct SmallMat {
+    int32_t n_loc;
+    int32_t n_copies;      // entries of the interface copy lists
+    int32_t rows, width;   // rows per thread (see small_rows), value slots per row
+    const double *val;     // [width][n_loc] slot-major, device position order, 0 past a row's length
+    const uint32_t *colw;  // [(width+1)/2][n_loc] two 16-bit column positions per word (padding: the
+                           // row itself); the upper half of the last word holds the row's length
+};
+
+inline size_t small_lds_bytes(int32_t n_loc, int32_t n_if, int32_t ngamma, int32_t n_copies)
+{
+    return sizeof(double) * (3 * (size_t)n_loc + (size_t)n_if + 2 * (kSmallThreads / 64)) +
+           sizeof(int32_t) * ((size_t)n_if + (size_t)ngamma + 1 + (size_t)n_copies);
+}
+// Rows per thread of the kernel for `rows_needed` rows of `width` slots, 0
+// if none is built: width 5 up to 9 rows per thread (4608 positions), width
+// 7 up to 7 (3584).
+int32_t small_rows(int32_t rows_needed, int32_t width);
+// The solve from the gathered b and x0 (x updated in place) to the final
+// status, iteration count, (r, r), (b, b) and restart count in `state`
+// (whose tol, kmax, hist and hist_cap the host set).
+void launch_cg_small(hipStream_t s, const SmallMat &M, const Iface &I, const double *b, double *x,
+                     DevState *state);
+
 // Adjoint gradient on the pattern: dvals[nzmap[k]] = -lambda[row] x[col] for
 // every stored (non-padding) entry k of A in device order.
 void launch_grad_vals(hipStream_t s, const Mat &A, const int32_t *nzmap, const int32_t *l2g, const double *lambda,
                       const double *x, double *dvals);
-// val64[k] = val_glob[nzmap[k]] (0 for padding, nzmap < 0), val32 its FP32 rounding.
+// dinv[c] = 1 / val_glob[dnz[c]] (the Jacobi preconditioner from new values).
+void launch_set_dinv(hipStream_t s, int32_t n_loc, const int32_t *dnz, const double *val_glob, double *dinv);
+// val64[k] = val_glob[nzmap[k]] (0 for padding, nzmap < 0), val32 its FP32 rounding
+// (val32 may be nullptr).
 void launch_set_values(hipStream_t s, int64_t len, const int32_t *nzmap, const double *val_glob, double *val64,
                        float *val32);
 

@@ -408,7 +408,7 @@ __global__ __launch_bounds__(kBS) __attribute__((amdgpu_waves_per_eu(1, 4))) voi
             // drain the previous chunk's stores (and this chunk's loads, needed
             // now): with stores outstanding the compiler can only wait for the
             // gathers below by draining everything
-            __builtin_amdgcn_s_waitcnt(0x0f70);
+            __builtin_amdgcn_s_waitcnt(dev::kWaitVmcnt0);
             // a dictionary chunk of at most 7 slots: the row length is the top
             // 4 bits of the index word
             if constexpr (DICT && U < 8) len = (int)(dw >> 28);
@@ -1221,6 +1221,14 @@ __global__ __launch_bounds__(kBS) void k_set_values(int64_t len, const int32_t *
     if (v32) v32[e] = (float)v;
 }
 
+// dinv[c] = 1 / a_ii of the node held at position c, a_ii = val_glob[dnz[c]]
+__global__ __launch_bounds__(kBS) void k_set_dinv(int32_t n_loc, const int32_t *__restrict__ dnz,
+                                                  const double *__restrict__ val_glob, double *__restrict__ dinv)
+{
+    const int c = blockIdx.x * kBS + threadIdx.x;
+    if (c < n_loc) dinv[c] = 1.0 / val_glob[dnz[c]];
+}
+
 inline int nblocks(int64_t n) { return (int)((n + kBS - 1) / kBS); }
 inline int nblocks(int64_t n, int per) { return (int)((n + per - 1) / per); }
 
@@ -1398,6 +1406,11 @@ void launch_grad_vals(hipStream_t s, const Mat &A, const int32_t *nzmap, const i
     const int64_t threads = A.fmt == FMT_SELL ? (int64_t)A.nchunks * 64 : A.nrows;
     if (threads > 0)
         hipLaunchKernelGGL(k_grad_vals, dim3(nblocks(threads)), dim3(kBS), 0, s, A, nzmap, l2g, lambda, x, dvals);
+}
+
+void launch_set_dinv(hipStream_t s, int32_t n_loc, const int32_t *dnz, const double *val_glob, double *dinv)
+{
+    if (n_loc > 0) hipLaunchKernelGGL(k_set_dinv, dim3(nblocks(n_loc)), dim3(kBS), 0, s, n_loc, dnz, val_glob, dinv);
 }
 
 void launch_set_values(hipStream_t s, int64_t len, const int32_t *nzmap, const double *val_glob, double *val64,

@@ -1,0 +1,300 @@
+// The whole CG solve of a small system in one launch of one workgroup.
+//
+// For a few thousand unknowns (the 64 x 64 Poisson system of the paper's
+// smallest class) an iteration moves well under a megabyte, and the two
+// launches per iteration of the streaming kernels cost more than their work.
+// Here one workgroup of 512 threads (two waves per SIMD, 256 registers a
+// thread) runs Algorithm 3 (M = I) from the first
+// residual to the converged, recomputed one:
+//   - every thread owns up to R rows of the block-diagonal matrix of all
+//     sub-domains (rows t, t + 512, ...), whose values and column positions
+//     stay in its registers for the whole solve;
+//   - x, r and p live in LDS (up to 160 KB a workgroup on gfx950); the local
+//     products gather p there;
+//   - the interface positions publish their unassembled product in LDS too
+//     (their copy lists are copied there at the start), and every copy
+//     of an interface node adds all copies in ascending sub-domain order
+//     (Algorithms 4 and 5 on one address space);
+//   - (p, A p) is the unassembled sum over all local rows, (r, r) the sum
+//     over the owned positions (the 0/1 weights of Section 4.4.2), each a
+//     fixed-order workgroup sum;
+//   - the stopping rule, the residual recomputation at convergence with the
+//     restart it may trigger, the iteration limit and the breakdown tests are
+//     those of the streaming path; the scalars go to the run's DevState.
+// Row sums are formed in stored column order with separately rounded
+// products and sums, so the products are bitwise those of the other kernels.
+#include "kernels.h"
+
+#include "device_common.h"
+
+#include <cmath>
+
+namespace ss {
+namespace {
+
+constexpr int kSW = kSmallThreads / 64;  // waves of the workgroup
+
+// Fixed-order workgroup sum, every thread gets the total.  Two alternating
+// slot sets: a set is rewritten two sums later, after a barrier that every
+// reader of its previous values has passed.
+__device__ __forceinline__ double small_sum(double v, double *ws, int &set)
+{
+    v = dev::wave_sum(v);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    double *slot = ws + set * kSW;
+    if (lane == 0) slot[w] = v;
+    __syncthreads();
+    double t = 0.0;
+#pragma unroll
+    for (int i = 0; i < kSW; ++i) t = t + slot[i];
+    set ^= 1;
+    return t;
+}
+
+template <int R, int U>
+__global__ __launch_bounds__(kSmallThreads) void k_cg_small(int32_t n_loc, int32_t n_own, int32_t n_if,
+                                                            int32_t ngamma, int32_t n_copies,
+                                                            const double *__restrict__ sval,
+                                                            const uint32_t *__restrict__ scol,
+                                                            const int32_t *__restrict__ pos_grp,
+                                                            const int32_t *__restrict__ copy_ptr,
+                                                            const int32_t *__restrict__ copy_pos,
+                                                            const double *__restrict__ b, double *__restrict__ x,
+                                                            DevState *__restrict__ st)
+{
+    constexpr int UW = (U + 1) / 2;  // column words per row: two 16-bit positions each
+    extern __shared__ double smem[];
+    double *pl = smem;              // p (or x while a residual is formed), n_loc
+    double *xl = pl + n_loc;        // x, n_loc
+    double *rl = xl + n_loc;        // r, n_loc
+    double *qif = rl + n_loc;       // unassembled products of the interface positions, n_if
+    double *ws = qif + n_if;        // 2 * kSW sum slots
+    // the interface copy lists, read from LDS inside the iterations
+    int32_t *grp_l = reinterpret_cast<int32_t *>(ws + 2 * kSW);  // pos_grp, n_if
+    int32_t *cptr_l = grp_l + n_if;                                // copy_ptr, ngamma + 1
+    int32_t *cpos_l = cptr_l + ngamma + 1;                         // copy_pos, n_copies
+    const int t = threadIdx.x;
+    int set = 0;
+    for (int i = t; i < n_if; i += kSmallThreads) grp_l[i] = pos_grp[i];
+    for (int i = t; i <= ngamma; i += kSmallThreads) cptr_l[i] = copy_ptr[i];
+    for (int i = t; i < n_copies; i += kSmallThreads) cpos_l[i] = copy_pos[i];
+
+    double val[R][U];
+    uint32_t cw[R][UW];
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+        const int i = t + k * kSmallThreads;
+        const bool in = i < n_loc;
+#pragma unroll
+        for (int u = 0; u < U; ++u) val[k][u] = in ? sval[(size_t)u * n_loc + i] : 0.0;
+#pragma unroll
+        for (int w = 0; w < UW; ++w) cw[k][w] = in ? scol[(size_t)w * n_loc + i] : 0u;
+        if (in) xl[i] = x[i];
+    }
+
+    // q = A_bd v for own row k (v in pl); the row length rides in the free
+    // upper half of the last column word (U odd)
+    auto rowsum = [&](int k) -> double {
+        const int len = (int)(cw[k][UW - 1] >> 16);
+        double s = 0.0;
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int c = (int)((cw[k][u >> 1] >> (16 * (u & 1))) & 0xffffu);
+            if (u < len) s = s + val[k][u] * pl[c];
+        }
+        return s;
+    };
+    auto assembled = [&](int i) -> double {
+        const int g = grp_l[i];
+        double s = 0.0;
+        for (int e = cptr_l[g]; e < cptr_l[g + 1]; ++e) s = s + qif[cpos_l[e]];
+        return s;
+    };
+
+    const double tol = st->tol;
+    const int kmax = st->kmax;
+    double *hist = st->hist;
+    const int hcap = st->hist_cap;
+    int k_it = 0, restarts = -1, status = ST_RUNNING;
+    double bb = 0.0, stop = 0.0, rr = 0.0;
+
+    for (bool first = true; status == ST_RUNNING; first = false) {
+        // ---- r = b - A x, p = r (the first residual, and every recomputation)
+        ++restarts;
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            const int i = t + k * kSmallThreads;
+            if (i < n_loc) pl[i] = xl[i];
+        }
+        __syncthreads();
+        double q[R];
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            const int i = t + k * kSmallThreads;
+            q[k] = i < n_loc ? rowsum(k) : 0.0;
+            if (i < n_if) qif[i] = q[k];
+        }
+        double arr = 0.0, abb = 0.0;
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            const int i = t + k * kSmallThreads;
+            if (i < n_loc) {
+                const double qa = i < n_if ? assembled(i) : q[k];
+                const double bi = b[i];
+                const double ri = bi - qa;
+                rl[i] = ri;
+                if (i < n_own || i >= n_if) {
+                    arr = arr + ri * ri;
+                    abb = abb + bi * bi;
+                }
+            }
+        }
+        rr = small_sum(arr, ws, set);
+        if (first) {
+            bb = small_sum(abb, ws, set);
+            if (!isfinite(bb)) {
+                status = ST_BREAKDOWN;
+                break;
+            }
+            if (bb == 0.0) {
+                if (t == 0 && hist && hcap > 0) hist[0] = 0.0;
+                status = ST_ZERO_RHS;
+                break;
+            }
+            stop = tol * sqrt(bb);
+        }
+        if (!isfinite(rr)) {
+            status = ST_BREAKDOWN;
+            break;
+        }
+        if (t == 0 && hist && k_it < hcap) hist[k_it] = sqrt(rr / bb);
+        if (sqrt(rr) <= stop) {
+            status = ST_CONVERGED;
+            break;
+        }
+        if (k_it >= kmax) {
+            status = ST_MAXIT;
+            break;
+        }
+        // every read of pl (x) happened before the sums' barriers
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            const int i = t + k * kSmallThreads;
+            if (i < n_loc) pl[i] = rl[i];
+        }
+        __syncthreads();
+
+        // ---- CG iterations until the recurrence meets the tolerance
+        for (;;) {
+            double apq = 0.0;
+#pragma unroll
+            for (int k = 0; k < R; ++k) {
+                const int i = t + k * kSmallThreads;
+                q[k] = i < n_loc ? rowsum(k) : 0.0;
+                if (i < n_if) qif[i] = q[k];
+                if (i < n_loc) apq = apq + pl[i] * q[k];
+            }
+            const double pAp = small_sum(apq, ws, set);  // its barrier also publishes qif
+            if (!(pAp > 0.0) || !isfinite(pAp)) {
+                status = ST_BREAKDOWN;
+                break;
+            }
+            const double alpha = rr / pAp;
+            double arn = 0.0;
+#pragma unroll
+            for (int k = 0; k < R; ++k) {
+                const int i = t + k * kSmallThreads;
+                if (i < n_loc) {
+                    const double qa = i < n_if ? assembled(i) : q[k];
+                    xl[i] = xl[i] + alpha * pl[i];
+                    const double ri = rl[i] - alpha * qa;
+                    rl[i] = ri;
+                    if (i < n_own || i >= n_if) arn = arn + ri * ri;
+                }
+            }
+            const double rr_new = small_sum(arn, ws, set);
+            ++k_it;
+            if (!isfinite(rr_new)) {
+                status = ST_BREAKDOWN;
+                break;
+            }
+            if (t == 0 && hist && k_it < hcap) hist[k_it] = sqrt(rr_new / bb);
+            const double beta = rr_new / rr;
+            rr = rr_new;
+            if (sqrt(rr_new) <= stop) break;  // recompute the residual, restart if needed
+            if (k_it >= kmax) {
+                status = ST_MAXIT;
+                break;
+            }
+#pragma unroll
+            for (int k = 0; k < R; ++k) {
+                const int i = t + k * kSmallThreads;
+                if (i < n_loc) pl[i] = rl[i] + beta * pl[i];
+            }
+            __syncthreads();
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+        const int i = t + k * kSmallThreads;
+        if (i < n_loc) x[i] = xl[i];
+    }
+    if (t == 0) {
+        st->bb = bb;
+        st->stop = stop;
+        st->rr_last = rr;
+        st->iter_last = k_it;
+        st->restarts = restarts;
+        dev::flag_store(&st->status, status);
+    }
+}
+
+template <int R, int U>
+void launch_r(hipStream_t s, const SmallMat &M, const Iface &I, const double *b, double *x, DevState *st)
+{
+    const size_t lds = small_lds_bytes(M.n_loc, I.n_if, I.ngamma, M.n_copies);
+    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_cg_small<R, U>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL((k_cg_small<R, U>), dim3(1), dim3(kSmallThreads), lds, s, M.n_loc, I.n_own, I.n_if,
+                       I.ngamma, M.n_copies, M.val, M.colw, I.pos_grp, I.copy_ptr, I.copy_pos, b, x, st);
+}
+
+}  // namespace
+
+int32_t small_rows(int32_t rows_needed, int32_t width)
+{
+    const int32_t cap = width == 5 ? 9 : width == 7 ? 7 : 0;
+    return rows_needed >= 1 && rows_needed <= cap ? rows_needed : 0;
+}
+
+void launch_cg_small(hipStream_t s, const SmallMat &M, const Iface &I, const double *b, double *x, DevState *st)
+{
+    if (M.width == 5) {
+        switch (M.rows) {
+        case 1: launch_r<1, 5>(s, M, I, b, x, st); break;
+        case 2: launch_r<2, 5>(s, M, I, b, x, st); break;
+        case 3: launch_r<3, 5>(s, M, I, b, x, st); break;
+        case 4: launch_r<4, 5>(s, M, I, b, x, st); break;
+        case 5: launch_r<5, 5>(s, M, I, b, x, st); break;
+        case 6: launch_r<6, 5>(s, M, I, b, x, st); break;
+        case 7: launch_r<7, 5>(s, M, I, b, x, st); break;
+        case 8: launch_r<8, 5>(s, M, I, b, x, st); break;
+        case 9: launch_r<9, 5>(s, M, I, b, x, st); break;
+        default: break;
+        }
+    } else if (M.width == 7) {
+        switch (M.rows) {
+        case 1: launch_r<1, 7>(s, M, I, b, x, st); break;
+        case 2: launch_r<2, 7>(s, M, I, b, x, st); break;
+        case 3: launch_r<3, 7>(s, M, I, b, x, st); break;
+        case 4: launch_r<4, 7>(s, M, I, b, x, st); break;
+        case 5: launch_r<5, 7>(s, M, I, b, x, st); break;
+        case 6: launch_r<6, 7>(s, M, I, b, x, st); break;
+        case 7: launch_r<7, 7>(s, M, I, b, x, st); break;
+        default: break;
+        }
+    }
+}
+
+}  // namespace ss

@@ -12,6 +12,7 @@
 
 #include "host_common.h"
 #include "kernels.h"
+#include "layout.h"
 #include "ss_internal.h"
 
 using namespace ss;
@@ -20,381 +21,6 @@ namespace {
 
 constexpr int kDefaultCheck = 32;
 constexpr int32_t kHistMax = 1 << 22;  // residual history entries kept on the device
-constexpr int kSpmvGridMax = 1024;      // persistent SpMV workgroups (4 per CU)
-// Up to this many chunks the SpMV grid is 3 workgroups per CU: at 4 a wave
-// gets one or two chunks and has little to pipeline (measured: 7% faster
-// per iteration at 64^3, equal at 96^3; 4 per CU wins from ~1.4M rows on).
-constexpr int kSpmvGridSmall = 768;
-constexpr int kSmallChunks = 16384;
-constexpr int kGridLimit = 65536;       // upper bound accepted for a requested grid
-
-// Persistent SpMV grid: one workgroup per 4 chunks (or per CSR tile) at most.
-int32_t spmv_grid(bool sell, int32_t units, int32_t opt)
-{
-    const int32_t work = sell ? (units + kBS / 64 - 1) / (kBS / 64) : units;
-    const int32_t dflt = sell && units <= kSmallChunks ? kSpmvGridSmall : kSpmvGridMax;
-    return xcd_grid(std::max(1, std::min(work, opt ? opt : dflt)));
-}
-
-// Offset dictionary of a chunk: at most kDictOffsets distinct column - row
-// offsets, rows of at most kDictSlots entries (4-bit indices, 8 to a word).
-constexpr int kDictOffsets = 16;
-constexpr int kDictSlots = 8;
-constexpr int kDictMinPerWg = 24;  // chunks per SpMV workgroup for the dictionaries to pay
-
-// Host image of the device data of one partition.
-struct Layout {
-    // device position of every concatenated local position
-    std::vector<int32_t> dev_pos;
-    int32_t n_own = 0, n_if = 0;
-    std::vector<int32_t> l2g, g2own, copy_pos, pos_grp;
-    // matrix in device order
-    int fmt = FMT_SELL;
-    std::vector<int32_t> col, nzmap;  // storage order (SELL padded: nzmap = -1); SELL: wide chunks only
-    std::vector<int32_t> ccol;        // SELL: per chunk, start in col16 (>= 0) or ~start in col
-    std::vector<uint16_t> col16;      // SELL: window offsets of the narrow chunks
-    std::vector<int32_t> cbase;       // SELL: two window bases per chunk
-    int64_t col_bytes = 0;            // column data the SpMV reads: 2 or 4 B per stored (non-padding) entry,
-                                      // a dictionary chunk's 4 B per row and 64 B table
-    int64_t struct_bytes = 0;         // row structure the SpMV reads: SELL a chunk's start, first row, length,
-                                      // column start, window bases (and dictionary block) and 1 B per row
-                                      // unless a dictionary word holds it; CSR the row pointers
-    bool encode_ok = true;            // column encoding verified
-    std::vector<int32_t> cptr, cpos, rowptr, tile_row;
-    std::vector<uint8_t> clen, rlen;
-    std::vector<int32_t> cdict, dtab;  // SELL: dictionary block of each chunk (-1: none); 16 offsets a block
-    std::vector<uint32_t> dword;       // SELL: per block and lane, the 4-bit offset indices of slots 0..7
-    int32_t nchunks = 0, ntiles = 0, tile_nnz = 2048;
-    int32_t unroll = 8;               // SELL: entries per lane loaded before use
-    int32_t one_batch = 0;            // SELL: no chunk longer than unroll
-    int64_t stored = 0;  // entries incl. padding
-};
-
-// Device order: all owned interface copies (sub-domain by sub-domain), then
-// all other interface copies, then every sub-domain's interior positions, the
-// local order kept inside each group.  Within one local row all columns
-// belong to the same sub-domain and keep their relative order, so row sums
-// are unchanged.  Interface positions come first so that their (slower,
-// gathering) update batches are dispatched first.
-void build_order(const ss_part *p, Layout &L)
-{
-    const int32_t P = p->P, nl = p->n_loc();
-    L.dev_pos.assign(nl, -1);
-    int32_t tot_int = 0, tot_own = 0;
-    for (int32_t s = 0; s < P; ++s) {
-        tot_int += p->n_int[s];
-        tot_own += p->n_own[s];
-    }
-    const int32_t tot_if = nl - tot_int;
-    int32_t a = tot_if, b = 0, c = tot_own;
-    for (int32_t s = 0; s < P; ++s) {
-        const int32_t o = p->sub_off[s], i1 = o + p->n_int[s], i2 = i1 + p->n_own[s], e = p->sub_off[s + 1];
-        for (int32_t u = o; u < i1; ++u) L.dev_pos[u] = a++;
-        for (int32_t u = i1; u < i2; ++u) L.dev_pos[u] = b++;
-        for (int32_t u = i2; u < e; ++u) L.dev_pos[u] = c++;
-    }
-    L.n_own = tot_own;
-    L.n_if = tot_if;
-    L.l2g.assign(nl, 0);
-    for (int32_t u = 0; u < nl; ++u) L.l2g[L.dev_pos[u]] = p->l2g[u];
-    L.g2own.resize(p->n);
-    for (int32_t i = 0; i < p->n; ++i) L.g2own[i] = L.dev_pos[p->g2own[i]];
-    L.copy_pos.resize(p->copy_pos.size());
-    for (size_t u = 0; u < p->copy_pos.size(); ++u) L.copy_pos[u] = L.dev_pos[p->copy_pos[u]];
-    L.pos_grp.assign((size_t)tot_if, -1);
-    for (size_t g = 0; g + 1 < p->copy_ptr.size(); ++g)
-        for (int32_t u = p->copy_ptr[g]; u < p->copy_ptr[g + 1]; ++u) L.pos_grp[L.copy_pos[u]] = (int32_t)g;
-}
-
-// Matrix storage.  SELL-64 unless a row is longer than 255 entries or the
-// chunk padding would add more than a quarter to the stored entries; then
-// CSR row tiles.  `force` = SS_MAT_* selection from the options, `grid_opt`
-// the SpMV grid option (the chunk order depends on the grid).
-void build_matrix(const ss_part *p, Layout &L, int32_t tile_nnz, int32_t force, int32_t grid_opt)
-{
-    const int32_t nl = p->n_loc();
-    // rows in device order
-    std::vector<int32_t> src_row(nl);
-    for (int32_t u = 0; u < nl; ++u) src_row[L.dev_pos[u]] = u;
-    auto row_len = [&](int32_t t) { return p->bd_rowptr[src_row[t] + 1] - p->bd_rowptr[src_row[t]]; };
-    int32_t maxlen = 0;
-    for (int32_t t = 0; t < nl; ++t) maxlen = std::max(maxlen, row_len(t));
-    const int32_t nch = (nl + 63) / 64;
-    int64_t padded = 0;
-    for (int32_t c = 0; c < nch; ++c) {
-        int32_t m = 0;
-        for (int32_t t = c * 64; t < std::min(nl, c * 64 + 64); ++t) m = std::max(m, row_len(t));
-        padded += 64 * (int64_t)m;
-    }
-    const bool sell_ok = maxlen <= 255 && padded < INT32_MAX;
-    bool sell = sell_ok && padded <= p->nnz + p->nnz / 4;
-    if (force == SS_MAT_SELL && sell_ok) sell = true;
-    if (force == SS_MAT_CSR) sell = false;
-    L.tile_nnz = tile_nnz;
-    if (sell) {
-        L.fmt = FMT_SELL;
-        L.nchunks = nch;
-        L.rlen.assign(nl, 0);
-        for (int32_t t = 0; t < nl; ++t) L.rlen[t] = (uint8_t)row_len(t);
-        // processing order: the chunks holding interface rows (positions
-        // [0, n_if)) are spread evenly among the interior chunks
-        const int32_t nif_ch = (L.n_if + 63) / 64;
-        std::vector<int32_t> order;
-        order.reserve(nch);
-        int64_t placed_if = 0;
-        int32_t next_if = 0, next_in = nif_ch;
-        for (int32_t i = 0; i < nch; ++i) {
-            const bool take_if = next_if < nif_ch &&
-                                 (next_in >= nch || (int64_t)(i + 1) * nif_ch > placed_if * nch);
-            if (take_if) {
-                order.push_back(next_if++);
-                ++placed_if;
-            } else {
-                order.push_back(next_in++);
-            }
-        }
-        // Offset dictionaries: with every chunk one batch of at most 8 entries
-        // (the unroll is chosen below from the same lengths), a chunk whose
-        // columns take at most 16 distinct offsets from their rows is stored
-        // once more as 4-bit indices into a table of those offsets; the
-        // pipelined SpMV then reads one word per lane instead of one per
-        // entry.  Inside each SpMV workgroup's range these chunks come first.
-        std::vector<char> dict_ok(nch, 0);
-        {
-            std::vector<int32_t> clen_id(nch, 0);
-            for (int32_t id = 0; id < nch; ++id)
-                for (int32_t t = id * 64; t < std::min(nl, id * 64 + 64); ++t)
-                    clen_id[id] = std::max(clen_id[id], std::max(row_len(t), 1));
-            int64_t best_u = INT64_MAX;
-            int32_t u_sel = 8;
-            for (int32_t u : {9, 8, 7, 5}) {
-                int64_t slots = 0;
-                for (int32_t id = 0; id < nch; ++id) slots += (int64_t)((clen_id[id] + u - 1) / u) * u;
-                if (slots < best_u) {
-                    best_u = slots;
-                    u_sel = u;
-                }
-            }
-            bool one = true;
-            for (int32_t id = 0; id < nch; ++id) one = one && clen_id[id] <= u_sel;
-            // only where a wave gets several chunks: the switch to the other
-            // kind costs a reload outside the pipeline (per iteration: 64^3,
-            // 1.3 chunks a wave, 4.5% slower; 96^3, 4.5 a wave, even; 128^3,
-            // 8 a wave, 2.8% faster; 160^3, 4.3% faster)
-            const int32_t g = spmv_grid(true, nch, grid_opt);
-            if (one && u_sel <= kDictSlots && nch >= kDictMinPerWg * g) {
-                for (int32_t id = 0; id < nch; ++id) {
-                    const int32_t c0 = id * 64;
-                    if (c0 + 64 > nl) continue;
-                    int32_t tbl[kDictOffsets] = {0};  // padding entries point at the row itself
-                    int nt = 1;
-                    bool ok = true;
-                    for (int32_t t = c0; t < c0 + 64 && ok; ++t) {
-                        const int32_t u = src_row[t];
-                        for (int32_t e = p->bd_rowptr[u]; e < p->bd_rowptr[u + 1] && ok; ++e) {
-                            const int32_t d = L.dev_pos[p->bd_colidx[e]] - t;
-                            int q = 0;
-                            while (q < nt && tbl[q] != d) ++q;
-                            if (q == nt) {
-                                if (nt == kDictOffsets)
-                                    ok = false;
-                                else
-                                    tbl[nt++] = d;
-                            }
-                        }
-                    }
-                    dict_ok[id] = ok;
-                }
-                const int32_t cpb = (nch + g - 1) / g;
-                for (int32_t lo = 0; lo < nch; lo += cpb)
-                    std::stable_partition(order.begin() + lo, order.begin() + std::min(nch, lo + cpb),
-                                          [&](int32_t id) { return dict_ok[id] != 0; });
-            }
-        }
-        L.cptr.assign(nch + 1, 0);
-        L.cpos.assign(nch, 0);
-        L.clen.assign(nch, 0);
-        for (int32_t i = 0; i < nch; ++i) {
-            const int32_t id = order[i];
-            int32_t m = 0;
-            for (int32_t t = id * 64; t < std::min(nl, id * 64 + 64); ++t) m = std::max(m, (int32_t)L.rlen[t]);
-            // at least one stored entry per chunk (padding for a chunk of
-            // empty rows), so every batch of a chunk has entries to gather
-            m = std::max(m, (int32_t)1);
-            L.cpos[i] = id * 64;
-            L.clen[i] = (uint8_t)m;
-            L.cptr[i + 1] = L.cptr[i] + 64 * m;
-        }
-        L.stored = L.cptr[nch];
-        // the unroll that wastes the fewest loads on the chunk lengths (ties:
-        // the larger); a 7-point stencil gets 7, a 27-point one 9
-        int64_t best = INT64_MAX;
-        for (int32_t u : {9, 8, 7, 5}) {
-            int64_t slots = 0;
-            for (int32_t i = 0; i < nch; ++i) slots += (int64_t)((L.clen[i] + u - 1) / u) * u;
-            if (slots < best) {
-                best = slots;
-                L.unroll = u;
-            }
-        }
-        // every chunk one batch: the SpMV pipelines chunk to chunk
-        L.one_batch = 1;
-        for (int32_t i = 0; i < nch; ++i)
-            if (L.clen[i] > L.unroll) L.one_batch = 0;
-        // padding points at a valid position (the row itself, or 0 past the
-        // last row) and is masked out by the row length
-        L.col.assign((size_t)L.stored, 0);
-        L.nzmap.assign((size_t)L.stored, -1);
-        for (int32_t i = 0; i < nch; ++i)
-            for (int32_t lane = 0; lane < 64; ++lane) {
-                const int32_t t = L.cpos[i] + lane;
-                const int32_t len = t < nl ? L.rlen[t] : 0;
-                for (int32_t j = 0; j < L.clen[i]; ++j) {
-                    const int64_t k = L.cptr[i] + (int64_t)j * 64 + lane;
-                    if (j < len) {
-                        const int32_t e = p->bd_rowptr[src_row[t]] + j;
-                        L.col[k] = L.dev_pos[p->bd_colidx[e]];
-                        L.nzmap[k] = p->bd_nzmap[e];
-                    } else {
-                        L.col[k] = t < nl ? t : 0;
-                    }
-                }
-            }
-        // 16-bit columns for chunks whose entries all fall in two windows of
-        // 32768 positions: one around the chunk's rows, one at the lowest
-        // column outside it (the interface copies an interior chunk reads);
-        // int32 positions otherwise, and for a chunk holding no row past the end
-        std::vector<int32_t> wide;
-        L.ccol.assign(nch, 0);
-        L.cbase.assign(2 * (size_t)nch, 0);
-        L.col_bytes = 0;
-        for (int32_t i = 0; i < nch; ++i) {
-            const int64_t k0 = L.cptr[i], k1 = L.cptr[i + 1];
-            const int32_t b1 = std::max(0, L.cpos[i] - 16384);
-            int32_t lo2 = INT32_MAX, hi2 = -1;
-            for (int64_t k = k0; k < k1; ++k)
-                if (L.col[k] < b1 || L.col[k] > b1 + 32767) {
-                    lo2 = std::min(lo2, L.col[k]);
-                    hi2 = std::max(hi2, L.col[k]);
-                }
-            const bool narrow = L.cpos[i] + 64 <= nl && (hi2 < 0 || hi2 - lo2 <= 32767);
-            const int32_t b2 = hi2 < 0 ? 0 : lo2;
-            int64_t real = 0;
-            for (int32_t lane = 0; lane < 64; ++lane)
-                if (L.cpos[i] + lane < nl) real += L.rlen[L.cpos[i] + lane];
-            L.col_bytes += real * (narrow ? 2 : 4);
-            if (narrow) {
-                // the SpMV reads 16-bit offsets in aligned pairs: each chunk's
-                // start is even (64 entries per slot)
-                L.ccol[i] = (int32_t)L.col16.size();
-                if (L.ccol[i] & 1) L.encode_ok = false;
-                L.cbase[2 * (size_t)i] = b1;
-                L.cbase[2 * (size_t)i + 1] = b2;
-                for (int64_t k = k0; k < k1; ++k) {
-                    const int32_t v = L.col[k];
-                    const bool in1 = v >= b1 && v <= b1 + 32767;
-                    L.col16.push_back(in1 ? (uint16_t)(v - b1) : (uint16_t)(0x8000u | (uint32_t)(v - b2)));
-                }
-            } else {
-                L.ccol[i] = ~(int32_t)wide.size();
-                wide.insert(wide.end(), L.col.begin() + k0, L.col.begin() + k1);
-            }
-        }
-        // every stored column must decode back to itself
-        for (int32_t i = 0; i < nch; ++i)
-            for (int64_t k = L.cptr[i]; k < L.cptr[i + 1]; ++k) {
-                int32_t v;
-                const int64_t off = k - L.cptr[i];
-                if (L.ccol[i] >= 0) {
-                    const uint32_t e = L.col16[(size_t)L.ccol[i] + off];
-                    v = ((e & 0x8000u) ? L.cbase[2 * (size_t)i + 1] : L.cbase[2 * (size_t)i]) + (int32_t)(e & 0x7fffu);
-                } else {
-                    v = wide[(size_t)~L.ccol[i] + off];
-                }
-                if (v != L.col[k] || v < 0 || v >= std::max(nl, 1)) L.encode_ok = false;
-            }
-        // the offset dictionaries (processing order), checked entry by entry
-        L.cdict.assign(nch, -1);
-        for (int32_t i = 0; i < nch; ++i) {
-            if (!dict_ok[L.cpos[i] / 64]) continue;
-            const int32_t blk = (int32_t)(L.dtab.size() / kDictOffsets);
-            std::vector<int32_t> offs(1, 0);
-            for (int64_t k = L.cptr[i]; k < L.cptr[i + 1]; ++k) {
-                const int32_t d = L.col[k] - (L.cpos[i] + (int32_t)((k - L.cptr[i]) % 64));
-                if (std::find(offs.begin(), offs.end(), d) == offs.end()) offs.push_back(d);
-                if ((int)offs.size() > kDictOffsets) break;
-            }
-            std::sort(offs.begin(), offs.end());
-            if ((int)offs.size() > kDictOffsets || L.clen[i] > kDictSlots) {
-                L.encode_ok = false;
-                continue;
-            }
-            L.cdict[i] = blk;
-            // the pipelined SpMV reads a word per row and the table instead
-            int64_t real = 0;
-            for (int32_t lane = 0; lane < 64; ++lane) real += L.rlen[L.cpos[i] + lane];
-            L.col_bytes += 64 * 4 + kDictOffsets * 4 - real * (L.ccol[i] >= 0 ? 2 : 4);
-            for (int32_t q = 0; q < kDictOffsets; ++q) L.dtab.push_back(q < (int32_t)offs.size() ? offs[q] : 0);
-            const int32_t zero = (int32_t)(std::lower_bound(offs.begin(), offs.end(), 0) - offs.begin());
-            for (int32_t lane = 0; lane < 64; ++lane) {
-                const int32_t t = L.cpos[i] + lane;
-                uint32_t wd = 0;
-                for (int32_t j = 0; j < kDictSlots; ++j) {
-                    int32_t q = zero;  // slots past the chunk length decode to the row itself
-                    if (j < L.clen[i]) {
-                        const int32_t d = L.col[L.cptr[i] + (int64_t)j * 64 + lane] - t;
-                        q = (int32_t)(std::lower_bound(offs.begin(), offs.end(), d) - offs.begin());
-                    }
-                    if (j < L.unroll) wd |= (uint32_t)q << (4 * j);
-                    const int32_t back = t + L.dtab[(size_t)blk * kDictOffsets + q];
-                    if (j < L.clen[i] ? back != L.col[L.cptr[i] + (int64_t)j * 64 + lane] : back != t)
-                        L.encode_ok = false;
-                }
-                // with at most 7 slots the top 4 bits hold the row's length
-                if (L.unroll < kDictSlots) wd |= (uint32_t)L.rlen[t] << (4 * (kDictSlots - 1));
-                L.dword.push_back(wd);
-            }
-        }
-        L.struct_bytes = 0;
-        for (int32_t i = 0; i < nch; ++i) {
-            L.struct_bytes += 4 + 4 + 1 + 4 + 8 + (L.dtab.empty() ? 0 : 4);
-            if (L.cdict[i] < 0 || L.unroll >= kDictSlots)
-                for (int32_t lane = 0; lane < 64; ++lane) L.struct_bytes += L.cpos[i] + lane < nl ? 1 : 0;
-        }
-        L.col.swap(wide);
-    } else {
-        L.fmt = FMT_CSR;
-        L.rowptr.assign(nl + 1, 0);
-        for (int32_t t = 0; t < nl; ++t) L.rowptr[t + 1] = L.rowptr[t] + row_len(t);
-        L.stored = L.rowptr[nl];
-        L.col.resize((size_t)L.stored);
-        L.nzmap.resize((size_t)L.stored);
-        L.col_bytes = 4 * L.stored;
-        L.struct_bytes = 4 * ((int64_t)nl + 1);
-        for (int32_t t = 0; t < nl; ++t) {
-            const int32_t u = src_row[t];
-            for (int32_t e = p->bd_rowptr[u], k = L.rowptr[t]; e < p->bd_rowptr[u + 1]; ++e, ++k) {
-                L.col[k] = L.dev_pos[p->bd_colidx[e]];
-                L.nzmap[k] = p->bd_nzmap[e];
-            }
-        }
-        // row tiles: at most tile_nnz entries and 4 * workgroup rows; a longer
-        // row is a tile of its own
-        L.tile_row.assign(1, 0);
-        int32_t r0 = 0;
-        while (r0 < nl) {
-            int32_t r = r0;
-            if (L.rowptr[r0 + 1] - L.rowptr[r0] > tile_nnz)
-                r = r0 + 1;
-            else
-                while (r < nl && r - r0 < 4 * kBS && L.rowptr[r + 1] - L.rowptr[r0] <= tile_nnz) ++r;
-            L.tile_row.push_back(r);
-            r0 = r;
-        }
-        L.ntiles = (int32_t)L.tile_row.size() - 1;
-    }
-}
-
 }  // namespace
 
 struct ss_solver {
@@ -421,9 +47,14 @@ struct ss_solver {
     double *part_a = nullptr, *part_b = nullptr, *part_r = nullptr;  // SpMV, update, residual partials
     // Jacobi preconditioner: 1 / a_ii per position, z = D^{-1} r, (r, z) partials
     double *dinv = nullptr, *z = nullptr, *part_b2 = nullptr;
+    int32_t *dnz = nullptr;  // global stored entry of each position's diagonal (for new values)
     DevState *st = nullptr;
     double *hist = nullptr;
     int32_t hist_cap = 0;
+
+    // one-launch solve of a small system (rows == 0: not used)
+    SmallMat small{};
+    int32_t *small_nz = nullptr;  // global stored entry of each small value slot (-1: padding)
 
     // FP32-value iterative refinement: FP32 copy of the values, inner vectors
     Mat mat32{};
@@ -605,6 +236,16 @@ int setup_impl(const ss_csr *A, const ss_part *p, const ss_opts *o, void *hip_st
     int rc = validate_csr(A, false);
     if (rc != SS_OK) return rc;
     if (A->n != p->n || (int64_t)A->nnz != p->nnz) return fail(SS_EINVAL, "matrix does not match the partition");
+    // the pattern too: every local entry names a stored entry of A in the
+    // row and column of its nodes
+    for (int32_t r = 0; r < p->n_loc(); ++r) {
+        const int32_t gi = p->l2g[r];
+        for (int32_t e = p->bd_rowptr[r]; e < p->bd_rowptr[r + 1]; ++e) {
+            const int32_t k = p->bd_nzmap[e];
+            if (k < A->rowptr[gi] || k >= A->rowptr[gi + 1] || A->colidx[k] != p->l2g[p->bd_colidx[e]])
+                return fail(SS_EINVAL, "matrix does not match the partition's pattern (row " + std::to_string(gi) + ")");
+        }
+    }
     ss_opts opts;
     ss_opts_default(&opts);
     if (o) opts = *o;
@@ -617,11 +258,16 @@ int setup_impl(const ss_csr *A, const ss_part *p, const ss_opts *o, void *hip_st
     if (opts.precond == SS_PRECOND_JACOBI && opts.precision != SS_FP64)
         return fail(SS_EUNSUPPORTED, "the Jacobi preconditioner is available with SS_FP64 only");
     std::vector<double> diag;
+    std::vector<int32_t> diag_nz;
     if (opts.precond == SS_PRECOND_JACOBI) {
         diag.assign((size_t)A->n, 0.0);
+        diag_nz.assign((size_t)A->n, -1);
         for (int32_t i = 0; i < A->n; ++i)
             for (int32_t k = A->rowptr[i]; k < A->rowptr[i + 1]; ++k)
-                if (A->colidx[k] == i) diag[i] = A->val[k];
+                if (A->colidx[k] == i) {
+                    diag[i] = A->val[k];
+                    diag_nz[i] = k;
+                }
         for (int32_t i = 0; i < A->n; ++i)
             if (!(diag[i] > 0.0) || !std::isfinite(diag[i]))
                 return fail(SS_EINVAL, "Jacobi needs a positive diagonal (row " + std::to_string(i) + ")");
@@ -632,6 +278,8 @@ int setup_impl(const ss_csr *A, const ss_part *p, const ss_opts *o, void *hip_st
         return fail(SS_EINVAL, "unknown matrix_format");
     if ((opts.alloc == nullptr) != (opts.free == nullptr)) return fail(SS_EINVAL, "alloc and free go together");
     if (opts.spmv_grid < 0 || opts.spmv_grid > kGridLimit) return fail(SS_EINVAL, "spmv_grid must be in [0, 65536]");
+    if (opts.small_solver != SS_SMALL_AUTO && opts.small_solver != SS_SMALL_OFF)
+        return fail(SS_EINVAL, "unknown small_solver");
     if (opts.precision == SS_FP32_IR && !(opts.inner_tol > 0.0 && opts.inner_tol < 1.0))
         return fail(SS_EINVAL, "inner_tol must be in (0, 1)");
 
@@ -746,9 +394,13 @@ int setup_impl(const ss_csr *A, const ss_part *p, const ss_opts *o, void *hip_st
         return bail(rc);
     if (opts.precond == SS_PRECOND_JACOBI) {
         std::vector<double> dinv(nl);
-        for (size_t c = 0; c < nl; ++c) dinv[c] = 1.0 / diag[(size_t)L.l2g[c]];
-        if ((rc = upload(s, &s->dinv, dinv.data(), dinv.size())) || (rc = alloc_dev(s, &s->z, nl)) ||
-            (rc = alloc_dev(s, &s->part_b2, (size_t)I.grid)))
+        std::vector<int32_t> dnz(nl);
+        for (size_t c = 0; c < nl; ++c) {
+            dinv[c] = 1.0 / diag[(size_t)L.l2g[c]];
+            dnz[c] = diag_nz[(size_t)L.l2g[c]];
+        }
+        if ((rc = upload(s, &s->dinv, dinv.data(), dinv.size())) || (rc = upload(s, &s->dnz, dnz.data(), dnz.size())) ||
+            (rc = alloc_dev(s, &s->z, nl)) || (rc = alloc_dev(s, &s->part_b2, (size_t)I.grid)))
             return bail(rc);
         I.dinv = s->dinv;
     }
@@ -795,6 +447,47 @@ int setup_impl(const ss_csr *A, const ss_part *p, const ss_opts *o, void *hip_st
     s->run32.p1 = s->p32b;
     s->run32.q = s->q32;
     s->run32.st = s->st_in;
+
+    // A small system (FP64, M = I, rows of at most 7 entries, at most 5120 or
+    // 4096 positions, x, r, p and the interface products within the LDS a
+    // workgroup may take) is solved by one launch per solve.
+    int lds_max = 0;
+    if (hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, s->device) != hipSuccess)
+        lds_max = 0;
+    if (opts.precision == SS_FP64 && opts.precond == SS_PRECOND_NONE && band_kind < 0 &&
+        opts.small_solver == SS_SMALL_AUTO && s->n_loc > 0) {
+        int32_t wmax = 0;
+        for (int32_t u = 0; u < s->n_loc; ++u) wmax = std::max(wmax, p->bd_rowptr[u + 1] - p->bd_rowptr[u]);
+        const int32_t width = wmax <= 5 ? 5 : 7;
+        const int32_t rows = small_rows((s->n_loc + kSmallThreads - 1) / kSmallThreads, width);
+        if (wmax <= 7 && rows > 0 && s->n_loc <= 65536 &&
+            small_lds_bytes(s->n_loc, L.n_if, s->ngamma, (int32_t)p->copy_pos.size()) <=
+                (size_t)std::max(lds_max, 0)) {
+            std::vector<double> sv;
+            std::vector<uint32_t> sc;
+            try {
+                build_small(p, L, A->val, width, sv, sc);
+            } catch (const std::bad_alloc &) {
+                return bail(fail(SS_ENOMEM, "host allocation failed"));
+            }
+            // where each value slot comes from, for new values (ss_cg_set_values)
+            std::vector<int32_t> snz(sv.size(), -1);
+            {
+                std::vector<int32_t> src(nl);
+                for (int32_t u = 0; u < s->n_loc; ++u) src[L.dev_pos[u]] = u;
+                for (int32_t t = 0; t < s->n_loc; ++t) {
+                    const int32_t u = src[t], e0 = p->bd_rowptr[u], len = p->bd_rowptr[u + 1] - e0;
+                    for (int32_t j = 0; j < len; ++j) snz[(size_t)j * nl + t] = p->bd_nzmap[e0 + j];
+                }
+            }
+            double *d_sv = nullptr;
+            uint32_t *d_sc = nullptr;
+            if ((rc = upload(s, &d_sv, sv.data(), sv.size())) || (rc = upload(s, &d_sc, sc.data(), sc.size())) ||
+                (rc = upload(s, &s->small_nz, snz.data(), snz.size())))
+                return bail(rc);
+            s->small = SmallMat{s->n_loc, (int32_t)p->copy_pos.size(), rows, width, d_sv, d_sc};
+        }
+    }
 
     DevState init{};
     std::memcpy(s->st_pinned, &init, sizeof(DevState));
@@ -868,6 +561,13 @@ int ss_band_setup(const ss_csr *A, int32_t kind, int32_t nbands, const ss_opts *
     return rc;
 }
 
+int ss_cg_path(const ss_solver *s, int32_t *path)
+{
+    if (!s || !path) return fail(SS_EINVAL, "NULL argument");
+    *path = s->small.rows > 0 ? SS_PATH_SMALL : SS_PATH_STREAM;
+    return SS_OK;
+}
+
 int ss_cg_info(const ss_solver *s, int32_t *n, int32_t *n_loc, int64_t *nnz, int32_t *matrix_format,
                int64_t *stored)
 {
@@ -880,14 +580,16 @@ int ss_cg_info(const ss_solver *s, int32_t *n, int32_t *n_loc, int64_t *nnz, int
     return SS_OK;
 }
 
-int ss_cg_solve(ss_solver *s, const double *b_dev, double *x_dev, double tol, int32_t maxit, ss_result *res,
-                double *hist_host)
+}  // extern "C"
+
+namespace {
+
+// The solve of ss_cg_solve on the solver's run state s->st, history s->hist
+// (capacity s->hist_cap, or none) and the launch mode s->opts.use_graph.
+int solve_core(ss_solver *s, const double *b_dev, double *x_dev, double tol, int32_t maxit, ss_result *res,
+               double *hist_host)
 {
-    if (!s) return fail(SS_EINVAL, "solver is NULL");
-    if (!b_dev || !x_dev) return fail(SS_EINVAL, "b or x is NULL");
-    if (!(tol >= 0.0) || maxit < 0) return fail(SS_EINVAL, "need tol >= 0 and maxit >= 0");
-    int rc = ensure_hist(s, std::min<int64_t>((int64_t)maxit + 1, kHistMax));
-    if (rc != SS_OK) return rc;
+    int rc = SS_OK;
     DevState init{};
     init.tol = tol;
     init.kmax = maxit;
@@ -902,7 +604,12 @@ int ss_cg_solve(ss_solver *s, const double *b_dev, double *x_dev, double tol, in
     int32_t status = ST_RUNNING;
     int32_t restarts = -1, outer = 0;
     bool outer_cap = false;  // IR stopped by max_outer
-    if (s->opts.precision == SS_FP64) {
+    if (s->opts.precision == SS_FP64 && s->small.rows > 0) {
+        // the whole solve in one launch; its restart count comes back in the state
+        launch_cg_small(s->stream, s->small, s->ifc, s->b, s->x, s->st);
+        SS_HIP(hipGetLastError());
+        restarts = 0;
+    } else if (s->opts.precision == SS_FP64) {
         for (bool first = true;; first = false) {
             ++restarts;
             // r = b - A x, p = r (Algorithm 3, first line; also the convergence check)
@@ -991,6 +698,7 @@ int ss_cg_solve(ss_solver *s, const double *b_dev, double *x_dev, double tol, in
     }
     (void)outer_cap;
     const double relres = f.status == ST_ZERO_RHS ? 0.0 : std::sqrt(f.rr_last / f.bb);
+    if (s->opts.precision == SS_FP64 && s->small.rows > 0) restarts = f.restarts;
     if (res) {
         res->status = code;
         res->iterations = f.iter_last;
@@ -999,12 +707,27 @@ int ss_cg_solve(ss_solver *s, const double *b_dev, double *x_dev, double tol, in
         res->relres = relres;
         res->true_relres = relres;
     }
-    if (hist_host) {
+    if (hist_host && s->hist) {
         const int32_t cnt = f.status == ST_ZERO_RHS ? 1 : std::min(f.iter_last + 1, s->hist_cap);
         SS_HIP(hipMemcpy(hist_host, s->hist, sizeof(double) * cnt, hipMemcpyDeviceToHost));
     }
     if (code == SS_EBREAKDOWN) fail(SS_EBREAKDOWN, "CG breakdown: (p, A p) <= 0 or non-finite value");
     return code;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ss_cg_solve(ss_solver *s, const double *b_dev, double *x_dev, double tol, int32_t maxit, ss_result *res,
+                double *hist_host)
+{
+    if (!s) return fail(SS_EINVAL, "solver is NULL");
+    if (!b_dev || !x_dev) return fail(SS_EINVAL, "b or x is NULL");
+    if (!(tol >= 0.0) || maxit < 0) return fail(SS_EINVAL, "need tol >= 0 and maxit >= 0");
+    const int rc = ensure_hist(s, std::min<int64_t>((int64_t)maxit + 1, kHistMax));
+    if (rc != SS_OK) return rc;
+    return solve_core(s, b_dev, x_dev, tol, maxit, res, hist_host);
 }
 
 int ss_cg_apply(ss_solver *s, const double *x_dev, double *y_dev)
@@ -1036,6 +759,10 @@ int ss_cg_set_values(ss_solver *s, const double *val_dev)
 {
     if (!s || !val_dev) return fail(SS_EINVAL, "NULL argument");
     launch_set_values(s->stream, s->stored, s->nzmap, val_dev, s->val, s->val32);
+    if (s->small.rows > 0)
+        launch_set_values(s->stream, (int64_t)s->small.width * s->n_loc, s->small_nz, val_dev,
+                          const_cast<double *>(s->small.val), nullptr);
+    if (s->dinv) launch_set_dinv(s->stream, s->n_loc, s->dnz, val_dev, s->dinv);
     SS_HIP(hipGetLastError());
     SS_HIP(hipStreamSynchronize(s->stream));
     return SS_OK;

@@ -135,3 +135,39 @@ def test_pcg_edge_cases():
         _pcg(Z, ss.ss_partition(Z, ss.SS_PART_BOX, 8, grid=(M, M, M), boxes=(2, 2, 2)))
     with pytest.raises(ss.SSError):
         _pcg(A, p, precision=ss.SS_FP32_RU)
+
+
+def _scaled(A, seed):
+    """D A D with a random positive diagonal D: the same pattern, still
+    symmetric positive-definite, every diagonal entry changed."""
+    d = np.random.default_rng(seed).uniform(0.5, 2.0, A.n)
+    rows = A.row_of_nz()
+    return CSR(A.n, A.rowptr, A.colidx, d[rows] * A.val * d[A.colidx])
+
+
+def test_set_values_updates_the_preconditioner():
+    # new values through ss_cg_set_values: the inverse diagonal follows, so the
+    # solve is the Jacobi PCG of the new matrix -- bitwise the solve of a
+    # solver set up on the new matrix, and the oracle's PCG within its bars
+    M = 12
+    A = diffusion3d_lognormal(M, seed=8)
+    p = ss.ss_partition(A, ss.SS_PART_BOX, 8, grid=(M, M, M), boxes=(2, 2, 2))
+    sd = O.split(A.rowptr, A.colidx, O.box_partition((M, M, M), (2, 2, 2)), 8)
+    A2 = _scaled(A, 3)
+    b = uniform_rhs(A.n, 6)
+    s = _pcg(A, p)
+    ss.ss_cg_set_values(s, _t(A2.val))
+    x = torch.zeros(A.n, dtype=torch.float64, device=DEV)
+    r = ss.ss_cg_solve(s, _t(b), x, tol=1e-10, maxit=10000)
+    x2 = torch.zeros(A.n, dtype=torch.float64, device=DEV)
+    r2 = ss.ss_cg_solve(_pcg(A2, p), _t(b), x2, tol=1e-10, maxit=10000)
+    assert r.status == r2.status == ss.SS_OK and r.iterations == r2.iterations
+    assert torch.equal(x, x2)
+    xo, ro = O.ss_pcg(A2, sd, b, tol=1e-10)
+    assert abs(r.iterations - ro.iterations) <= 2
+    xg = x.cpu().numpy()
+    assert np.linalg.norm(b - O.csr_matvec(A2, xg)) <= 1e-10 * np.linalg.norm(b)
+    # the old matrix's PCG would differ
+    x3 = torch.zeros(A.n, dtype=torch.float64, device=DEV)
+    r3 = ss.ss_cg_solve(_pcg(A, p), _t(b), x3, tol=1e-10, maxit=10000)
+    assert not torch.equal(x3, x)

@@ -30,12 +30,32 @@ def test_library_exports_every_declared_symbol():
     assert not missing, missing
 
 
+def _c_layout(struct, fields):
+    """sizeof and offsetof of a struct of include/ss.h, as a C compiler lays it out."""
+    import subprocess
+    import tempfile
+    inc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
+    body = "".join(f'printf("%zu\\n", offsetof({struct}, {f}));' for f in fields)
+    src = ("#include <stddef.h>\n#include <stdio.h>\n#include \"ss.h\"\n"
+           f"int main(void) {{ printf(\"%zu\\n\", sizeof({struct})); {body} return 0; }}\n")
+    with tempfile.TemporaryDirectory() as d:
+        c, exe = os.path.join(d, "l.c"), os.path.join(d, "l")
+        with open(c, "w") as f:
+            f.write(src)
+        subprocess.run(["gcc", "-std=c99", f"-I{inc}", "-o", exe, c], check=True)
+        out = subprocess.run([exe], check=True, capture_output=True, text=True).stdout.split()
+    return [int(v) for v in out]
+
+
 def test_opts_layout_and_defaults():
     o = ss.default_opts()
-    assert C.sizeof(ss.ss_opts) == 80
+    names = [f[0] for f in ss.ss_opts._fields_]
+    lay = _c_layout("ss_opts", names)
+    assert C.sizeof(ss.ss_opts) == lay[0]
+    assert [getattr(ss.ss_opts, f).offset for f in names] == lay[1:]
     assert o.precision == ss.SS_FP64 and o.inner_tol == 1e-6 and o.max_outer == 50 and o.ru_delta == 0.1
     assert o.check_every == 32 and o.use_graph == 1 and o.tile_nnz == 0
-    assert o.matrix_format == ss.SS_MAT_AUTO
+    assert o.matrix_format == ss.SS_MAT_AUTO and o.small_solver == ss.SS_SMALL_AUTO
     assert ss.lib().ss_version() >= 100
     assert ss.strerror(ss.SS_EBREAKDOWN).startswith("CG breakdown")
 
