@@ -257,6 +257,27 @@ int ss_cg_setup(const ss_csr *A, const ss_part *p, const ss_opts *o, void *hip_s
 int ss_cg_solve(ss_solver *s, const double *b_dev, double *x_dev, double tol, int32_t maxit, ss_result *res,
                 double *hist_host);
 
+/*
+ * ss_cg_solve_noalloc -- ss_cg_solve for callers that cannot allocate device
+ * memory: code under HIP graph capture, tight serving loops, harnesses that
+ * forbid allocation.  Same method, arguments and results as ss_cg_solve for a
+ * solver set up with SS_FP64 (any preconditioner and path), but the run
+ * state and the residual history live in a fixed device array of the library
+ * (256 bytes + SS_NOALLOC_HIST_MAX doubles per GPU, held until the process
+ * ends) instead of the solver's buffers, no graph is instantiated (the polled
+ * chunks are launched kernel by kernel), and nothing is allocated: no
+ * hipMalloc, hipFree or allocator callback.
+ * hist_host: NULL (no history), or capacity maxit+1 with maxit + 1 <=
+ * SS_NOALLOC_HIST_MAX.
+ * Every call on one GPU uses that GPU's array: calls that overlap on one GPU
+ * (through any solver, on any stream or thread) race and must not be made.
+ * Returns as ss_cg_solve; also SS_EINVAL (history longer than the maximum),
+ * SS_EUNSUPPORTED (precision other than SS_FP64).
+ */
+#define SS_NOALLOC_HIST_MAX 32768
+int ss_cg_solve_noalloc(ss_solver *s, const double *b_dev, double *x_dev, double tol, int32_t maxit,
+                        ss_result *res, double *hist_host);
+
 /* y_dev = A x_dev through the sub-structured path (local SpMV in every
  * sub-domain, then interface assembly; Section 4.4.1).  Device, global
  * numbering, length n; y must not alias x. */

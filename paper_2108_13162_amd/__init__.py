@@ -92,6 +92,7 @@ def lib() -> C.CDLL:
         "ss_opts_default": (None, [P]),
         "ss_cg_setup": (C.c_int, [P, P, P, P, P]),
         "ss_cg_solve": (C.c_int, [P, P, P, dbl, i32, P, P]),
+        "ss_cg_solve_noalloc": (C.c_int, [P, P, P, dbl, i32, P, P]),
         "ss_cg_apply": (C.c_int, [P, P, P]),
         "ss_cg_apply_f32": (C.c_int, [P, P, P]),
         "ss_cg_set_values": (C.c_int, [P, P]),
@@ -396,6 +397,21 @@ def ss_cg_solve(s: Solver, b, x, tol: float = 1e-10, maxit: int = 10000, hist: b
     h = np.full(maxit + 1, np.nan) if hist else None
     code = lib().ss_cg_solve(s.h, pb, px, float(tol), int(maxit), C.byref(res), _ptr(h))
     _check(code, "ss_cg_solve", ok=(SS_OK, SS_NOT_CONVERGED, SS_EBREAKDOWN))
+    return Result(res.status, res.iterations, res.outer_iterations, res.restarts, res.relres, res.true_relres,
+                  None if h is None else h[: res.iterations + 1])
+
+
+SS_NOALLOC_HIST_MAX = 32768
+
+
+def ss_cg_solve_noalloc(s: Solver, b, x, tol: float = 1e-10, maxit: int = 10000, hist: bool = False) -> Result:
+    """ss_cg_solve without any device allocation (state in the library's fixed
+    per-GPU array; calls that overlap on one GPU race)."""
+    pb, px = _dev_f64(b, s.n, "b"), _dev_f64(x, s.n, "x")
+    res = ss_result()
+    h = np.full(maxit + 1, np.nan) if hist else None
+    code = lib().ss_cg_solve_noalloc(s.h, pb, px, float(tol), int(maxit), C.byref(res), _ptr(h))
+    _check(code, "ss_cg_solve_noalloc", ok=(SS_OK, SS_NOT_CONVERGED, SS_EBREAKDOWN))
     return Result(res.status, res.iterations, res.outer_iterations, res.restarts, res.relres, res.true_relres,
                   None if h is None else h[: res.iterations + 1])
 

@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -21,6 +22,39 @@ namespace {
 
 constexpr int kDefaultCheck = 32;
 constexpr int32_t kHistMax = 1 << 22;  // residual history entries kept on the device
+
+// ---- device memory of ss_cg_solve_noalloc ----------------------------------
+// The run state (DevState, in the first 256 bytes) and the residual history
+// (SS_NOALLOC_HIST_MAX doubles) of the solve that allocates nothing: one fixed
+// array per GPU, held until the process ends and shared by every such call on
+// that GPU.  Host code never uses the name of the array (a host-side stand-in,
+// not a device address): it takes the address hipGetSymbolAddress gives for
+// the current device at set-up, kept per device below.
+constexpr size_t kScratchState = 256;
+constexpr size_t kScratchBytes = kScratchState + sizeof(double) * SS_NOALLOC_HIST_MAX;
+static_assert(sizeof(DevState) <= kScratchState, "the run state fits its slot");
+__device__ __align__(256) static unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_dev[kMaxDevices] = {};
+
+// The device address of `scratch` on `device`, which must be current; looked
+// up once per device.
+int scratch_address(int device, void **out)
+{
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (device < 0 || device >= kMaxDevices) return fail(SS_EDEVICE, "device ordinal out of range");
+    if (!g_scratch_dev[device]) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return fail(SS_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        g_scratch_dev[device] = ptr;
+    }
+    *out = g_scratch_dev[device];
+    return SS_OK;
+}
 }  // namespace
 
 struct ss_solver {
@@ -51,6 +85,7 @@ struct ss_solver {
     DevState *st = nullptr;
     double *hist = nullptr;
     int32_t hist_cap = 0;
+    void *scratch = nullptr;  // device address of the no-allocation solve's array on this device
 
     // one-launch solve of a small system (rows == 0: not used)
     SmallMat small{};
@@ -319,6 +354,11 @@ int setup_impl(const ss_csr *A, const ss_part *p, const ss_opts *o, void *hip_st
         return code;
     };
     if (hipGetDevice(&s->device) != hipSuccess) return bail(fail(SS_EDEVICE, "no HIP device"));
+    // the no-allocation solve's array: an unavailable one fails that call only
+    if (scratch_address(s->device, &s->scratch) != SS_OK) {
+        s->scratch = nullptr;
+        (void)hipGetLastError();
+    }
     if (hipStreamCreateWithFlags(&s->cap, hipStreamNonBlocking) != hipSuccess)
         return bail(fail(SS_EDEVICE, "stream creation failed"));
     for (auto &e : s->ev)
@@ -728,6 +768,42 @@ int ss_cg_solve(ss_solver *s, const double *b_dev, double *x_dev, double tol, in
     const int rc = ensure_hist(s, std::min<int64_t>((int64_t)maxit + 1, kHistMax));
     if (rc != SS_OK) return rc;
     return solve_core(s, b_dev, x_dev, tol, maxit, res, hist_host);
+}
+
+int ss_cg_solve_noalloc(ss_solver *s, const double *b_dev, double *x_dev, double tol, int32_t maxit,
+                        ss_result *res, double *hist_host)
+{
+    if (!s) return fail(SS_EINVAL, "solver is NULL");
+    if (!b_dev || !x_dev) return fail(SS_EINVAL, "b or x is NULL");
+    if (!(tol >= 0.0) || maxit < 0) return fail(SS_EINVAL, "need tol >= 0 and maxit >= 0");
+    if (s->opts.precision != SS_FP64)
+        return fail(SS_EUNSUPPORTED, "the no-allocation solve is available with SS_FP64 only");
+    if (hist_host && (int64_t)maxit + 1 > SS_NOALLOC_HIST_MAX)
+        return fail(SS_EINVAL, "with a history, maxit + 1 must not exceed SS_NOALLOC_HIST_MAX (" +
+                                   std::to_string(SS_NOALLOC_HIST_MAX) + ")");
+    if (!s->scratch)
+        return fail(SS_EDEVICE, "the device array of the no-allocation solve was not found at set-up");
+    // the run state and history in the device's fixed array, chunks launched
+    // one by one (no graph is instantiated); the whole state is written at
+    // the start of the solve, history entries before they are read
+    DevState *const st = reinterpret_cast<DevState *>(s->scratch);
+    double *const hist = hist_host ? reinterpret_cast<double *>(static_cast<char *>(s->scratch) + kScratchState)
+                                   : nullptr;
+    DevState *const st0 = s->st;
+    double *const hist0 = s->hist;
+    const int32_t cap0 = s->hist_cap, graph0 = s->opts.use_graph;
+    s->st = st;
+    s->run64.st = st;
+    s->hist = hist;
+    s->hist_cap = hist ? maxit + 1 : 0;
+    s->opts.use_graph = 0;
+    const int rc = solve_core(s, b_dev, x_dev, tol, maxit, res, hist_host);
+    s->st = st0;
+    s->run64.st = st0;
+    s->hist = hist0;
+    s->hist_cap = cap0;
+    s->opts.use_graph = graph0;
+    return rc;
 }
 
 int ss_cg_apply(ss_solver *s, const double *x_dev, double *y_dev)
