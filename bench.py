@@ -522,13 +522,18 @@ def variant_beyond_mall(ss, torch, reps: int, tol: float) -> dict:
     spmv_ms, spmv_bytes = ss.ss_cg_time_spmv(s, 20)
     n_loc = s.info()["n_loc"]
     survey_bytes = 12.0 * A.nnz + 20.0 * n_loc
+    st_ms, st_bytes = ss.ss_stream_rate(n_loc, 7, 20)
+    ceil_gbps = st_bytes / (st_ms * 1e-3) / 1e9
     out = {"workload": w.name, "n": int(A.n), "nnz": int(A.nnz), "n_loc": int(n_loc), "ms": round(ms, 3),
            "status": r.status, "iterations": r.iterations, "true_relres": true,
            "us_per_iteration": round(ms * 1e3 / max(r.iterations, 1), 2),
            "step_spmv_us": round(spmv_ms * 1e3, 2), "step_algorithmic_bytes": int(spmv_bytes),
            "step_gbps": round(spmv_bytes / (spmv_ms * 1e-3) / 1e9, 1),
            "frac": round(spmv_bytes / (spmv_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-           "frac_spmv_only": round(survey_bytes / (spmv_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+           "frac_spmv_only": round(survey_bytes / (spmv_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+           "stream_ceiling_gbps": round(ceil_gbps, 1),
+           "stream_ceiling_frac": round(ceil_gbps / HBM_PEAK_GBS, 4),
+           "step_frac_of_ceiling": round(spmv_bytes / (spmv_ms * 1e-3) / 1e9 / ceil_gbps, 4)}
     print(f"# beyond MALL {w.name}: {ms:.3f} ms, {r.iterations} iterations, step {spmv_ms * 1e3:.1f} us "
           f"({out['frac']:.3f} of 8 TB/s)", file=sys.stderr, flush=True)
     del s
@@ -654,6 +659,13 @@ def main_measurement(args, ss, torch, config):
             "stream_copy_gbps": round(stream_copy_gbps(torch), 1),
         },
     }
+    # the same bytes per row streamed without the step's gathers: the ceiling
+    # the step is held to on this device
+    st_ms, st_bytes = ss.ss_stream_rate(n_loc, 7, 20)
+    out["roofline"]["stream_ceiling"] = {
+        "gbps": round(st_bytes / (st_ms * 1e-3) / 1e9, 1), "rows": int(n_loc), "slots": 7,
+        "what": "gather-free stream of the CG step's pattern (7 values + 3 vector reads + 3 vector writes per row)",
+        "step_frac_of_ceiling": round(achieved / (st_bytes / (st_ms * 1e-3) / 1e9), 4)}
     if not args.no_cpu_baseline:
         import oracle as O
 

@@ -319,6 +319,18 @@ int ss_cg_grad_vals(ss_solver *s, const double *lambda_dev, const double *x_dev,
  * and x; the two-launch step also reads p back). */
 int ss_cg_time_spmv(ss_solver *s, int32_t reps, double *ms_per_launch, double *bytes_per_launch);
 
+/* Measurement: the rate at which the current device streams the bytes of the
+ * CG step without its gathers.  rows (>= 64, rounded down to a multiple of
+ * 64) rows in chunks of 64 with `slots` (5, 7, 9 or 27) FP64 values per row
+ * stored as the SELL-64 matrix stores them, one read each of three FP64
+ * vectors and one write each of three, on the CG step's persistent grid;
+ * reps timed back-to-back launches on hip_stream (NULL = default stream).
+ * *ms_per_launch: average launch time; *bytes_per_launch (may be NULL):
+ * rows * (8 slots + 48).  Allocates and frees its own buffers.
+ * Errors: SS_EINVAL, SS_ENOMEM, SS_EDEVICE. */
+int ss_stream_rate(int64_t rows, int32_t slots, int32_t reps, void *hip_stream, double *ms_per_launch,
+                   double *bytes_per_launch);
+
 /* Sizes of the device problem (any pointer may be NULL): matrix_format is
  * the SS_MAT_SELL / SS_MAT_CSR storage chosen, stored the entries it holds
  * (SELL: including the chunk padding). */

@@ -99,6 +99,7 @@ def lib() -> C.CDLL:
         "ss_cg_grad_vals": (C.c_int, [P, P, P, P]),
         "ss_cg_time_spmv": (C.c_int, [P, i32, P, P]),
         "ss_cg_info": (C.c_int, [P, P, P, P, P, P]),
+        "ss_stream_rate": (C.c_int, [i64, i32, i32, P, P, P]),
         "ss_cg_path": (C.c_int, [P, P]),
         "ss_cg_destroy": (None, [P]),
         "ss_band_size": (C.c_int, [P, i32, i32, i32, P, P, P]),
@@ -429,6 +430,17 @@ def ss_cg_apply_f32(s: Solver, x, y=None):
     y = torch.empty_like(x) if y is None else y
     _check(lib().ss_cg_apply_f32(s.h, _dev_f32(x, s.n, "x"), _dev_f32(y, s.n, "y")), "ss_cg_apply_f32")
     return y
+
+
+def ss_stream_rate(rows: int, slots: int, reps: int = 20) -> tuple:
+    """(ms per launch, bytes per launch) of the CG step's streaming pattern
+    without gathers on the current device and stream."""
+    torch = _torch()
+    ms, nb = C.c_double(), C.c_double()
+    stream = torch.cuda.current_stream()
+    _check(lib().ss_stream_rate(int(rows), int(slots), int(reps), C.c_void_p(stream.cuda_stream), C.byref(ms),
+                                C.byref(nb)), "ss_stream_rate")
+    return ms.value, nb.value
 
 
 def ss_cg_set_values(s: Solver, vals) -> None:
