@@ -211,7 +211,7 @@ struct SmallMat {
 
 inline size_t small_lds_bytes(int32_t n_loc, int32_t n_if, int32_t ngamma, int32_t n_copies)
 {
-    return sizeof(double) * (3 * (size_t)n_loc + (size_t)n_if + 2 * (kSmallThreads / 64)) +
+    return sizeof(double) * (3 * (size_t)n_loc + (size_t)n_if + 2 * (kSmallThreads / 64) + 256) +
            sizeof(int32_t) * ((size_t)n_if + (size_t)ngamma + 1 + (size_t)n_copies);
 }
 // Rows per thread of the kernel for `rows_needed` rows of `width` slots, 0

@@ -28,21 +28,51 @@
 #include "device_common.h"
 
 #include <cmath>
+#include <cstdint>
 
 namespace ss {
 namespace {
 
 constexpr int kSW = kSmallThreads / 64;  // waves of the workgroup
+constexpr int kHistRing = 256;           // residual history entries staged in LDS
+
+// A lane's value from another lane by a DPP move (CTRL, rows ROW_MASK); lanes
+// without a source, or outside the rows, get +0.  Both halves of the double
+// move the same way.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ double dpp_f64(double v)
+{
+    const uint64_t u = __builtin_bit_cast(uint64_t, v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)u, CTRL, ROW_MASK, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(u >> 32), CTRL, ROW_MASK, 0xf, false);
+    return __builtin_bit_cast(double, ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+
+// Sum over the 64 lanes of a wave in a fixed order, the total in lane 63:
+// lanes pair up (quad_perm 1,0,3,2), then pairs (2,3,0,1), then each 16-lane
+// row shifts by 4 and by 8, lane 15 of each row feeds the next row and lane 31
+// the upper half (row_bcast 15 and 31, gfx9 DPP).  Register moves instead of
+// LDS permutes.
+__device__ __forceinline__ double wave_sum_last(double v)
+{
+    v = v + dpp_f64<0xb1, 0xf>(v);   // quad_perm: 1, 0, 3, 2
+    v = v + dpp_f64<0x4e, 0xf>(v);   // quad_perm: 2, 3, 0, 1
+    v = v + dpp_f64<0x114, 0xf>(v);  // row_shr: 4
+    v = v + dpp_f64<0x118, 0xf>(v);  // row_shr: 8
+    v = v + dpp_f64<0x142, 0xa>(v);  // row_bcast: 15 into rows 1 and 3
+    v = v + dpp_f64<0x143, 0xc>(v);  // row_bcast: 31 into rows 2 and 3
+    return v;
+}
 
 // Fixed-order workgroup sum, every thread gets the total.  Two alternating
 // slot sets: a set is rewritten two sums later, after a barrier that every
 // reader of its previous values has passed.
 __device__ __forceinline__ double small_sum(double v, double *ws, int &set)
 {
-    v = dev::wave_sum(v);
+    v = wave_sum_last(v);
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     double *slot = ws + set * kSW;
-    if (lane == 0) slot[w] = v;
+    if (lane == 63) slot[w] = v;
     __syncthreads();
     double t = 0.0;
 #pragma unroll
@@ -69,8 +99,9 @@ __global__ __launch_bounds__(kSmallThreads) void k_cg_small(int32_t n_loc, int32
     double *rl = xl + n_loc;        // r, n_loc
     double *qif = rl + n_loc;       // unassembled products of the interface positions, n_if
     double *ws = qif + n_if;        // 2 * kSW sum slots
+    double *hring = ws + 2 * kSW;   // kHistRing residual history entries
     // the interface copy lists, read from LDS inside the iterations
-    int32_t *grp_l = reinterpret_cast<int32_t *>(ws + 2 * kSW);  // pos_grp, n_if
+    int32_t *grp_l = reinterpret_cast<int32_t *>(hring + kHistRing);  // pos_grp, n_if
     int32_t *cptr_l = grp_l + n_if;                                // copy_ptr, ngamma + 1
     int32_t *cpos_l = cptr_l + ngamma + 1;                         // copy_pos, n_copies
     const int t = threadIdx.x;
@@ -115,6 +146,22 @@ __global__ __launch_bounds__(kSmallThreads) void k_cg_small(int32_t n_loc, int32
     const int kmax = st->kmax;
     double *hist = st->hist;
     const int hcap = st->hist_cap;
+    // The residual history goes to a ring in LDS and reaches memory in blocks
+    // written by wave 0: a global store inside the loop would make every
+    // barrier wait for it.  Entries [flushed, k] are in the ring (k - flushed
+    // < kHistRing); every thread tracks `flushed` the same way.
+    int flushed = 0, last = -1;  // last: the highest entry recorded
+    auto flush = [&](int upto) {  // entries [flushed, upto) to memory
+        if (hist && (threadIdx.x >> 6) == 0)
+            for (int j = flushed + (int)(threadIdx.x & 63); j < upto && j < hcap; j += 64)
+                hist[j] = hring[j & (kHistRing - 1)];
+        flushed = upto;
+    };
+    auto record = [&](int k, double v) {
+        if (k - flushed >= kHistRing) flush(k);
+        if (threadIdx.x == 0) hring[k & (kHistRing - 1)] = v;
+        last = k;
+    };
     int k_it = 0, restarts = -1, status = ST_RUNNING;
     double bb = 0.0, stop = 0.0, rr = 0.0;
 
@@ -158,7 +205,7 @@ __global__ __launch_bounds__(kSmallThreads) void k_cg_small(int32_t n_loc, int32
                 break;
             }
             if (bb == 0.0) {
-                if (t == 0 && hist && hcap > 0) hist[0] = 0.0;
+                record(0, 0.0);
                 status = ST_ZERO_RHS;
                 break;
             }
@@ -168,7 +215,7 @@ __global__ __launch_bounds__(kSmallThreads) void k_cg_small(int32_t n_loc, int32
             status = ST_BREAKDOWN;
             break;
         }
-        if (t == 0 && hist && k_it < hcap) hist[k_it] = sqrt(rr / bb);
+        record(k_it, sqrt(rr / bb));
         if (sqrt(rr) <= stop) {
             status = ST_CONVERGED;
             break;
@@ -214,12 +261,12 @@ __global__ __launch_bounds__(kSmallThreads) void k_cg_small(int32_t n_loc, int32
                 }
             }
             const double rr_new = small_sum(arn, ws, set);
-            ++k_it;
-            if (!isfinite(rr_new)) {
+            if (!isfinite(rr_new)) {  // as the streaming path: the step is not counted
                 status = ST_BREAKDOWN;
                 break;
             }
-            if (t == 0 && hist && k_it < hcap) hist[k_it] = sqrt(rr_new / bb);
+            ++k_it;
+            record(k_it, sqrt(rr_new / bb));
             const double beta = rr_new / rr;
             rr = rr_new;
             if (sqrt(rr_new) <= stop) break;  // recompute the residual, restart if needed
@@ -240,6 +287,7 @@ __global__ __launch_bounds__(kSmallThreads) void k_cg_small(int32_t n_loc, int32
         const int i = t + k * kSmallThreads;
         if (i < n_loc) x[i] = xl[i];
     }
+    flush(last + 1);  // the recorded entries not yet in memory
     if (t == 0) {
         st->bb = bb;
         st->stop = stop;
