@@ -303,6 +303,18 @@ def variant_batched(ss, torch, reps: int, tol: float, one_by_one: bool = True) -
                              threads=cpu_threads())
             errs.append(rel_err(xh[offs[si] * nrhs + j: offs[si + 1] * nrhs: nrhs], xr))
         out["error_vs_oracle_sampled"] = {"max": max(errs), "pairs": [[int(si), int(si % nrhs)] for si in pick]}
+    # the same solve with every iteration in one launch (persistent schedule,
+    # the tuned tiles): same bits, timed for comparison
+    x_tuned = x.clone()
+    ss.ss_batch_set_tuning(bt, chosen["tile_granules"], 0, chosen["unroll"], chosen["check_every"],
+                           ss.SS_BATCH_PERSISTENT)
+    ms_p, (res_p, _) = _timed(torch, run, 1)
+    out["persistent_one_launch_ms"] = round(ms_p, 3)
+    out["persistent_bitwise_equal"] = bool(torch.equal(x, x_tuned)) and \
+        [r.iterations for r in res_p] == [r.iterations for r in res]
+    ss.ss_batch_set_tuning(bt, **chosen)
+    print(f"# batched, one persistent launch: {ms_p:.3f} ms, bitwise equal {out['persistent_bitwise_equal']}",
+          file=sys.stderr, flush=True)
     if not one_by_one:
         return out
     # one by one: one solver per system (set up outside the timing), every pair solved separately

@@ -391,14 +391,15 @@ int ss_band_setup(const ss_csr *A, int32_t kind, int32_t nbands, const ss_opts *
 /* ------------------------------------------------------- batched solver */
 /*
  * Many independent SPD systems, each with nrhs right-hand sides, solved
- * together: every CG iteration of every (system, right-hand side) pair is one
- * pass of two kernels over all systems still running, so the launch cost is
- * shared by the whole batch and one read of each matrix serves all its
- * right-hand sides.  Each pair runs exactly the CG of ss_cg_solve on its own
+ * together: one pass of the batched update and SpMV code over a system's
+ * tiles advances all of its (system, right-hand side) pairs by one CG
+ * iteration, so one read of each matrix serves all its right-hand sides, and
+ * all systems share the launches (two per iteration, or one for all
+ * iterations; see the schedules below).  Each pair runs exactly the CG of ss_cg_solve on its own
  * (Algorithm 3, M = I, one sub-domain): own scalars, own stopping test,
  * recomputed-residual restarts, own iteration count; a pair that stops keeps
  * its x while the others go on, and a system whose pairs have all stopped
- * drops out of the launches.  Only the summation order of the dot products
+ * drops out.  Only the summation order of the dot products
  * differs from one-by-one solves.
  *
  * Vector layout at the boundary (b_dev, x_dev): device, FP64, the systems'
@@ -408,15 +409,33 @@ int ss_band_setup(const ss_csr *A, int32_t kind, int32_t nbands, const ss_opts *
  */
 typedef struct ss_batch ss_batch;
 
+/* Schedules of the batched iterations.
+ * SS_BATCH_CHUNKED: every iteration is two launches over the tiles of all
+ *   systems still running, captured in graphs of check_every iterations; the
+ *   host polls between graphs and the list of running systems is rebuilt.
+ * SS_BATCH_PERSISTENT: all iterations in one launch.  Each system moves
+ *   through its own update / SpMV phases; a free workgroup claims the next
+ *   tile of the first system (largest first) that has one, and the
+ *   workgroup finishing a phase's last tile starts the system's next phase,
+ *   so no system waits for the others and no launch boundary drains the
+ *   device.  Every hand-over of a phase between workgroups costs a
+ *   device-scope release and acquire (an L2 write-back and invalidation on
+ *   this multi-XCD device), which makes it slower than the chunked
+ *   schedule on large batches; the autotuner times both.  check_every is not
+ *   used. */
+enum { SS_BATCH_CHUNKED = 0, SS_BATCH_PERSISTENT = 1 };
+
 /* Launch shape of the batched kernels.  It changes timing only: results are
  * bitwise the same for every choice (all partial sums are taken over fixed
- * 512-row granules). */
+ * 512-row granules, each system's phases run in the same order). */
 typedef struct {
     int32_t tile_granules; /* 512-row granules per workgroup tile: 1, 2, 4, 8   */
     int32_t grid;          /* workgroups per launch, a multiple of 8 in
-                              [8, 65536]; 0 = one per tile                     */
+                              [8, 65536]; 0 = one per tile (chunked) or as
+                              many as are resident at once (persistent)     */
     int32_t unroll;        /* matrix entries loaded per lane before use: 4, 5, 8 */
     int32_t check_every;   /* CG iterations between host polls, even, 2..1024  */
+    int32_t schedule;      /* SS_BATCH_CHUNKED or SS_BATCH_PERSISTENT          */
 } ss_batch_tuning;
 
 typedef struct {
@@ -429,8 +448,8 @@ typedef struct {
  * and in range, pattern and values symmetric) for nrhs right-hand sides each (1, 2 or 4; pad to 4 with zero columns otherwise: a zero
  * right-hand side costs nothing) to the current HIP device.  Rows may hold at
  * most 255 entries.  o: NULL or options (only the allocator fields and
- * check_every are used).  Default tuning: 2 granules per tile, one workgroup
- * per tile, unroll 8, check_every 32.
+ * check_every are used).  Default tuning: 2 granules per tile, chunked, one
+ * workgroup per tile, unroll 8, check_every 32.
  * Errors: SS_EINVAL, SS_EUNSUPPORTED (nrhs, row length), SS_ENOMEM,
  * SS_EDEVICE.
  */
@@ -456,9 +475,10 @@ int ss_batch_get_tuning(const ss_batch *bt, ss_batch_tuning *t);
 
 /*
  * ss_batch_tune -- the autotuner.  Times each candidate launch shape (tile
- * granules 1/2/4/8 x grid one-per-tile/2048/1024 x unroll 4/5/8) over `iters`
- * CG iterations (<= 0: 8) of this batch with right-hand sides b_dev, every
- * pair running from x = 0 (x_dev is not touched), and keeps the fastest.
+ * granules 1/2/4/8 x unroll 4/5/8 x {chunked with grid one-per-tile / 2048 /
+ * 1024, persistent with the resident grid}: 48 shapes) over `iters` CG
+ * iterations (<= 0: 8) of this batch with right-hand sides b_dev, every pair
+ * running from x = 0 (x_dev is not touched), and keeps the fastest.
  * The choice is remembered for the process, keyed by the batch structure
  * (row counts, entry counts, nrhs, device): a later call for a batch of the
  * same structure takes it without timing, unless force is nonzero.

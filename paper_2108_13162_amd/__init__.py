@@ -31,6 +31,7 @@ SS_MAT_AUTO, SS_MAT_SELL, SS_MAT_CSR = 0, 1, 2
 SS_PRECOND_NONE, SS_PRECOND_JACOBI = 0, 1
 SS_SMALL_AUTO, SS_SMALL_OFF = 0, 1
 SS_PATH_STREAM, SS_PATH_SMALL = 0, 1
+SS_BATCH_CHUNKED, SS_BATCH_PERSISTENT = 0, 1
 
 _ALLOC_T = C.CFUNCTYPE(C.c_void_p, C.c_void_p, C.c_size_t)
 _FREE_T = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
@@ -58,7 +59,7 @@ class ss_result(C.Structure):
 
 class ss_batch_tuning(C.Structure):
     _fields_ = [("tile_granules", C.c_int32), ("grid", C.c_int32), ("unroll", C.c_int32),
-                ("check_every", C.c_int32)]
+                ("check_every", C.c_int32), ("schedule", C.c_int32)]
 
 
 class ss_batch_trial(C.Structure):
@@ -498,7 +499,8 @@ class Batch:
 
 
 def _tuning_dict(t: ss_batch_tuning) -> dict:
-    return {"tile_granules": t.tile_granules, "grid": t.grid, "unroll": t.unroll, "check_every": t.check_every}
+    return {"tile_granules": t.tile_granules, "grid": t.grid, "unroll": t.unroll, "check_every": t.check_every,
+            "schedule": t.schedule}
 
 
 def ss_batch_setup(systems, nrhs: int = 4, opts: Optional[ss_opts] = None, device=None) -> Batch:
@@ -549,8 +551,9 @@ def ss_batch_tune(bt: Batch, b, iters: int = 8, force: bool = False):
                                   for i in range(nt.value)]
 
 
-def ss_batch_set_tuning(bt: Batch, tile_granules: int, grid: int, unroll: int, check_every: int) -> None:
-    t = ss_batch_tuning(tile_granules, grid, unroll, check_every)
+def ss_batch_set_tuning(bt: Batch, tile_granules: int, grid: int, unroll: int, check_every: int,
+                        schedule: int = SS_BATCH_CHUNKED) -> None:
+    t = ss_batch_tuning(tile_granules, grid, unroll, check_every, schedule)
     _check(lib().ss_batch_set_tuning(bt.h, C.byref(t)), "ss_batch_set_tuning")
 
 

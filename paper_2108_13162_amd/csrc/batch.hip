@@ -125,16 +125,6 @@ __device__ __forceinline__ void st_row(double *__restrict__ v, int row, const do
     }
 }
 
-template <int NR>
-__device__ __forceinline__ double pick(const double (&a)[NR], int j)
-{
-    double v = a[0];
-#pragma unroll
-    for (int i = 1; i < NR; ++i)
-        if (j == i) v = a[i];
-    return v;
-}
-
 // The pair statuses of system s into LDS; true if any pair is running.
 template <int NR>
 __device__ __forceinline__ bool load_sys_status(const BState &S, int s, int32_t *sh)
@@ -252,23 +242,26 @@ __device__ __forceinline__ void x_update_rows(double *__restrict__ x, const doub
     }
 }
 
+template <int NR>
+constexpr int ring_rows()
+{
+    return kRingBytes / (8 * NR);  // a power of two
+}
+
+// One tile t of the SpMV (whole workgroup).  ws: kWaves * NR, sh_st: NR,
+// ring: ring_rows<NR>() * NR doubles of LDS.
 template <int NR, int U, int MODE, bool ALL_STAGED>
-__global__ __launch_bounds__(kWG) void k_bspmv(BMat M, BTiles T, BState S, const double *__restrict__ pin,
-                                               const double *__restrict__ r, double *__restrict__ pout,
-                                               double *__restrict__ q, double *__restrict__ x,
-                                               double *__restrict__ part_a, const double *__restrict__ part_b,
-                                               int slot)
+__device__ __forceinline__ void spmv_tile(const BMat &M, const BTiles &T, const BState &S, int t,
+                                          const double *__restrict__ pin, const double *__restrict__ r,
+                                          double *__restrict__ pout, double *__restrict__ q, double *__restrict__ x,
+                                          double *__restrict__ part_a, const double *__restrict__ part_b, int slot,
+                                          double *ws, int32_t *sh_st, double *ring)
 {
     constexpr bool CG = MODE != M_PLAIN;
-    constexpr int W = kRingBytes / (8 * NR);  // ring rows (power of two)
+    constexpr int W = ring_rows<NR>();
     constexpr int HMAX = (W - kGranRows) / 2;
-    __shared__ double ws[kWaves * NR];
-    __shared__ int32_t sh_st[NR];
-    __shared__ __align__(16) double ring[W * NR];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const Share sh = list_share(*T.nlist);
-    for (int i = sh.i; i < sh.end; i += sh.step) {
-        const int t = T.list[i];
+    {
         const int s = T.tile_sys[t];
         double beta[NR];
 #pragma unroll
@@ -288,7 +281,7 @@ __global__ __launch_bounds__(kWG) void k_bspmv(BMat M, BTiles T, BState S, const
             // the system's first tile: the x update is owed all the same)
             if (!load_sys_status<NR>(S, s, sh_st)) {
                 if (MODE == M_STEP && xupd) x_update_rows<NR>(x, pin, own0, own1, al);
-                continue;
+                return;
             }
             bool any = false;
             if (MODE == M_STEP) {
@@ -333,7 +326,7 @@ __global__ __launch_bounds__(kWG) void k_bspmv(BMat M, BTiles T, BState S, const
             if (!any) {
                 // every pair stops here: the previous update's x still lands
                 if (MODE == M_STEP && xupd) x_update_rows<NR>(x, pin, own0, own1, al);
-                continue;
+                return;
             }
         }
         const int g0 = T.tile_g0[t], g1 = T.tile_g0[t + 1];
@@ -488,25 +481,39 @@ __global__ __launch_bounds__(kWG) void k_bspmv(BMat M, BTiles T, BState S, const
     }
 }
 
-// ---- alpha + x / r update + (r, r) partials ----------------------------------
-
-template <int NR>
-__global__ __launch_bounds__(kWG) void k_bupdate(BMat M, BTiles T, BState S, double *__restrict__ r,
-                                                 const double *__restrict__ q, double *__restrict__ part_b,
-                                                 const double *__restrict__ part_a, int slot)
+template <int NR, int U, int MODE, bool ALL_STAGED>
+__global__ __launch_bounds__(kWG) void k_bspmv(BMat M, BTiles T, BState S, const double *__restrict__ pin,
+                                               const double *__restrict__ r, double *__restrict__ pout,
+                                               double *__restrict__ q, double *__restrict__ x,
+                                               double *__restrict__ part_a, const double *__restrict__ part_b,
+                                               int slot)
 {
-    constexpr int NI = kGranRows * NR / kWG;  // elements per thread of a full granule
     __shared__ double ws[kWaves * NR];
     __shared__ int32_t sh_st[NR];
-    const int jt = threadIdx.x % NR;
+    __shared__ __align__(16) double ring[ring_rows<NR>() * NR];
     const Share sh = list_share(*T.nlist);
-    for (int i = sh.i; i < sh.end; i += sh.step) {
-        const int t = T.list[i];
+    for (int i = sh.i; i < sh.end; i += sh.step)
+        spmv_tile<NR, U, MODE, ALL_STAGED>(M, T, S, T.list[i], pin, r, pout, q, x, part_a, part_b, slot, ws, sh_st,
+                                           ring);
+}
+
+// ---- alpha + x / r update + (r, r) partials ----------------------------------
+
+// One tile t of the update (whole workgroup).  ws: kWaves * NR, sh_st: NR.
+template <int NR>
+__device__ __forceinline__ void update_tile(const BMat &M, const BTiles &T, const BState &S, int t,
+                                            double *__restrict__ r, const double *__restrict__ q,
+                                            double *__restrict__ part_b, const double *__restrict__ part_a, int slot,
+                                            double *ws, int32_t *sh_st)
+{
+    constexpr int NI = kGranRows * NR / kWG;  // elements per thread of a full granule
+    const int jt = threadIdx.x % NR;
+    {
         const int s = T.tile_sys[t];
         if (!load_sys_status<NR>(S, s, sh_st)) {
             // nothing ran: the next step owes no x update for this system
             if (T.tile_g0[t] == T.sys_g0[s] && threadIdx.x < NR) S.alpha[s * NR + threadIdx.x] = 0.0;
-            continue;
+            return;
         }
         const int g0 = T.tile_g0[t], g1 = T.tile_g0[t + 1];
         // operands of the first granule, loaded before alpha is known
@@ -521,15 +528,15 @@ __global__ __launch_bounds__(kWG) void k_bupdate(BMat M, BTiles T, BState S, dou
                 qv[k] = q[e];
             }
         }
-        double pAp[NR], alpha[NR], runv[NR];
+        double pAp[NR];
         sys_sum<NR>(part_a, T.sys_g0[s], T.sys_g0[s + 1], ws, pAp);
         const bool lead = T.tile_g0[t] == T.sys_g0[s] && threadIdx.x == 0;
         const double *rrc = rr_slot(S, slot);
-        bool any = false;
+        bool any = false, run = false;
+        double a = 0.0;  // alpha of this thread's right-hand side jt
 #pragma unroll
         for (int j = 0; j < NR; ++j) {
-            alpha[j] = 0.0;
-            runv[j] = 0.0;
+            double al = 0.0;
             if (sh_st[j] == BS_RUNNING) {
                 const int pr = s * NR + j;
                 if (!(pAp[j] > 0.0) || !isfinite(pAp[j])) {
@@ -538,17 +545,16 @@ __global__ __launch_bounds__(kWG) void k_bupdate(BMat M, BTiles T, BState S, dou
                         atomicSub(S.nrun, 1);
                     }
                 } else {
-                    alpha[j] = rrc[pr] / pAp[j];
-                    runv[j] = 1.0;
+                    al = rrc[pr] / pAp[j];
                     any = true;
+                    if (j == jt) run = true;
                 }
             }
+            if (j == jt) a = al;
             // the next CG step applies x += alpha p with these (0: no change)
-            if (lead) S.alpha[s * NR + j] = alpha[j];
+            if (lead) S.alpha[s * NR + j] = al;
         }
-        if (!any) continue;
-        const double a = pick<NR>(alpha, jt);
-        const bool run = pick<NR>(runv, jt) != 0.0;
+        if (!any) return;
         for (int g = g0; g < g1; ++g) {
             if (g != g0) {
                 e0 = M.crow[T.gran_c0[g]] * NR;
@@ -586,6 +592,219 @@ __global__ __launch_bounds__(kWG) void k_bupdate(BMat M, BTiles T, BState S, dou
             granule_store_strided<NR>(accv, part_b, g, ws);
         }
     }
+}
+
+template <int NR>
+__global__ __launch_bounds__(kWG) void k_bupdate(BMat M, BTiles T, BState S, double *__restrict__ r,
+                                                 const double *__restrict__ q, double *__restrict__ part_b,
+                                                 const double *__restrict__ part_a, int slot)
+{
+    __shared__ double ws[kWaves * NR];
+    __shared__ int32_t sh_st[NR];
+    const Share sh = list_share(*T.nlist);
+    for (int i = sh.i; i < sh.end; i += sh.step) update_tile<NR>(M, T, S, T.list[i], r, q, part_b, part_a, slot, ws, sh_st);
+}
+
+// ---- all iterations in one launch ----------------------------------------------
+//
+// The iterations of every system run inside one persistent launch, each
+// system at its own pace: phase seq of system s is the update of its step
+// seq / 2 when seq is even, the SpMV step after that update when odd (slot
+// and p ping-pong from seq / 2 as in the chunked launches).  A phase is the
+// system's tiles, claimed one at a time by whichever workgroup is free: the
+// claim word of s holds (seq << 32) | next unclaimed tile, and an atomic add
+// on it hands out the tile.  The workgroup that finishes the last tile of a
+// phase publishes the next one (after an update: the SpMV step; after a step:
+// the next update while a pair of s runs, else s retires).  Phases of one
+// system never overlap, so the kernels' per-tile code runs unchanged and the
+// results are bitwise those of the chunked launches; systems do not wait for
+// each other, and no workgroup waits for a particular other one: a free
+// workgroup takes a tile of the first system in priority order (largest
+// first) that has one, else polls.  Every workgroup leaves when all systems
+// have retired, or when no phase has finished for a long time (an error
+// flag the host reports; it never happens in a correct run).
+
+constexpr uint32_t kRetired = 0xffffffffu;
+constexpr uint32_t kStallPolls = 1u << 22;  // polls without a finished phase before giving up
+constexpr int kSpread = 8;                  // claimable systems a free workgroup chooses among
+
+struct BFlow {
+    unsigned long long *claim;  // [nsys] (seq << 32) | next tile
+    int32_t *done;              // [nsys] finished tiles of the current phase
+    const int32_t *prio;        // [nsys] systems in claiming order
+    const int32_t *sys_t0;      // [nsys+1] tiles of system s: sys_t0[s] .. sys_t0[s+1]
+    int32_t *ctl;               // [0] systems not retired, [1] finished phases, [2] stall flag
+    int32_t nsys;
+};
+
+__device__ __forceinline__ unsigned long long claim_load(const unsigned long long *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Claims a tile (whole workgroup).  False when every system has retired or
+// the stall limit was reached.  sh: 5 + kSpread ints of LDS.
+//
+// A workgroup that finds nothing to claim waits for the count of finished
+// phases to move (every publication of a phase, and every retirement, is
+// counted after it is made), then looks again; while it waits it polls that
+// one counter, sleeping between polls.
+__device__ bool flow_claim(const BFlow &F, int &s_out, uint32_t &seq_out, int &tile_out, int32_t *sh)
+{
+    uint32_t polls = 0;  // thread 0: polls without a finished phase
+    int32_t seen = -1;   // thread 0: finished-phase count of the last look
+    for (;;) {
+        __syncthreads();  // sh is free
+        if (threadIdx.x < kSpread) sh[5 + threadIdx.x] = INT_MAX;
+        __syncthreads();
+        // the first kSpread systems in priority order with a tile left (one
+        // candidate per wave and lane position: lane l of the first wave
+        // that holds one); a workgroup takes the one its index selects, so
+        // claims spread over several counters
+        for (int i = (int)threadIdx.x; i < F.nsys; i += kWG) {
+            const int s = F.prio[i];
+            const unsigned long long c = claim_load(&F.claim[s]);
+            if ((uint32_t)(c >> 32) != kRetired && (uint32_t)c < (uint32_t)(F.sys_t0[s + 1] - F.sys_t0[s])) {
+                atomicMin(&sh[5 + (i & (kSpread - 1))], i);
+                break;  // this thread's later entries come after i
+            }
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            int32_t res = 0;  // 0: look again, 1: claimed, 2: leave
+            int nc = 0;
+#pragma unroll
+            for (int k = 0; k < kSpread; ++k) nc += sh[5 + k] != INT_MAX;
+            int i = INT_MAX;
+            if (nc) {
+                int want = (int)(blockIdx.x % (unsigned)nc);
+#pragma unroll
+                for (int k = 0; k < kSpread; ++k)
+                    if (sh[5 + k] != INT_MAX) {
+                        if (want == 0) i = sh[5 + k];
+                        --want;
+                    }
+            }
+            if (i != INT_MAX) {
+                const int s = F.prio[i];
+                const unsigned long long old = __hip_atomic_fetch_add(&F.claim[s], 1ull, __ATOMIC_RELAXED,
+                                                                      __HIP_MEMORY_SCOPE_AGENT);
+                const uint32_t seq = (uint32_t)(old >> 32), tile = (uint32_t)old;
+                if (seq != kRetired && tile < (uint32_t)(F.sys_t0[s + 1] - F.sys_t0[s])) {
+                    sh[1] = s;
+                    sh[2] = (int32_t)seq;
+                    sh[3] = (int32_t)tile;
+                    res = 1;
+                    // the previous phase's vectors, partials and scalars,
+                    // written by other workgroups, are visible from here on
+                    // (one invalidation of this CU's L1 and the L2 serves the
+                    // workgroup's waves, which read after the barrier below)
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                }
+            }
+            // nothing claimed: look again at once if a tile was seen (another
+            // workgroup was faster) or phases finished since the last look,
+            // else wait until they do
+            while (res == 0) {
+                const int32_t fin = __hip_atomic_load(&F.ctl[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+                if (fin != seen) {
+                    seen = fin;
+                    polls = 0;
+                    if (dev::flag_load(&F.ctl[0]) == 0 || dev::flag_load(&F.ctl[2]) != 0) res = 2;
+                    break;
+                }
+                if (i != INT_MAX) break;
+                if (++polls > kStallPolls) {
+                    dev::flag_store(&F.ctl[2], 1);
+                    res = 2;
+                } else if ((polls & 255u) == 0 && dev::flag_load(&F.ctl[2]) != 0) {
+                    res = 2;
+                } else {
+                    __builtin_amdgcn_s_sleep(16);
+                }
+            }
+            sh[4] = res;
+        }
+        __syncthreads();
+        const int32_t res = sh[4];
+        if (res == 2) return false;
+        if (res == 1) {
+            s_out = sh[1];
+            seq_out = (uint32_t)sh[2];
+            tile_out = sh[3];
+            return true;
+        }
+    }
+}
+
+// After a tile of phase seq of system s (whole workgroup): the finisher of
+// the phase's last tile publishes the next phase or retires the system.
+template <int NR>
+__device__ void flow_finish(const BFlow &F, const BState &S, int s, uint32_t seq)
+{
+    // every wave's stores have reached the L2 before the barrier; one
+    // device-scope release (an L2 write-back) by thread 0 then covers them all
+    __builtin_amdgcn_s_waitcnt(dev::kWaitVmcnt0);
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    const int nt = F.sys_t0[s + 1] - F.sys_t0[s];
+    const int32_t old = __hip_atomic_fetch_add(&F.done[s], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (old != nt - 1) return;
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    bool next = true;
+    if (seq & 1u) {  // after a step: the statuses its first tile recorded
+        next = false;
+        for (int j = 0; j < NR; ++j) next = next || dev::flag_load(&S.status[s * NR + j]) == BS_RUNNING;
+    }
+    __hip_atomic_store(&F.done[s], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const unsigned long long word = (unsigned long long)(next ? seq + 1u : kRetired) << 32;
+    __hip_atomic_store(&F.claim[s], word, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    if (!next) __hip_atomic_fetch_add(&F.ctl[0], -1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    // counted after the publication (and retirement) it announces
+    __hip_atomic_fetch_add(&F.ctl[1], 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <int NR, int U, bool ALL_STAGED>
+__global__ __launch_bounds__(kWG) void k_bflow(BMat M, BTiles T, BState S, BFlow F, double *__restrict__ r,
+                                               double *__restrict__ q, double *__restrict__ x,
+                                               double *__restrict__ p0, double *__restrict__ p1,
+                                               double *__restrict__ part_a, double *__restrict__ part_b)
+{
+    __shared__ double ws[kWaves * NR];
+    __shared__ int32_t sh_st[NR];
+    __shared__ int32_t sh[5 + kSpread];
+    __shared__ __align__(16) double ring[ring_rows<NR>() * NR];
+    int s, tile;
+    uint32_t seq;
+    while (flow_claim(F, s, seq, tile, sh)) {
+        const int t = F.sys_t0[s] + tile;
+        const int slot = (int)((seq >> 1) & 1u);
+        if ((seq & 1u) == 0)
+            update_tile<NR>(M, T, S, t, r, q, part_b, part_a, slot, ws, sh_st);
+        else
+            spmv_tile<NR, U, M_STEP, ALL_STAGED>(M, T, S, t, slot ? p0 : p1, r, slot ? p1 : p0, q, x, part_a,
+                                                 part_b, slot, ws, sh_st, ring);
+        flow_finish<NR>(F, S, s, seq);
+    }
+}
+
+// Phase 0 for every system with a running pair, retired otherwise; counters.
+template <int NR>
+__global__ __launch_bounds__(kWG) void k_bflow_init(BState S, BFlow F)
+{
+    const int s = blockIdx.x * kWG + threadIdx.x;
+    if (s >= F.nsys) return;
+    bool run = false;
+    for (int j = 0; j < NR; ++j) run = run || dev::flag_load(&S.status[s * NR + j]) == BS_RUNNING;
+    F.claim[s] = run ? 0ull : (unsigned long long)kRetired << 32;
+    F.done[s] = 0;
+    if (run) atomicAdd(&F.ctl[0], 1);
+}
+
+__global__ __launch_bounds__(64) void k_bflow_reset(int32_t *ctl)
+{
+    if (threadIdx.x < 3) ctl[threadIdx.x] = 0;
 }
 
 // ---- fresh residual r = b - q (q = A x), partials (r, r) [and (b, b)] ------------
@@ -780,6 +999,7 @@ bool tuning_valid(const ss_batch_tuning &t)
     if (t.grid != 0 && (t.grid < 8 || t.grid > kGridLimit || t.grid % 8 != 0)) return false;
     if (t.unroll != 4 && t.unroll != 5 && t.unroll != 8) return false;
     if (t.check_every < 2 || t.check_every > 1024 || t.check_every % 2 != 0) return false;
+    if (t.schedule != SS_BATCH_CHUNKED && t.schedule != SS_BATCH_PERSISTENT) return false;
     return true;
 }
 
@@ -813,6 +1033,9 @@ struct ss_batch {
     int32_t *it0 = nullptr, *it1 = nullptr, *it_last = nullptr, *status = nullptr, *restarts = nullptr;
     int32_t *nrun = nullptr, *kmax = nullptr;
     double *alpha = nullptr;
+    // one-launch schedule
+    unsigned long long *claim = nullptr;
+    int32_t *done = nullptr, *prio = nullptr, *ctl = nullptr;
     int32_t *pinned = nullptr;  // host: polled running counts
     hipEvent_t ev[2] = {nullptr, nullptr};
     ss_batch_tuning tun{};
@@ -831,6 +1054,7 @@ struct ss_batch {
         return BState{rr0, rr1, it0, it1, bb, stop, rr_last, it_last, status, restarts, nrun, kmax, alpha};
     }
     int grid() const { return tun.grid ? tun.grid : std::max(8, (ntiles + 7) / 8 * 8); }
+    BFlow flow() const { return BFlow{claim, done, prio, sys_t0, ctl, nsys}; }
 };
 
 namespace {
@@ -1005,9 +1229,64 @@ int ensure_graph(ss_batch *b, int32_t pairs)
     return SS_OK;
 }
 
+template <int NR, int U, bool ALL_STAGED>
+int flow_launch(ss_batch *b)
+{
+    auto kern = k_bflow<NR, U, ALL_STAGED>;
+    int grid = b->tun.grid;
+    if (grid == 0) {
+        // every workgroup resident at once (not needed for progress: a
+        // workgroup never waits for another particular one)
+        int per_cu = 0, cus = 0;
+        SS_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kWG, 0));
+        SS_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, b->device));
+        grid = std::max(8, std::min(kGridLimit, std::max(1, per_cu) * std::max(1, cus)) / 8 * 8);
+    }
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(kWG), 0, b->stream, b->bmat(), b->tiles(true), b->state(), b->flow(),
+                       b->r, b->q, b->x, b->p0, b->p1, b->part_a, b->part_b);
+    return SS_OK;
+}
+
+template <int NR, int U>
+int flow_launch_s(ss_batch *b)
+{
+    return b->max_halo <= staged_halo(NR) ? flow_launch<NR, U, true>(b) : flow_launch<NR, U, false>(b);
+}
+
+template <int NR>
+int flow_t(ss_batch *b)
+{
+    hipLaunchKernelGGL(k_bflow_reset, dim3(1), dim3(64), 0, b->stream, b->ctl);
+    hipLaunchKernelGGL(k_bflow_init<NR>, dim3((b->nsys + kWG - 1) / kWG), dim3(kWG), 0, b->stream, b->state(),
+                       b->flow());
+    switch (b->tun.unroll) {
+    case 4: return flow_launch_s<NR, 4>(b);
+    case 5: return flow_launch_s<NR, 5>(b);
+    default: return flow_launch_s<NR, 8>(b);
+    }
+}
+
+// Every iteration of every running pair in one launch (no host polling).
+int iterate_flow(ss_batch *b)
+{
+    int rc;
+    switch (b->nrhs) {
+    case 1: rc = flow_t<1>(b); break;
+    case 2: rc = flow_t<2>(b); break;
+    default: rc = flow_t<4>(b); break;
+    }
+    if (rc != SS_OK) return rc;
+    SS_HIP(hipGetLastError());
+    SS_HIP(hipMemcpyAsync(&b->pinned[2], b->ctl + 2, sizeof(int32_t), hipMemcpyDeviceToHost, b->stream));
+    SS_HIP(hipStreamSynchronize(b->stream));
+    if (b->pinned[2] != 0) return fail(SS_EDEVICE, "batched solve: no phase finished within the stall limit");
+    return SS_OK;
+}
+
 // Iterates until no pair is running; chunks are queued one ahead of the poll.
 int iterate(ss_batch *b)
 {
+    if (b->tun.schedule == SS_BATCH_PERSISTENT) return iterate_flow(b);
     const int32_t chunk = b->tun.check_every;
     int rc = ensure_graph(b, chunk);
     if (rc != SS_OK) return rc;
@@ -1206,14 +1485,25 @@ int ss_batch_setup(int32_t nsys, const ss_csr *systems, int32_t nrhs, const ss_o
         (rc = alloc_dev(b, &b->bb, np)) || (rc = alloc_dev(b, &b->stop, np)) || (rc = alloc_dev(b, &b->rr_last, np)) ||
         (rc = alloc_dev(b, &b->it0, np)) || (rc = alloc_dev(b, &b->it1, np)) || (rc = alloc_dev(b, &b->it_last, np)) ||
         (rc = alloc_dev(b, &b->status, np)) || (rc = alloc_dev(b, &b->restarts, np)) ||
-        (rc = alloc_dev(b, &b->nrun, 1)) || (rc = alloc_dev(b, &b->kmax, 1)) || (rc = alloc_dev(b, &b->alpha, np)))
+        (rc = alloc_dev(b, &b->nrun, 1)) || (rc = alloc_dev(b, &b->kmax, 1)) || (rc = alloc_dev(b, &b->alpha, np)) ||
+        (rc = alloc_dev(b, &b->claim, (size_t)nsys)) || (rc = alloc_dev(b, &b->done, (size_t)nsys)) ||
+        (rc = alloc_dev(b, &b->ctl, 4)))
         return bail(rc);
+    {
+        // claiming order of the one-launch schedule: larger systems (more
+        // rows, as a rule more iterations) first
+        std::vector<int32_t> prio(nsys);
+        for (int s = 0; s < nsys; ++s) prio[s] = s;
+        std::stable_sort(prio.begin(), prio.end(), [&](int32_t a, int32_t c) { return rows_h[a] > rows_h[c]; });
+        if ((rc = upload(b, &b->prio, prio)) != SS_OK) return bail(rc);
+    }
     // p0 / p1 are read (times beta = 0) before first written for stopped pairs
     if (hipMemsetAsync(b->p0, 0, sizeof(double) * nv, b->stream) != hipSuccess ||
         hipMemsetAsync(b->p1, 0, sizeof(double) * nv, b->stream) != hipSuccess ||
         hipMemsetAsync(b->status, 0xff, sizeof(int32_t) * np, b->stream) != hipSuccess)
         return bail(fail(SS_EDEVICE, "initialisation failed"));
-    ss_batch_tuning t{2, 0, 8, opts.check_every > 0 ? opts.check_every + (opts.check_every & 1) : 32};
+    ss_batch_tuning t{2, 0, 8, opts.check_every > 0 ? opts.check_every + (opts.check_every & 1) : 32,
+                      SS_BATCH_CHUNKED};
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         auto it = g_tune_cache.find(b->key);
@@ -1333,34 +1623,43 @@ int ss_batch_tune(ss_batch *b, const double *b_dev, int32_t iters, int32_t force
     const int32_t check = b->tun.check_every;
     const size_t nv = (size_t)b->nrows * b->nrhs;
     std::vector<ss_batch_tuning> cands;
-    for (int k : {1, 2, 4, 8})
+    for (int k : {1, 2, 4, 8}) {
         for (int g : {0, 2048, 1024})
-            for (int u : {4, 5, 8}) cands.push_back(ss_batch_tuning{k, g, u, pairs});
+            for (int u : {4, 5, 8}) cands.push_back(ss_batch_tuning{k, g, u, pairs, SS_BATCH_CHUNKED});
+        for (int u : {4, 5, 8}) cands.push_back(ss_batch_tuning{k, 0, u, check, SS_BATCH_PERSISTENT});
+    }
     ss_batch_tuning best = b->tun;
     double best_ms = 0.0;
     int32_t n = 0;
     for (const auto &c : cands) {
+        const bool flow = c.schedule == SS_BATCH_PERSISTENT;
         int rc = apply_tuning(b, c);
         if (rc != SS_OK) return rc;
-        if ((rc = ensure_graph(b, pairs)) != SS_OK) return rc;
+        if (!flow && (rc = ensure_graph(b, pairs)) != SS_OK) return rc;
         double ms = 0.0;
         for (int rep = 0; rep < 2; ++rep) {  // first repetition warms up
             SS_HIP(hipMemsetAsync(b->x, 0, sizeof(double) * nv, b->stream));
             int32_t nrun = 0;
-            if ((rc = start_pairs(b, b_dev, 0.0, INT32_MAX, &nrun)) != SS_OK) return rc;
+            // the one launch runs until every pair reaches the iteration limit
+            if ((rc = start_pairs(b, b_dev, 0.0, flow ? pairs : INT32_MAX, &nrun)) != SS_OK) return rc;
             SS_HIP(hipEventRecord(b->ev[0], b->stream));
-            SS_HIP(hipGraphLaunch(b->exec, b->stream));
+            if (flow) {
+                if (nrun > 0 && (rc = iterate_flow(b)) != SS_OK) return rc;
+            } else {
+                SS_HIP(hipGraphLaunch(b->exec, b->stream));
+            }
             SS_HIP(hipEventRecord(b->ev[1], b->stream));
             SS_HIP(hipEventSynchronize(b->ev[1]));
             float f = 0.f;
             SS_HIP(hipEventElapsedTime(&f, b->ev[0], b->ev[1]));
             ms = (double)f / pairs;
         }
-        if (trials && n < cap) trials[n] = ss_batch_trial{ss_batch_tuning{c.tile_granules, c.grid, c.unroll, check}, ms};
+        const ss_batch_tuning used{c.tile_granules, c.grid, c.unroll, check, c.schedule};
+        if (trials && n < cap) trials[n] = ss_batch_trial{used, ms};
         ++n;
         if (best_ms == 0.0 || ms < best_ms) {
             best_ms = ms;
-            best = ss_batch_tuning{c.tile_granules, c.grid, c.unroll, check};
+            best = used;
         }
     }
     if (ntrials) *ntrials = std::min(n, cap > 0 ? cap : 0);

@@ -101,10 +101,17 @@ def test_fixed_iterations_match_oracle(small, k):
             assert np.linalg.norm(X[s][:, j] - xo) <= 1e-12 * np.linalg.norm(xo), (s, j)
 
 
+CH, PE = ss.SS_BATCH_CHUNKED, ss.SS_BATCH_PERSISTENT
+
+
 def test_results_independent_of_launch_shape(small):
+    # both schedules: chunked graphs and the single persistent launch (down to
+    # 8 workgroups for all systems' phases), every tile size and unroll
     S, bt, B = small
     ref = None
-    for shape in [(2, 0, 8, 32), (1, 0, 4, 32), (8, 0, 8, 2), (1, 8, 5, 32), (4, 1024, 4, 64), (2, 16, 5, 4)]:
+    for shape in [(2, 0, 8, 32, CH), (1, 0, 4, 32, CH), (8, 0, 8, 2, CH), (1, 8, 5, 32, CH), (4, 1024, 4, 64, CH),
+                  (2, 16, 5, 4, CH), (2, 0, 8, 32, PE), (1, 0, 4, 32, PE), (8, 0, 5, 32, PE), (4, 8, 8, 32, PE),
+                  (1, 16, 4, 32, PE)]:
         ss.ss_batch_set_tuning(bt, *shape)
         X, res, _ = _solve(bt, B)
         flat = np.concatenate([x.ravel() for x in X])
@@ -113,14 +120,15 @@ def test_results_independent_of_launch_shape(small):
             ref = (flat, its)
         else:
             assert np.array_equal(flat, ref[0]) and its == ref[1], shape
-    ss.ss_batch_set_tuning(bt, 2, 0, 8, 32)
+    ss.ss_batch_set_tuning(bt, 2, 0, 8, 32, CH)
 
 
 def test_autotuner_picks_a_candidate_and_caches_it(small):
     S, bt, B = small
     b = _t(ss.pack_batch(B))
     chosen, trials = ss.ss_batch_tune(bt, b, iters=4, force=True)
-    assert len(trials) == 36 and all(ms > 0 for _, ms in trials)
+    assert len(trials) == 48 and all(ms > 0 for _, ms in trials)
+    assert sum(t["schedule"] == PE for t, _ in trials) == 12
     shapes = [t for t, _ in trials]
     assert chosen in shapes
     best = min(trials, key=lambda t: t[1])[0]
@@ -178,6 +186,8 @@ def test_initial_guess_and_edge_cases(small):
         ss.ss_batch_set_tuning(bt, 3, 0, 8, 32)
     with pytest.raises(ss.SSError):
         ss.ss_batch_set_tuning(bt, 2, 12, 8, 32)
+    with pytest.raises(ss.SSError):
+        ss.ss_batch_set_tuning(bt, 2, 0, 8, 32, 2)  # no such schedule
     with pytest.raises(ss.SSError):
         ss.ss_batch_setup(S, nrhs=3)
 
@@ -247,22 +257,28 @@ def test_wide_systems_take_the_direct_gather_path(nrhs):
             assert abs(r.iterations - ro.iterations) <= max(2, 0.05 * ro.iterations), (s, j, r, ro)
             true = np.linalg.norm(b - O.csr_matvec(A, X[s][:, j])) / np.linalg.norm(b)
             assert true <= 1e-10
-    # and the launch shape still changes nothing
-    ss.ss_batch_set_tuning(bt, 1, 8, 4, 2)
-    X2, res2, _ = _solve(bt, B)
-    assert all(np.array_equal(a, c) for a, c in zip(X, X2))
-    assert [r.iterations for r in res] == [r.iterations for r in res2]
+    # and the launch shape and schedule still change nothing
+    for shape in [(1, 8, 4, 2, CH), (1, 8, 4, 2, PE)]:
+        ss.ss_batch_set_tuning(bt, *shape)
+        X2, res2, _ = _solve(bt, B)
+        assert all(np.array_equal(a, c) for a, c in zip(X, X2)), shape
+        assert [r.iterations for r in res] == [r.iterations for r in res2], shape
 
 
 def test_many_small_systems():
     # 6000 systems of 1x1 .. 12x12 grids, 2 right-hand sides: 12,000 pairs, far
     # more tiles than workgroups, and systems leaving the running list at
-    # every polled chunk
+    # every polled chunk (chunked, the default) or retiring one by one
+    # (persistent); both schedules give the same bits
     S = batch2d_lognormal(6000, 1, 12, seed=41)
     bt = ss.ss_batch_setup(S, nrhs=2)
     B = _rhs(S, 2, 42)
     X, res, summ = _solve(bt, B, maxit=2000)
     assert summ.status == ss.SS_OK
+    ss.ss_batch_set_tuning(bt, 2, 0, 8, 32, PE)
+    Xc, resc, _ = _solve(bt, B, maxit=2000)
+    assert all(np.array_equal(a, c) for a, c in zip(X, Xc))
+    assert [r.iterations for r in res] == [r.iterations for r in resc]
     for s, A in enumerate(S):
         for j in range(2):
             r = res[s * 2 + j]
