@@ -23,7 +23,7 @@
 //     those of the streaming path; the scalars go to the run's DevState.
 // Row sums are formed in stored column order with separately rounded
 // products and sums, so the products are bitwise those of the other kernels.
-#include "kernels.h"
+#include "small.h"
 
 #include "device_common.h"
 

@@ -14,6 +14,7 @@
 #include "host_common.h"
 #include "kernels.h"
 #include "layout.h"
+#include "small.h"
 #include "ss_internal.h"
 
 using namespace ss;
@@ -488,9 +489,10 @@ int setup_impl(const ss_csr *A, const ss_part *p, const ss_opts *o, void *hip_st
     s->run32.q = s->q32;
     s->run32.st = s->st_in;
 
-    // A small system (FP64, M = I, rows of at most 7 entries, at most 5120 or
-    // 4096 positions, x, r, p and the interface products within the LDS a
-    // workgroup may take) is solved by one launch per solve.
+    // A small system (FP64, M = I, rows of at most 7 entries, at most 4608
+    // positions with 5-entry rows or 3584 with 7, x, r, p and the interface
+    // products within the LDS a workgroup may take) is solved by one launch
+    // per solve.
     int lds_max = 0;
     if (hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, s->device) != hipSuccess)
         lds_max = 0;
