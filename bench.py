@@ -506,8 +506,9 @@ def variant_configs(ss, torch, reps: int, tol: float) -> dict:
     from workloads import config
 
     w1 = config(1)
-    return {"poisson2d_64": _solve_line(ss, torch, w1, max(reps, 10), tol),
-            "poisson2d_64_streaming": _solve_line(ss, torch, w1, max(reps, 10), tol,
+    # ~1-3 ms solves: enough of them that the device clocks have settled
+    return {"poisson2d_64": _solve_line(ss, torch, w1, max(reps, 50), tol),
+            "poisson2d_64_streaming": _solve_line(ss, torch, w1, max(reps, 50), tol,
                                                   ss.default_opts(small_solver=ss.SS_SMALL_OFF)),
             "diffusion3d_grf_64": _solve_line(ss, torch, config(5), reps, tol)}
 
