@@ -171,7 +171,8 @@ def floor_solution(A, b):
 
 
 _REFS: dict = {}
-_ERRORS = {"on": True}
+_ORACLE_AT_TOL: dict = {}  # workload -> the oracle's own CG to the bench tolerance, its error vs the floor
+_ERRORS = {"on": True, "tol": 1e-10}
 
 
 def reference_for(w):
@@ -184,6 +185,13 @@ def reference_for(w):
         print(f"# oracle floor solution {w.name}: {r.iterations} iterations, true relres {r.true_relres:.1e} "
               f"({time.perf_counter() - t0:.1f} s)", file=sys.stderr, flush=True)
         _REFS[w.name] = x
+        # the same oracle stopped at the bench tolerance: the error a correct
+        # CG run to that residual has on this system
+        import oracle as O
+
+        xt, rt = O.cg_omp(w.A, w.b, tol=_ERRORS["tol"], maxit=200000, threads=cpu_threads())
+        _ORACLE_AT_TOL[w.name] = {"error_vs_floor": rel_err(xt, x), "iterations": rt.iterations,
+                                  "true_relres": rt.true_relres}
     return _REFS[w.name]
 
 
@@ -724,6 +732,7 @@ def main() -> int:
     from workloads import config
 
     _ERRORS["on"] = not args.no_cpu_baseline
+    _ERRORS["tol"] = args.tol
     if args.copy_calibration:
         calibrate_copy(torch)
     out = {} if args.no_main else main_measurement(args, ss, torch, config)
@@ -738,6 +747,10 @@ def main() -> int:
             kw = {"one_by_one": not args.no_one_by_one} if v == "batched" else {}
             out["variants"][v] = funcs[v](ss, torch, args.variant_steps, args.tol, **kw)
             torch.cuda.empty_cache()
+    if _ORACLE_AT_TOL:
+        out["oracle_cg_at_tol"] = {"what": "the oracle's global CG (all host cores) stopped at the same relative "
+                                           "residual: its error against the floor solution, per workload",
+                                   **_ORACLE_AT_TOL}
     print(json.dumps(out), flush=True)
     return 0
 
