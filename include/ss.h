@@ -160,8 +160,8 @@ enum {
 /* Solve of a small system in one launch (SS_FP64, M = I): one workgroup
  * runs every CG iteration, with the matrix in registers and p in LDS, instead
  * of two launches per iteration.  Used for systems whose local rows hold at
- * most 7 entries and number at most 5120 (rows of at most 5 entries) or 3072
- * (at most 7).  Same method, stopping rule and outputs as the general path. */
+ * most 7 entries and number at most 4608 (rows of at most 5 entries) or 3840
+ * (at most 7), within the LDS a workgroup may take.  Same method, stopping rule and outputs as the general path. */
 enum {
     SS_SMALL_AUTO = 0, /* use it when the system qualifies (default) */
     SS_SMALL_OFF = 1   /* always the general path                    */

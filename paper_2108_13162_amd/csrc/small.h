@@ -16,7 +16,7 @@ namespace ss {
 // block-diagonal matrix, their `width` (5 or 7) value slots and column
 // positions held in registers; x, r, p, the interface products and the
 // interface copy lists live in LDS.
-constexpr int kSmallThreads = 512;
+constexpr int kSmallThreads = 768;
 
 struct SmallMat {
     int32_t n_loc;
@@ -33,8 +33,9 @@ inline size_t small_lds_bytes(int32_t n_loc, int32_t n_if, int32_t ngamma, int32
            sizeof(int32_t) * ((size_t)n_if + (size_t)ngamma + 1 + (size_t)n_copies);
 }
 // Rows per thread of the kernel for `rows_needed` rows of `width` slots, 0
-// if none is built: width 5 up to 9 rows per thread (4608 positions), width
-// 7 up to 7 (3584).
+// if none is built: width 5 up to 6 rows per thread (4608 positions), width
+// 7 up to 5 (3840) -- what fits in a thread's registers without spilling at
+// three waves per SIMD.
 int32_t small_rows(int32_t rows_needed, int32_t width);
 // The solve from the gathered b and x0 (x updated in place) to the final
 // status, iteration count, (r, r), (b, b) and restart count in `state`

@@ -3,11 +3,12 @@
 // For a few thousand unknowns (the 64 x 64 Poisson system of the paper's
 // smallest class) an iteration moves well under a megabyte, and the two
 // launches per iteration of the streaming kernels cost more than their work.
-// Here one workgroup of 512 threads (two waves per SIMD, 256 registers a
-// thread) runs Algorithm 3 (M = I) from the first
+// Here one workgroup of 768 threads (three waves per SIMD, up to 168
+// registers a thread; 512 threads with more rows each measured 1.22 against
+// 0.98 ms on the 64 x 64 system) runs Algorithm 3 (M = I) from the first
 // residual to the converged, recomputed one:
 //   - every thread owns up to R rows of the block-diagonal matrix of all
-//     sub-domains (rows t, t + 512, ...), whose values and column positions
+//     sub-domains (rows t, t + 768, ...), whose values and column positions
 //     stay in its registers for the whole solve;
 //   - x, r and p live in LDS (up to 160 KB a workgroup on gfx950); the local
 //     products gather p there;
@@ -312,7 +313,7 @@ void launch_r(hipStream_t s, const SmallMat &M, const Iface &I, const double *b,
 
 int32_t small_rows(int32_t rows_needed, int32_t width)
 {
-    const int32_t cap = width == 5 ? 9 : width == 7 ? 7 : 0;
+    const int32_t cap = width == 5 ? 6 : width == 7 ? 5 : 0;
     return rows_needed >= 1 && rows_needed <= cap ? rows_needed : 0;
 }
 
@@ -326,9 +327,6 @@ void launch_cg_small(hipStream_t s, const SmallMat &M, const Iface &I, const dou
         case 4: launch_r<4, 5>(s, M, I, b, x, st); break;
         case 5: launch_r<5, 5>(s, M, I, b, x, st); break;
         case 6: launch_r<6, 5>(s, M, I, b, x, st); break;
-        case 7: launch_r<7, 5>(s, M, I, b, x, st); break;
-        case 8: launch_r<8, 5>(s, M, I, b, x, st); break;
-        case 9: launch_r<9, 5>(s, M, I, b, x, st); break;
         default: break;
         }
     } else if (M.width == 7) {
@@ -338,8 +336,6 @@ void launch_cg_small(hipStream_t s, const SmallMat &M, const Iface &I, const dou
         case 3: launch_r<3, 7>(s, M, I, b, x, st); break;
         case 4: launch_r<4, 7>(s, M, I, b, x, st); break;
         case 5: launch_r<5, 7>(s, M, I, b, x, st); break;
-        case 6: launch_r<6, 7>(s, M, I, b, x, st); break;
-        case 7: launch_r<7, 7>(s, M, I, b, x, st); break;
         default: break;
         }
     }

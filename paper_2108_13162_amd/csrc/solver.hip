@@ -490,7 +490,7 @@ int setup_impl(const ss_csr *A, const ss_part *p, const ss_opts *o, void *hip_st
     s->run32.st = s->st_in;
 
     // A small system (FP64, M = I, rows of at most 7 entries, at most 4608
-    // positions with 5-entry rows or 3584 with 7, x, r, p and the interface
+    // positions with 5-entry rows or 3840 with 7, x, r, p and the interface
     // products within the LDS a workgroup may take) is solved by one launch
     // per solve.
     int lds_max = 0;

@@ -31,7 +31,7 @@ def _solve(s, b, x0=None, **kw):
 def _case(kind):
     """(name, A, library partition, oracle sub-domains)"""
     if kind == "cfg1":
-        w = config(1)  # 64 x 64 Poisson, 2 x 2 boxes: 4224 positions, 9 rows a thread
+        w = config(1)  # 64 x 64 Poisson, 2 x 2 boxes: 4224 positions, 6 rows a thread
         return "poisson64_box2x2", w.A, ss.partition_workload(w), O.split(
             w.A.rowptr, w.A.colidx, O.box_partition(w.grid, w.boxes), 4)
     if kind.startswith("p2d"):
