@@ -7,7 +7,9 @@ runs on the same seeded inputs.  Bars:
   - CG iterates after a fixed number of steps: relative difference at most
     1e-12 or 10x the oracle's own deviation when only its dot-product
     summation order changes (CG amplifies rounding, more so when the system
-    is ill conditioned);
+    is ill conditioned); and, against the oracle run with Dot2 dot products,
+    no further than 2x the farther of the two sequential oracle orders (or
+    1e-15);
   - solves to ||r|| <= 1e-10 ||b||: recomputed residual <= 1e-10 (checked with
     the oracle's own SpMV), iteration count within 2 of the oracle's;
   - relative solution error <= 1e-9 against the oracle's floor solution when
@@ -138,6 +140,15 @@ def test_fixed_k_iterates(cases, k):
         print(f"{name} k={k}: gpu-oracle {dx:.2e} (hist {dh:.2e}); oracle spread {dx_o:.2e} (hist {dh_o:.2e})")
         assert dx <= max(1e-12, 10 * dx_o), (name, dx, dx_o)
         assert dh <= max(1e-12, 10 * dh_o), (name, dh, dh_o)
+        # tighter: against the oracle with Dot2 (twice-working-precision) dot
+        # products, the GPU iterate is no further than either sequential
+        # oracle order (twice its distance as margin, 1e-15 as the floor)
+        xd, _ = O.ss_cg_dot2(A, sd, b, tol=0.0, maxit=k)
+        nd = np.linalg.norm(xd)
+        e_gpu = np.linalg.norm(xg - xd) / nd
+        e_seq = max(np.linalg.norm(xo - xd) / nd, np.linalg.norm(O.cg(A, b, tol=0.0, maxit=k)[0] - xd) / nd)
+        print(f"{name} k={k}: to the Dot2 oracle: gpu {e_gpu:.2e}, sequential orders up to {e_seq:.2e}")
+        assert e_gpu <= max(1e-15, 2 * e_seq), (name, e_gpu, e_seq)
 
 
 @pytest.mark.parametrize("graph,chk", [(1, 8), (0, 6), (1, 64)])
