@@ -126,6 +126,14 @@ def test_fixed_k_iterates_match_oracle(cases, k):
         dh = _hist_diff(r.hist, ro.hist)
         assert dx <= max(1e-12, 10 * dx_o), (name, dx, dx_o)
         assert dh <= max(1e-12, 10 * dh_o), (name, dh, dh_o)
+        # against the oracle with Dot2 dot products: no further than either
+        # sequential oracle order (2x margin, 1e-15 floor)
+        xd, _ = O.ss_cg_dot2(A, sd, b, tol=0.0, maxit=k)
+        nd = np.linalg.norm(xd)
+        e_gpu = np.linalg.norm(x - xd) / nd
+        e_seq = max(np.linalg.norm(xo - xd) / nd, np.linalg.norm(O.cg(A, b, tol=0.0, maxit=k)[0] - xd) / nd)
+        print(f"{name} k={k}: to the Dot2 oracle: gpu {e_gpu:.2e}, sequential orders up to {e_seq:.2e}")
+        assert e_gpu <= max(1e-15, 2 * e_seq), (name, e_gpu, e_seq)
 
 
 def test_solves_match_oracle_and_stream_path(cases):
