@@ -619,8 +619,8 @@ __global__ __launch_bounds__(kWG) void k_bupdate(BMat M, BTiles T, BState S, dou
 // system never overlap, so the kernels' per-tile code runs unchanged and the
 // results are bitwise those of the chunked launches; systems do not wait for
 // each other, and no workgroup waits for a particular other one: a free
-// workgroup takes a tile of the first system in priority order (largest
-// first) that has one, else polls.  Every workgroup leaves when all systems
+// workgroup takes a tile of one of the first systems in priority order
+// (largest first) that have one, else polls.  Every workgroup leaves when all systems
 // have retired, or when no phase has finished for a long time (an error
 // flag the host reports; it never happens in a correct run).
 
@@ -657,10 +657,11 @@ __device__ bool flow_claim(const BFlow &F, int &s_out, uint32_t &seq_out, int &t
         __syncthreads();  // sh is free
         if (threadIdx.x < kSpread) sh[5 + threadIdx.x] = INT_MAX;
         __syncthreads();
-        // the first kSpread systems in priority order with a tile left (one
-        // candidate per wave and lane position: lane l of the first wave
-        // that holds one); a workgroup takes the one its index selects, so
-        // claims spread over several counters
+        // candidates: for each residue k of the priority index modulo
+        // kSpread, the first system of that residue with a tile left (so the
+        // candidates are among the first such systems in priority order); a
+        // workgroup takes the one its index selects, so claims spread over
+        // several counters
         for (int i = (int)threadIdx.x; i < F.nsys; i += kWG) {
             const int s = F.prio[i];
             const unsigned long long c = claim_load(&F.claim[s]);
