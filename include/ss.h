@@ -429,7 +429,11 @@ enum { SS_BATCH_CHUNKED = 0, SS_BATCH_PERSISTENT = 1 };
  * bitwise the same for every choice (all partial sums are taken over fixed
  * 512-row granules, each system's phases run in the same order). */
 typedef struct {
-    int32_t tile_granules; /* 512-row granules per workgroup tile: 1, 2, 4, 8   */
+    int32_t tile_granules; /* 512-row granules per workgroup tile: 1, 2, 4, 8;
+                              0 = per system, the fewest of those for which
+                              the 2h rows around a tile that the staged SpMV
+                              reads twice (h: the system's largest
+                              |column - row|) are at most a quarter of it  */
     int32_t grid;          /* workgroups per launch, a multiple of 8 in
                               [8, 65536]; 0 = one per tile (chunked) or as
                               many as are resident at once (persistent)     */
@@ -475,8 +479,8 @@ int ss_batch_get_tuning(const ss_batch *bt, ss_batch_tuning *t);
 
 /*
  * ss_batch_tune -- the autotuner.  Times each candidate launch shape (tile
- * granules 1/2/4/8 x unroll 4/5/8 x {chunked with grid one-per-tile / 2048 /
- * 1024, persistent with the resident grid}: 48 shapes) over `iters` CG
+ * granules per system/1/2/4/8 x unroll 4/5/8 x {chunked with grid one-per-tile
+ * / 2048 / 1024, persistent with the resident grid}: 60 shapes) over `iters` CG
  * iterations (<= 0: 8) of this batch with right-hand sides b_dev, every pair
  * running from x = 0 (x_dev is not touched), and keeps the fastest.
  * The choice is remembered for the process, keyed by the batch structure

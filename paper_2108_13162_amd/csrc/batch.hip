@@ -975,14 +975,27 @@ struct Tiles {
     std::vector<int32_t> tile_sys, tile_g0, sys_t0;
 };
 
-// Tiles of k granules, never crossing a system boundary.
-Tiles make_tiles(const std::vector<int32_t> &sys_g0, int k)
+// Granules per tile of a system whose entries lie within h rows of the
+// diagonal, for the per-system choice (tile_granules 0): the staged SpMV
+// reads the 2h rows around a tile twice, so the tile takes the fewest
+// granules (1, 2, 4, 8) that keep those rows at most a quarter of its own.
+int reach_granules(int32_t h)
+{
+    int k = 1;
+    while (k < 8 && 2 * (int64_t)h * 4 > (int64_t)k * kGranRows) k *= 2;
+    return k;
+}
+
+// Tiles of k granules (k = 0: reach_granules of each system's halo h),
+// never crossing a system boundary.
+Tiles make_tiles(const std::vector<int32_t> &sys_g0, int k0, const std::vector<int32_t> &h)
 {
     Tiles T;
     const int nsys = (int)sys_g0.size() - 1;
     T.sys_t0.assign(nsys + 1, 0);
     T.tile_g0.push_back(0);
     for (int s = 0; s < nsys; ++s) {
+        const int k = k0 > 0 ? k0 : reach_granules(h[s]);
         T.sys_t0[s] = (int32_t)T.tile_sys.size();
         for (int g = sys_g0[s]; g < sys_g0[s + 1]; g += k) {
             T.tile_sys.push_back(s);
@@ -996,7 +1009,7 @@ Tiles make_tiles(const std::vector<int32_t> &sys_g0, int k)
 bool tuning_valid(const ss_batch_tuning &t)
 {
     const int k = t.tile_granules;
-    if (k != 1 && k != 2 && k != 4 && k != 8) return false;
+    if (k != 0 && k != 1 && k != 2 && k != 4 && k != 8) return false;
     if (t.grid != 0 && (t.grid < 8 || t.grid > kGridLimit || t.grid % 8 != 0)) return false;
     if (t.unroll != 4 && t.unroll != 5 && t.unroll != 8) return false;
     if (t.check_every < 2 || t.check_every > 1024 || t.check_every % 2 != 0) return false;
@@ -1018,6 +1031,7 @@ struct ss_batch {
     hipStream_t stream = nullptr, cap = nullptr;
     DeviceMem mem;
     std::vector<int32_t> sys_g0_h;
+    std::vector<int32_t> sys_h_h;  // largest |column - row| of each system (host)
     int32_t *sys_h = nullptr;
     // matrix and granules
     int32_t *col = nullptr, *cptr = nullptr, *crow = nullptr, *gran_c0 = nullptr, *sys_g0 = nullptr;
@@ -1088,7 +1102,7 @@ void destroy_graph(ss_batch *b)
 // Uploads the tiles of tuning t (the identity list is the full list).
 int apply_tuning(ss_batch *b, const ss_batch_tuning &t)
 {
-    Tiles T = make_tiles(b->sys_g0_h, t.tile_granules);
+    Tiles T = make_tiles(b->sys_g0_h, t.tile_granules, b->sys_h_h);
     const int nt = (int)T.tile_sys.size();
     std::vector<int32_t> ident(nt);
     for (int i = 0; i < nt; ++i) ident[i] = i;
@@ -1460,6 +1474,7 @@ int ss_batch_setup(int32_t nsys, const ss_csr *systems, int32_t nrhs, const ss_o
     b->nchunks = (int32_t)cptr.size();
     b->ngran = (int32_t)gran_c0.size() - 1;
     b->sys_g0_h = sys_g0;
+    b->sys_h_h = halo;
     b->max_halo = *std::max_element(halo.begin(), halo.end());
     if (hipGetDevice(&b->device) != hipSuccess) return bail(fail(SS_EDEVICE, "no HIP device"));
     b->key = structure_key(rows_h, nnz_h, nrhs, b->device);
@@ -1624,7 +1639,7 @@ int ss_batch_tune(ss_batch *b, const double *b_dev, int32_t iters, int32_t force
     const int32_t check = b->tun.check_every;
     const size_t nv = (size_t)b->nrows * b->nrhs;
     std::vector<ss_batch_tuning> cands;
-    for (int k : {1, 2, 4, 8}) {
+    for (int k : {0, 1, 2, 4, 8}) {
         for (int g : {0, 2048, 1024})
             for (int u : {4, 5, 8}) cands.push_back(ss_batch_tuning{k, g, u, pairs, SS_BATCH_CHUNKED});
         for (int u : {4, 5, 8}) cands.push_back(ss_batch_tuning{k, 0, u, check, SS_BATCH_PERSISTENT});

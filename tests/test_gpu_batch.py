@@ -110,8 +110,8 @@ def test_results_independent_of_launch_shape(small):
     S, bt, B = small
     ref = None
     for shape in [(2, 0, 8, 32, CH), (1, 0, 4, 32, CH), (8, 0, 8, 2, CH), (1, 8, 5, 32, CH), (4, 1024, 4, 64, CH),
-                  (2, 16, 5, 4, CH), (2, 0, 8, 32, PE), (1, 0, 4, 32, PE), (8, 0, 5, 32, PE), (4, 8, 8, 32, PE),
-                  (1, 16, 4, 32, PE)]:
+                  (2, 16, 5, 4, CH), (0, 0, 8, 32, CH), (0, 24, 5, 2, CH), (2, 0, 8, 32, PE), (1, 0, 4, 32, PE),
+                  (8, 0, 5, 32, PE), (4, 8, 8, 32, PE), (1, 16, 4, 32, PE), (0, 0, 8, 32, PE)]:
         ss.ss_batch_set_tuning(bt, *shape)
         X, res, _ = _solve(bt, B)
         flat = np.concatenate([x.ravel() for x in X])
@@ -127,8 +127,9 @@ def test_autotuner_picks_a_candidate_and_caches_it(small):
     S, bt, B = small
     b = _t(ss.pack_batch(B))
     chosen, trials = ss.ss_batch_tune(bt, b, iters=4, force=True)
-    assert len(trials) == 48 and all(ms > 0 for _, ms in trials)
-    assert sum(t["schedule"] == PE for t, _ in trials) == 12
+    assert len(trials) == 60 and all(ms > 0 for _, ms in trials)
+    assert sum(t["schedule"] == PE for t, _ in trials) == 15
+    assert sum(t["tile_granules"] == 0 for t, _ in trials) == 12
     shapes = [t for t, _ in trials]
     assert chosen in shapes
     best = min(trials, key=lambda t: t[1])[0]
