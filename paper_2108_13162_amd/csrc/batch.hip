@@ -25,6 +25,10 @@
 // same partials in the same order (bitwise equal everywhere); the workgroup
 // of the system's first tile records them.  A pair that stops freezes its x
 // and r; a system with no running pair leaves the list.
+//
+// The same per-tile code also runs under a persistent schedule (k_bflow):
+// one launch for all iterations, each system moving through its own update
+// and SpMV phases (see "all iterations in one launch" below).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
