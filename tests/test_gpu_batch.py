@@ -160,8 +160,10 @@ def test_fewer_rhs(nrhs):
             assert np.linalg.norm(X[s][:, j] - xr) <= 1e-9 * np.linalg.norm(xr)
 
 
-def test_initial_guess_and_edge_cases(small):
+@pytest.mark.parametrize("schedule", [0, 1])  # SS_BATCH_CHUNKED, SS_BATCH_PERSISTENT
+def test_initial_guess_and_edge_cases(small, schedule):
     S, bt, B = small
+    ss.ss_batch_set_tuning(bt, 2, 0, 8, 32, schedule)
     # starting from the solution: converged after the first residual, 0 iterations
     X, res, _ = _solve(bt, B)
     X2, res2, summ = _solve(bt, B, x0=X)
@@ -191,6 +193,7 @@ def test_initial_guess_and_edge_cases(small):
         ss.ss_batch_set_tuning(bt, 2, 0, 8, 32, 2)  # no such schedule
     with pytest.raises(ss.SSError):
         ss.ss_batch_setup(S, nrhs=3)
+    ss.ss_batch_set_tuning(bt, 2, 0, 8, 32, CH)
 
 
 def test_matches_one_by_one_gpu_solves(small):
