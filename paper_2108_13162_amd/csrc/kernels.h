@@ -84,9 +84,14 @@ struct Mat {
     // 0..U-1 in dword[64 b + l] (with U <= 7 its top 4 bits hold the row's
     // length); inside each SpMV workgroup's range these chunks come first.
     // nullptr: none.
+    // Rows of several load batches (dict_batches > 0): the wide kind, 64
+    // offsets a block (dtab[64 b ..]), and for batch j of block b lane l's two
+    // words of 6-bit indices of the batch's slots at dword[2 ((b
+    // dict_batches + j) 64 + l) ..].
     const int32_t *cdict;
     const int32_t *dtab;
     const uint32_t *dword;
+    int32_t dict_batches;
     // CSR tiles
     const int32_t *rowptr;        // [nrows+1]
     const int32_t *tile_row;      // [ntiles+1]

@@ -295,6 +295,23 @@ __device__ __forceinline__ void decode_dict(int (&cc)[U], uint32_t dw, int tab, 
     for (int u = 0; u < U; ++u) cc[u] = row + __shfl(tab, (int)((dw >> (4 * u)) & 15u), 64);
 }
 
+// Rows of several batches: the lane's two words of 6-bit indices for batch j
+// of wide dictionary block blk (dict_batches batches a block).
+__device__ __forceinline__ uint64_t wide_word(const uint32_t *__restrict__ dword, int blk, int nbatch, int j, int lane)
+{
+    const uint2 w = reinterpret_cast<const uint2 *>(dword)[((size_t)blk * nbatch + j) * 64 + lane];
+    return ((uint64_t)w.y << 32) | w.x;
+}
+
+// Columns of a batch's slots 0..U-1: the row plus the offset (one of the
+// block's 64, one per lane) its 6-bit index names.
+template <int U>
+__device__ __forceinline__ void decode_wide(int (&cc)[U], uint64_t bits, int tab, int row)
+{
+#pragma unroll
+    for (int u = 0; u < U; ++u) cc[u] = row + __shfl(tab, (int)((bits >> (6 * u)) & 63u), 64);
+}
+
 // Band-column product (one device): the row sum is split where the column
 // crosses into the next band of bm columns (the last band takes the rest);
 // the band partial sums are added in band order.  First column of the band
@@ -326,10 +343,12 @@ __global__ __launch_bounds__(kBS) __attribute__((amdgpu_waves_per_eu(1, 4))) voi
     XT *__restrict__ q, XT *__restrict__ x, double *__restrict__ part_a, const double *__restrict__ part_b,
     const double *__restrict__ part_b2, int32_t nb, int32_t slot, DevState *__restrict__ st,
     const int32_t *__restrict__ gate, int32_t bm, int32_t nbands, const int32_t *__restrict__ cdict,
-    const int32_t *__restrict__ dtab, const uint32_t *__restrict__ dword)
+    const int32_t *__restrict__ dtab, const uint32_t *__restrict__ dword, int32_t dict_batches)
 {
     constexpr bool CG = MODE != SPMV_PLAIN;                        // status, (p, A p)
     constexpr bool PUPD = MODE == SPMV_FIRST || MODE == SPMV_STEP;  // p formed here
+    // rows of several batches with the wide offset dictionaries
+    constexpr bool WIDE = !ONE && DICT_ON && !BAND && U <= 10;
     constexpr int W = kBS / 64;
     __shared__ double ws[2 * (kBS / 64) + 2];
     __shared__ int s_flag;
@@ -352,7 +371,7 @@ __global__ __launch_bounds__(kBS) __attribute__((amdgpu_waves_per_eu(1, 4))) voi
     int2 wb = make_int2(0, 0);
     XT rrow = XT(0), prow = XT(0), xrow = XT(0);
     uint32_t dw = 0;  // ONE, dictionary chunk: the lane's 4-bit offset indices
-    int tab = 0;      // and offset (lane & 15) of the chunk's table
+    int tab = 0;      // and offset (lane & 15) of the chunk's table (wide: entry lane of 64)
     if (c < cend) {
         base = cptr[c];
         L = chunk_len(clen, c);
@@ -368,7 +387,14 @@ __global__ __launch_bounds__(kBS) __attribute__((amdgpu_waves_per_eu(1, 4))) voi
             load_batch<VT, U>(cw, vv, cb, base, 0, L, lane, col, col16, val);
             load_row<XT, MODE>(len, rrow, prow, xrow, row, nrows, rlen, r, pin, x);
         } else {
-            load_cols<U>(cc, cb, wb, 0, L, lane, col, col16);
+            if (WIDE) {
+                blk = cdict[c];
+                if (blk >= 0) tab = dtab[blk * 64 + lane];
+            }
+            if (WIDE && blk >= 0)
+                decode_wide<U>(cc, wide_word(dword, blk, dict_batches, 0, lane), tab, row);
+            else
+                load_cols<U>(cc, cb, wb, 0, L, lane, col, col16);
 #pragma unroll
             for (int u = 0; u < U; ++u) vv[u] = val[base + min(u, L - 1) * 64 + lane];
         }
@@ -545,6 +571,10 @@ __global__ __launch_bounds__(kBS) __attribute__((amdgpu_waves_per_eu(1, 4))) voi
                 cb = ccol[c];
                 if (cb >= 0) wb = cbase[c];
                 row = cpos[c] + lane;
+                if (WIDE) {
+                    blk = cdict[c];
+                    if (blk >= 0) tab = dtab[blk * 64 + lane];
+                }
             }
             len = row < nrows ? (int)rlen[row] : 0;
             XT sacc = XT(0);
@@ -552,7 +582,10 @@ __global__ __launch_bounds__(kBS) __attribute__((amdgpu_waves_per_eu(1, 4))) voi
             int bnext = -1;
             for (int j0 = 0; j0 < L; j0 += U) {
                 if (!have) {
-                    load_cols<U>(cc, cb, wb, j0, L, lane, col, col16);
+                    if (WIDE && blk >= 0)
+                        decode_wide<U>(cc, wide_word(dword, blk, dict_batches, j0 / U, lane), tab, row);
+                    else
+                        load_cols<U>(cc, cb, wb, j0, L, lane, col, col16);
 #pragma unroll
                     for (int u = 0; u < U; ++u) vv[u] = val[base + min(j0 + u, L - 1) * 64 + lane];
                 }
@@ -1243,12 +1276,17 @@ void spmv_dispatch(hipStream_t s, const Mat &A, const XT *pin, const XT *r, XT *
     hipLaunchKernelGGL((k_spmv_sell<VT, XT, MODE, U, ONE, BAND, false>), grid, block, 0, s, A.nrows, A.nchunks,   \
                        A.cptr, A.cpos, A.clen, A.rlen, A.ccol, A.col, A.col16, A.cbase, (const VT *)A.val, pin, r,  \
                        pout, q, x, P.a, (const double *)P.b, (const double *)P.b2, P.nb, slot, st, gate, A.band_m,  \
-                       A.nbands, nullptr, nullptr, nullptr)
+                       A.nbands, nullptr, nullptr, nullptr, 0)
+#define SS_SELL_W(U)                                                                                             \
+    hipLaunchKernelGGL((k_spmv_sell<VT, XT, MODE, U, false, false, true>), grid, block, 0, s, A.nrows, A.nchunks,  \
+                       A.cptr, A.cpos, A.clen, A.rlen, A.ccol, A.col, A.col16, A.cbase, (const VT *)A.val, pin, r,  \
+                       pout, q, x, P.a, (const double *)P.b, (const double *)P.b2, P.nb, slot, st, gate, A.band_m,  \
+                       A.nbands, A.cdict, A.dtab, A.dword, A.dict_batches)
 #define SS_SELL_D(U)                                                                                             \
     hipLaunchKernelGGL((k_spmv_sell<VT, XT, MODE, U, true, false, true>), grid, block, 0, s, A.nrows, A.nchunks, A.cptr,  \
                        A.cpos, A.clen, A.rlen, A.ccol, A.col, A.col16, A.cbase, (const VT *)A.val, pin, r, pout, q, x, \
                        P.a, (const double *)P.b, (const double *)P.b2, P.nb, slot, st, gate, A.band_m, A.nbands, A.cdict,  \
-                       A.dtab, A.dword)
+                       A.dtab, A.dword, 0)
 #define SS_SELL_U(ONE, BAND)                    \
     switch (A.unroll) {                         \
     case 5: SS_SELL(5, ONE, BAND); break;       \
@@ -1276,10 +1314,19 @@ void spmv_dispatch(hipStream_t s, const Mat &A, const XT *pin, const XT *r, XT *
             }
         } else if (A.one_batch) {
             SS_SELL_U(true, false)
+        } else if (A.cdict && A.dict_batches > 0 && A.unroll <= 10) {
+            // wide offset dictionaries (rows of several batches)
+            switch (A.unroll) {
+            case 5: SS_SELL_W(5); break;
+            case 7: SS_SELL_W(7); break;
+            case 9: SS_SELL_W(9); break;
+            default: SS_SELL_W(8); break;
+            }
         } else {
             SS_SELL_U(false, false)
         }
 #undef SS_SELL_U
+#undef SS_SELL_W
 #undef SS_SELL_D
 #undef SS_SELL
         return;
@@ -1301,26 +1348,30 @@ template <typename VT, typename XT>
 void spmv_pq_dispatch(hipStream_t s, const Mat &A, const XT *p, XT *q, Partials P, DevState *st)
 {
     const dim3 grid(A.grid), block(kBS);
-#define SS_PQ(U, BAND)                                                                                              \
-    hipLaunchKernelGGL((k_spmv_sell<VT, XT, SPMV_PQ, U, false, BAND, false>), grid, block, 0, s, A.nrows, A.nchunks, \
+#define SS_PQ(U, BAND, WD)                                                                                          \
+    hipLaunchKernelGGL((k_spmv_sell<VT, XT, SPMV_PQ, U, false, BAND, WD>), grid, block, 0, s, A.nrows, A.nchunks,    \
                        A.cptr, A.cpos, A.clen, A.rlen, A.ccol, A.col, A.col16, A.cbase, (const VT *)A.val, p,       \
                        (const XT *)nullptr, (XT *)nullptr, q, (XT *)nullptr, P.a, (const double *)nullptr,          \
                        (const double *)nullptr, 0, 0, st, (const int32_t *)nullptr, A.band_m, A.nbands,             \
-                       (const int32_t *)nullptr, (const int32_t *)nullptr, (const uint32_t *)nullptr)
-#define SS_PQ_U(BAND)                      \
+                       WD ? A.cdict : nullptr, WD ? A.dtab : nullptr, WD ? A.dword : nullptr, WD ? A.dict_batches : 0)
+#define SS_PQ_U(BAND, WD)                  \
     switch (A.unroll) {                    \
-    case 5: SS_PQ(5, BAND); break;         \
-    case 7: SS_PQ(7, BAND); break;         \
-    case 9: SS_PQ(9, BAND); break;         \
-    default: SS_PQ(8, BAND); break;        \
+    case 5: SS_PQ(5, BAND, WD); break;     \
+    case 7: SS_PQ(7, BAND, WD); break;     \
+    case 9: SS_PQ(9, BAND, WD); break;     \
+    default: SS_PQ(8, BAND, WD); break;    \
     }
     if constexpr (std::is_same<VT, double>::value && std::is_same<XT, double>::value) {
         if (A.nbands > 1) {
-            SS_PQ_U(true)
+            SS_PQ_U(true, false)
             return;
         }
     }
-    SS_PQ_U(false)
+    if (A.cdict && A.dict_batches > 0 && A.unroll <= 10) {
+        SS_PQ_U(false, true)
+    } else {
+        SS_PQ_U(false, false)
+    }
 #undef SS_PQ_U
 #undef SS_PQ
 }

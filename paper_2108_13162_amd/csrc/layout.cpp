@@ -23,6 +23,10 @@ constexpr int kSmallChunks = 16384;
 constexpr int kDictOffsets = 16;
 constexpr int kDictSlots = 8;
 constexpr int kDictMinPerWg = 24;  // chunks per SpMV workgroup for the dictionaries to pay
+// Rows of several load batches: at most 64 offsets (6-bit indices, a batch of
+// at most 10 slots in two words).
+constexpr int kWideOffsets = 64;
+constexpr int kWideSlots = 10;
 
 }  // namespace
 
@@ -321,6 +325,56 @@ void build_matrix(const ss_part *p, Layout &L, int32_t tile_nnz, int32_t force, 
                 L.dword.push_back(wd);
             }
         }
+        // Wide offset dictionaries (rows of several load batches, all 64 rows
+        // of the chunk present): at most 64 distinct column - row offsets,
+        // each batch's slots as 6-bit indices in two words per lane, so the
+        // SpMV reads 8 B per row and batch and a 256 B table instead of 2 or
+        // 4 B per entry.  Checked entry by entry.
+        if (L.dtab.empty() && !L.one_batch && L.unroll <= kWideSlots) {
+            int32_t nbmax = 0;
+            for (int32_t i = 0; i < nch; ++i) nbmax = std::max(nbmax, (L.clen[i] + L.unroll - 1) / L.unroll);
+            std::vector<int32_t> offs;
+            for (int32_t i = 0; i < nch; ++i) {
+                if (L.cpos[i] + 64 > nl) continue;
+                offs.assign(1, 0);  // padding and clamped slots decode to the row itself
+                bool ok = true;
+                for (int64_t k = L.cptr[i]; k < L.cptr[i + 1] && ok; ++k) {
+                    const int32_t d = L.col[k] - (L.cpos[i] + (int32_t)((k - L.cptr[i]) % 64));
+                    if (std::find(offs.begin(), offs.end(), d) == offs.end()) {
+                        offs.push_back(d);
+                        ok = (int)offs.size() <= kWideOffsets;
+                    }
+                }
+                if (!ok) continue;
+                std::sort(offs.begin(), offs.end());
+                const int32_t blk = (int32_t)(L.dtab.size() / kWideOffsets);
+                L.cdict[i] = blk;
+                for (int32_t q = 0; q < kWideOffsets; ++q) L.dtab.push_back(q < (int32_t)offs.size() ? offs[q] : 0);
+                const int32_t len_c = L.clen[i], nb = (len_c + L.unroll - 1) / L.unroll;
+                L.dword.resize(((size_t)blk + 1) * nbmax * 64 * 2, 0u);
+                int64_t real = 0;
+                for (int32_t lane = 0; lane < 64; ++lane) {
+                    const int32_t t = L.cpos[i] + lane;
+                    real += L.rlen[t];
+                    for (int32_t j = 0; j < nb; ++j) {
+                        uint64_t bits = 0;
+                        for (int32_t u = 0; u < L.unroll; ++u) {
+                            // slots past the chunk repeat its last one, as the SpMV's loads do
+                            const int32_t slot = std::min(j * L.unroll + u, len_c - 1);
+                            const int32_t d = L.col[L.cptr[i] + (int64_t)slot * 64 + lane] - t;
+                            const int32_t q = (int32_t)(std::lower_bound(offs.begin(), offs.end(), d) - offs.begin());
+                            if (q >= (int32_t)offs.size() || offs[q] != d) L.encode_ok = false;
+                            bits |= (uint64_t)q << (6 * u);
+                        }
+                        const size_t w = (((size_t)blk * nbmax + j) * 64 + lane) * 2;
+                        L.dword[w] = (uint32_t)bits;
+                        L.dword[w + 1] = (uint32_t)(bits >> 32);
+                    }
+                }
+                L.col_bytes += (int64_t)nb * 64 * 8 + kWideOffsets * 4 - real * (L.ccol[i] >= 0 ? 2 : 4);
+            }
+            if (!L.dtab.empty()) L.dict_batches = nbmax;
+        }
         L.struct_bytes = 0;
         for (int32_t i = 0; i < nch; ++i) {
             L.struct_bytes += 4 + 4 + 1 + 4 + 8 + (L.dtab.empty() ? 0 : 4);
@@ -427,8 +481,16 @@ int64_t layout_check(const ss_part *p, const Layout &L)
                         expect(t, j, col, L.nzmap[k]);
                     else if (L.nzmap[k] != -1 || col < 0 || col >= std::max(nl, 1))
                         ++bad;
+                    // a wide dictionary chunk decodes to the same column
+                    if (L.dict_batches > 0 && L.cdict[i] >= 0) {
+                        const int32_t jb = j / L.unroll, u = j % L.unroll;
+                        const size_t w = (((size_t)L.cdict[i] * L.dict_batches + jb) * 64 + lane) * 2;
+                        const uint64_t bits = ((uint64_t)L.dword[w + 1] << 32) | L.dword[w];
+                        const int32_t q = (int32_t)((bits >> (6 * u)) & 63u);
+                        if (t + L.dtab[(size_t)L.cdict[i] * kWideOffsets + q] != col) ++bad;
+                    }
                     // a dictionary chunk decodes to the same column
-                    if (!L.cdict.empty() && L.cdict[i] >= 0 && j < std::min(len_c, L.unroll)) {
+                    if (L.dict_batches == 0 && !L.cdict.empty() && L.cdict[i] >= 0 && j < std::min(len_c, L.unroll)) {
                         const uint32_t wd = L.dword[(size_t)L.cdict[i] * 64 + lane];
                         const int32_t q = (int32_t)((wd >> (4 * j)) & 15u);
                         const int32_t dc = t + L.dtab[(size_t)L.cdict[i] * kDictOffsets + q];

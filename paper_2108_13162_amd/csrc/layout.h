@@ -39,8 +39,13 @@ struct Layout {
     bool encode_ok = true;            // column encoding verified
     std::vector<int32_t> cptr, cpos, rowptr, tile_row;
     std::vector<uint8_t> clen, rlen;
-    std::vector<int32_t> cdict, dtab;  // SELL: dictionary block of each chunk (-1: none); 16 offsets a block
-    std::vector<uint32_t> dword;       // SELL: per block and lane, the 4-bit offset indices of slots 0..7
+    // SELL offset dictionaries.  One-batch rows: 16 offsets a block, per block
+    // and lane one word of 4-bit indices (slots 0..7).  Rows of several load
+    // batches (dict_batches > 0): 64 offsets a block, per block, batch and
+    // lane two words of 6-bit indices (the batch's slots, at most 10).
+    std::vector<int32_t> cdict, dtab;  // dictionary block of each chunk (-1: none); the block's offsets
+    std::vector<uint32_t> dword;       // the index words
+    int32_t dict_batches = 0;          // several-batch rows: load batches per block (0: the one-batch kind)
     int32_t nchunks = 0, ntiles = 0, tile_nnz = 2048;
     int32_t unroll = 8;               // SELL: entries per lane loaded before use
     int32_t one_batch = 0;            // SELL: no chunk longer than unroll

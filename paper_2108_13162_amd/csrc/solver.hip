@@ -465,6 +465,7 @@ int setup_impl(const ss_csr *A, const ss_part *p, const ss_opts *o, void *hip_st
     M.cdict = L.dtab.empty() ? nullptr : d_cdict;
     M.dtab = d_dtab;
     M.dword = d_dword;
+    M.dict_batches = L.dict_batches;
     M.rowptr = d_rowptr;
     M.tile_row = d_tile;
     I.pos_grp = d_pos_grp;

@@ -21,7 +21,7 @@
 namespace {
 
 int g_fail = 0;
-int64_t g_dict_chunks = 0, g_wide_chunks = 0, g_narrow_chunks = 0, g_csr_layouts = 0;
+int64_t g_dict_chunks = 0, g_wdict_chunks = 0, g_wide_chunks = 0, g_narrow_chunks = 0, g_csr_layouts = 0;
 
 #define CHECK(cond)                                                              \
     do {                                                                         \
@@ -155,7 +155,8 @@ void check_layouts(const Csr &A, const ss_part *p)
                 CHECK(ss::layout_check(p, L) == 0);
                 if (L.fmt == ss::FMT_CSR) ++g_csr_layouts;
                 for (int32_t i = 0; i < L.nchunks; ++i) {
-                    g_dict_chunks += !L.cdict.empty() && L.cdict[i] >= 0;
+                    g_dict_chunks += !L.cdict.empty() && L.cdict[i] >= 0 && L.dict_batches == 0;
+                    g_wdict_chunks += !L.cdict.empty() && L.cdict[i] >= 0 && L.dict_batches > 0;
                     (L.ccol[i] >= 0 ? g_narrow_chunks : g_wide_chunks) += 1;
                 }
             }
@@ -262,9 +263,10 @@ int main()
         CHECK(p == nullptr);
     }
     // every storage variant was exercised
-    CHECK(g_dict_chunks > 0 && g_wide_chunks > 0 && g_narrow_chunks > 0 && g_csr_layouts > 0);
-    std::printf("chunks checked: %lld with offset dictionaries, %lld with 16-bit columns, %lld with int32 columns; "
-                "%lld CSR layouts\n", (long long)g_dict_chunks, (long long)g_narrow_chunks, (long long)g_wide_chunks,
+    CHECK(g_dict_chunks > 0 && g_wdict_chunks > 0 && g_wide_chunks > 0 && g_narrow_chunks > 0 && g_csr_layouts > 0);
+    std::printf("chunks checked: %lld with offset dictionaries, %lld with wide (several-batch) dictionaries, "
+                "%lld with 16-bit columns, %lld with int32 columns; %lld CSR layouts\n", (long long)g_dict_chunks,
+                (long long)g_wdict_chunks, (long long)g_narrow_chunks, (long long)g_wide_chunks,
                 (long long)g_csr_layouts);
     if (g_fail) {
         std::fprintf(stderr, "%d checks failed\n", g_fail);
