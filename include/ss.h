@@ -170,7 +170,9 @@ enum {
 /* Device storage of the block-diagonal matrix of all local matrices. */
 enum {
     SS_MAT_AUTO = 0, /* SELL-64 unless rows are too uneven, else CSR row tiles */
-    SS_MAT_SELL = 1, /* chunks of 64 rows, one row per lane, column-major      */
+    SS_MAT_SELL = 1, /* chunks of 64 rows, one row per lane, column-major
+                        (rows of at most 255 entries and fewer than 2^29 local
+                        positions; otherwise CSR row tiles)                  */
     SS_MAT_CSR = 2   /* CSR cut into row tiles of tile_nnz entries             */
 };
 
@@ -381,7 +383,8 @@ int ss_band_extract(const ss_csr *A, int32_t kind, int32_t nbands, int32_t p, in
  * is done per row: each row's sum is split where its columns cross into the
  * next band.  Dot products and the stopping rule as ss_cg_solve.
  * o: SS_FP64 only (SS_EUNSUPPORTED otherwise); the band-column product needs
- * the SELL layout (rows of at most 255 entries; SS_EUNSUPPORTED otherwise).
+ * the SELL layout (rows of at most 255 entries, fewer than 2^29 rows;
+ * SS_EUNSUPPORTED otherwise).
  * Errors: SS_EINVAL (invalid CSR, unknown kind, nbands outside [1, n]),
  * SS_EUNSUPPORTED, SS_ENOMEM, SS_EDEVICE.
  */

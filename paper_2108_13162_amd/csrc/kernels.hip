@@ -131,6 +131,22 @@ __device__ __forceinline__ XT pupd(XT r, XT p, double beta)
     return (XT)((double)r + beta * (double)p);
 }
 
+// Element i of an array whose base is wave-uniform, through a 32-bit byte
+// offset: the base stays in scalar registers and a lane needs one VGPR for
+// the offset (arrays of at most 4 GiB: SELL storage is built for fewer than
+// 2^29 positions).
+template <typename T>
+__device__ __forceinline__ T ld32(const T *__restrict__ base, uint32_t i)
+{
+    return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) + i * (uint32_t)sizeof(T));
+}
+
+template <typename T>
+__device__ __forceinline__ void st32(T *__restrict__ base, uint32_t i, T v)
+{
+    *reinterpret_cast<T *>(reinterpret_cast<char *>(base) + i * (uint32_t)sizeof(T)) = v;
+}
+
 // PLAIN: q = A x.  FIRST / STEP: p = r + beta p formed on the fly at every
 // gathered column (beta = 0 for FIRST), q = A p, (p, A p) partials; STEP also
 // finishes (r, r) and applies the previous x update.  PQ: q = A p for a p
@@ -192,21 +208,6 @@ __device__ __forceinline__ double finish_rr(const double *__restrict__ part_b, c
 // Column position of a 16-bit entry: bit 15 selects the window base.
 __device__ __forceinline__ int narrow_col(uint32_t v, int2 base) { return ((v & 0x8000u) ? base.y : base.x) + (int)(v & 0x7fffu); }
 
-// Columns of entries j .. j+U-1 of a chunk (the last index repeated past L):
-// narrow chunks store 16-bit window offsets, wide ones int32 positions.
-template <int U>
-__device__ __forceinline__ void load_cols(int (&cc)[U], int cb, int2 base, int j0, int L, int lane,
-                                          const int32_t *__restrict__ col, const uint16_t *__restrict__ col16)
-{
-    if (cb >= 0) {
-#pragma unroll
-        for (int u = 0; u < U; ++u) cc[u] = narrow_col(col16[cb + min(j0 + u, L - 1) * 64 + lane], base);
-    } else {
-#pragma unroll
-        for (int u = 0; u < U; ++u) cc[u] = col[~cb + min(j0 + u, L - 1) * 64 + lane];
-    }
-}
-
 // Length of chunk c (wave-uniform), read as the 32-bit word holding its
 // byte so that it comes through the scalar path (the length array is padded
 // to whole words).
@@ -216,16 +217,18 @@ __device__ __forceinline__ int chunk_len(const uint8_t *__restrict__ clen, int c
     return (int)((wd >> (8 * (c & 3))) & 0xffu);
 }
 
-// The column words and the values of entries j0 .. j0+U-1 of a chunk, the
-// last entry repeated past L; decoded at use (decode_cols), so that the loads
-// can stay in flight across other work.  One 32-bit load per entry for either
-// kind of chunk: a wide chunk's int32 position, or the aligned word holding
-// the 16-bit offsets of lanes 2l and 2l+1 of a narrow chunk (every chunk's
-// offsets start at an even index, chunks being 64 entries a slot).
-template <typename VT, int U>
-__device__ __forceinline__ void load_batch(uint32_t (&cw)[U], VT (&vv)[U], int cb, int base, int j0, int L, int lane,
-                                           const int32_t *__restrict__ col, const uint16_t *__restrict__ col16,
-                                           const VT *__restrict__ val)
+// The loads of a one-batch chunk (see k_spmv_sell), addressed from the
+// chunk's wave-uniform bases: its values cv, its first row pos.
+//
+// The column words of slots j0..j0+U-1, the last slot repeated past L; decoded
+// at use (decode_cols), so that the loads can stay in flight across other
+// work.  One 32-bit load per entry for either kind of chunk: a wide chunk's
+// int32 position, or the aligned word holding the 16-bit offsets of lanes 2l
+// and 2l+1 of a narrow chunk (every chunk's offsets start at an even index,
+// chunks being 64 entries a slot).
+template <int U>
+__device__ __forceinline__ void load_cwords(uint32_t (&cw)[U], int cb, int j0, int L, int lane,
+                                            const int32_t *__restrict__ col, const uint16_t *__restrict__ col16)
 {
     const bool narrow = cb >= 0;
     const uint32_t *w32 = narrow ? reinterpret_cast<const uint32_t *>(col16 + cb)
@@ -233,37 +236,44 @@ __device__ __forceinline__ void load_batch(uint32_t (&cw)[U], VT (&vv)[U], int c
 #pragma unroll
     for (int u = 0; u < U; ++u) {
         const int off = max(min(j0 + u, L - 1), 0) * 64 + lane;
-        cw[u] = w32[narrow ? off >> 1 : off];
-        vv[u] = val[base + off];
+        cw[u] = ld32(w32, (uint32_t)(narrow ? off >> 1 : off));
     }
+}
+
+// The values of slots 0..U-1, the last slot repeated past L.
+template <typename VT, int U>
+__device__ __forceinline__ void load_vals(VT (&vv)[U], const VT *__restrict__ cv, int L, int lane)
+{
+#pragma unroll
+    for (int u = 0; u < U; ++u) vv[u] = ld32(cv, (uint32_t)(max(min(u, L - 1), 0) * 64 + lane));
 }
 
 // A row's own length and operands (r, p_{k-1}, x), at a clamped position
 // for the lanes past the last row.
 template <typename XT, int MODE>
-__device__ __forceinline__ void load_row(int &len, XT &rv, XT &pv, XT &xv, int row, int nrows,
+__device__ __forceinline__ void load_row(int &len, XT &rv, XT &pv, XT &xv, int pos, int lane, int nrows,
                                          const uint8_t *__restrict__ rlen, const XT *__restrict__ r,
                                          const XT *__restrict__ p, const XT *__restrict__ x)
 {
-    const int t = min(row, nrows - 1);
-    const int l = rlen[t];
-    len = row < nrows ? l : 0;
+    const uint32_t t = (uint32_t)min(lane, nrows - 1 - pos);
+    const int l = ld32(rlen + pos, t);
+    len = pos + lane < nrows ? l : 0;
     rv = pv = xv = XT(0);
-    if (MODE == SPMV_FIRST || MODE == SPMV_STEP) rv = r[t];
-    if (MODE != SPMV_PLAIN) pv = p[t];
-    if (MODE == SPMV_STEP) xv = x[t];
+    if (MODE == SPMV_FIRST || MODE == SPMV_STEP) rv = ld32(r + pos, t);
+    if (MODE != SPMV_PLAIN) pv = ld32(p + pos, t);
+    if (MODE == SPMV_STEP) xv = ld32(x + pos, t);
 }
 
 // load_row for a dictionary chunk of at most 7 slots: the length comes with
 // the lane's index word (and every row of the chunk exists).
 template <typename XT, int MODE>
-__device__ __forceinline__ void load_row_nolen(XT &rv, XT &pv, XT &xv, int row, const XT *__restrict__ r,
+__device__ __forceinline__ void load_row_nolen(XT &rv, XT &pv, XT &xv, int pos, int lane, const XT *__restrict__ r,
                                                const XT *__restrict__ p, const XT *__restrict__ x)
 {
     rv = pv = xv = XT(0);
-    if (MODE == SPMV_FIRST || MODE == SPMV_STEP) rv = r[row];
-    if (MODE != SPMV_PLAIN) pv = p[row];
-    if (MODE == SPMV_STEP) xv = x[row];
+    if (MODE == SPMV_FIRST || MODE == SPMV_STEP) rv = ld32(r + pos, (uint32_t)lane);
+    if (MODE != SPMV_PLAIN) pv = ld32(p + pos, (uint32_t)lane);
+    if (MODE == SPMV_STEP) xv = ld32(x + pos, (uint32_t)lane);
 }
 
 template <int U>
@@ -282,8 +292,8 @@ __device__ __forceinline__ void decode_cols(int (&cc)[U], const uint32_t (&cw)[U
 __device__ __forceinline__ void load_dict(uint32_t &dw, int &tab, int blk, int lane,
                                           const int32_t *__restrict__ dtab, const uint32_t *__restrict__ dword)
 {
-    dw = dword ? dword[blk * 64 + lane] : 0u;
-    tab = dtab ? dtab[blk * 16 + (lane & 15)] : 0;
+    dw = ld32(dword + blk * 64, (uint32_t)lane);
+    tab = ld32(dtab + blk * 16, (uint32_t)(lane & 15));
 }
 
 // Columns of a dictionary chunk's slots 0..U-1: the row plus the offset its
@@ -323,13 +333,12 @@ __device__ __forceinline__ int band_next(int col, int bm, int nbands)
 }
 
 // ONE: every chunk has at most U entries per row, so a chunk is one batch.
-// Then the wave software-pipelines its chunks: the gathers of chunk c are
-// issued first, then the loads of chunk c+W (header, values, columns, the
-// row's own r, p, x) -- always the same loads, at clamped indexes past the
-// wave's last chunk -- so that the products of chunk c wait for its gathers
-// only (vector loads return in issue order) while chunk c+W's loads stay in
-// flight.  Otherwise (rows longer than U) the batches of each chunk are
-// walked in turn, each batch's gathers waiting for its own loads.
+// Then the wave software-pipelines its chunks: a chunk's columns are loaded
+// with the chunk before, and its gathers, values and own operands go out
+// together with the next chunk's columns, behind one wait.  Otherwise (rows
+// longer than U) the batches of each chunk are walked in turn, the same way
+// batch to batch.  Every vector is addressed from its base through 32-bit
+// offsets (fewer than 2^29 positions).
 // BAND: the band-column product (positions are global ids, bands of bm).
 // DICT_ON (ONE, U <= 8, no BAND): the chunks with an offset dictionary
 // (cdict, dtab, dword) come first in the workgroup's range and take their
@@ -349,6 +358,8 @@ __global__ __launch_bounds__(kBS) __attribute__((amdgpu_waves_per_eu(1, 4))) voi
     constexpr bool PUPD = MODE == SPMV_FIRST || MODE == SPMV_STEP;  // p formed here
     // rows of several batches with the wide offset dictionaries
     constexpr bool WIDE = !ONE && DICT_ON && !BAND && U <= 10;
+    // one-batch rows of at most 8 entries with the offset dictionaries
+    constexpr bool USE_DICT = ONE && DICT_ON && U <= 8 && !BAND;
     constexpr int W = kBS / 64;
     __shared__ double ws[2 * (kBS / 64) + 2];
     __shared__ int s_flag;
@@ -362,14 +373,13 @@ __global__ __launch_bounds__(kBS) __attribute__((amdgpu_waves_per_eu(1, 4))) voi
     const int cend = min(rb * cpb + cpb, nchunks);
     int c = rb * cpb + w;
 
-    // first batch of the first chunk (and, for ONE, the row's own operands),
-    // loaded before beta is known
+    // the columns of the first chunk's first batch, loaded before beta is
+    // known
     int cc[U];
-    uint32_t cw[U];  // ONE: column words of chunk c, decoded at use
-    VT vv[U];
-    int base = 0, L = 0, cb = 0, row = 0, len = 0, blk = -1;
+    uint32_t cw[U];      // column words of the next batch to run, decoded at use
+    uint64_t wbits = 0;  // several batches, wide dictionary: that batch's index word
+    int base = 0, L = 0, cb = 0, pos = 0, row = 0, len = 0, blk = -1;
     int2 wb = make_int2(0, 0);
-    XT rrow = XT(0), prow = XT(0), xrow = XT(0);
     uint32_t dw = 0;  // ONE, dictionary chunk: the lane's 4-bit offset indices
     int tab = 0;      // and offset (lane & 15) of the chunk's table (wide: entry lane of 64)
     if (c < cend) {
@@ -377,26 +387,25 @@ __global__ __launch_bounds__(kBS) __attribute__((amdgpu_waves_per_eu(1, 4))) voi
         L = chunk_len(clen, c);
         cb = ccol[c];
         if (cb >= 0) wb = cbase[c];
-        row = cpos[c] + lane;
+        pos = cpos[c];
+        row = pos + lane;
         if constexpr (ONE) {
-            // both encodings (block 0 stands in when the chunk has none)
-            if (DICT_ON && U <= 8 && !BAND && cdict) {
-                blk = cdict[c];
-                load_dict(dw, tab, max(blk, 0), lane, dtab, dword);
-            }
-            load_batch<VT, U>(cw, vv, cb, base, 0, L, lane, col, col16, val);
-            load_row<XT, MODE>(len, rrow, prow, xrow, row, nrows, rlen, r, pin, x);
+            // the chunk's columns in its own encoding
+            if (USE_DICT) blk = cdict[c];
+            if (USE_DICT && blk >= 0)
+                load_dict(dw, tab, blk, lane, dtab, dword);
+            else
+                load_cwords<U>(cw, cb, 0, L, lane, col, col16);
         } else {
+            // the first batch's columns
             if (WIDE) {
                 blk = cdict[c];
-                if (blk >= 0) tab = dtab[blk * 64 + lane];
+                if (blk >= 0) tab = ld32(dtab + blk * 64, (uint32_t)lane);
             }
             if (WIDE && blk >= 0)
-                decode_wide<U>(cc, wide_word(dword, blk, dict_batches, 0, lane), tab, row);
+                wbits = wide_word(dword, blk, dict_batches, 0, lane);
             else
-                load_cols<U>(cc, cb, wb, 0, L, lane, col, col16);
-#pragma unroll
-            for (int u = 0; u < U; ++u) vv[u] = val[base + min(u, L - 1) * 64 + lane];
+                load_cwords<U>(cw, cb, 0, L, lane, col, col16);
         }
     }
     // x_k = x_{k-1} + alpha p_{k-1} is deferred to here.  It is owed whenever
@@ -421,23 +430,27 @@ __global__ __launch_bounds__(kBS) __attribute__((amdgpu_waves_per_eu(1, 4))) voi
 
     double acc = 0.0;
     if constexpr (ONE) {
-        // Inside the workgroup's range the dictionary chunks come first: the
-        // wave runs them in a loop that reads one word of offset indices per
-        // lane and the chunk's offsets, then the others in the loop that reads
-        // one column word per entry.  The registers hold chunk c (`have`).
-        // (rows of at most 8 entries, not the band-column product; the other
-        // instantiations ignore the dictionaries)
-        constexpr bool USE_DICT = DICT_ON && U <= 8 && !BAND;
-        bool have = true;
+        // Every chunk is one batch, and the wave software-pipelines its chunks:
+        // for chunk c it issues the gathers (their columns were loaded with the
+        // previous chunk), then chunk c's values and its rows' own r, p, x,
+        // then the columns of its next chunk c+W (the header through the
+        // scalar path, then the column or index words -- always the same loads,
+        // at chunk c again when there is no next chunk of the kind), waits once
+        // for all of them and for chunk c-W's stores, computes chunk c and
+        // issues its stores.  So each chunk waits for one round trip of memory,
+        // on loads and stores issued together, and only the next chunk's
+        // columns are held across it.  Inside the workgroup's range the
+        // dictionary chunks come first: the wave runs them in one loop, which
+        // takes the columns from the index words, and then the rest of its
+        // chunks in a second loop, which takes them from the column words
+        // (every chunk has those).
+        bool have = true;  // the next chunk is of the running loop's kind
         auto run_chunk = [&](auto kind) {
             constexpr bool DICT = decltype(kind)::value && USE_DICT;
-            // drain the previous chunk's stores (and this chunk's loads, needed
-            // now): with stores outstanding the compiler can only wait for the
-            // gathers below by draining everything
-            __builtin_amdgcn_s_waitcnt(dev::kWaitVmcnt0);
-            // a dictionary chunk of at most 7 slots: the row length is the top
-            // 4 bits of the index word
-            if constexpr (DICT && U < 8) len = (int)(dw >> 28);
+            // a dictionary chunk's rows all exist; with at most 7 slots their
+            // lengths come with the index words (top 4 bits)
+            constexpr bool LEN_IN_WORD = DICT && U < 8;
+            if constexpr (LEN_IN_WORD) len = (int)(dw >> 28);
             XT rx[U], px[U];
             if constexpr (DICT)
                 decode_dict<U>(cc, dw, tab, row);
@@ -445,44 +458,43 @@ __global__ __launch_bounds__(kBS) __attribute__((amdgpu_waves_per_eu(1, 4))) voi
                 decode_cols<U>(cc, cw, cb, wb, lane);
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                if (PUPD) rx[u] = r[cc[u]];
-                px[u] = pin[cc[u]];
+                if (PUPD) rx[u] = ld32(r, (uint32_t)cc[u]);
+                px[u] = ld32(pin, (uint32_t)cc[u]);
             }
-            // keep the issue order: the scheduler would otherwise interleave
-            // the two groups of loads, and the products would wait for both
+            // keep the issue order: the gathers first
             __builtin_amdgcn_sched_barrier(0);
-            // the wave's next chunk when it is of this kind, else chunk c again
-            // (unused)
+            // chunk c's values and its rows' own operands
+            VT cv[U];
+            load_vals<VT, U>(cv, val + base, L, lane);
+            XT ro, po, xo;
+            if constexpr (LEN_IN_WORD)
+                load_row_nolen<XT, MODE>(ro, po, xo, pos, lane, r, pin, x);
+            else
+                load_row<XT, MODE>(len, ro, po, xo, pos, lane, nrows, rlen, r, pin, x);
+            // the columns of the wave's next chunk when it is of this kind, else
+            // of chunk c again (unused)
             const int nc = c + W;
-            const bool nxt = nc < cend && (!USE_DICT || ((cdict ? cdict[nc] : -1) >= 0) == DICT);
+            const bool nxt = nc < cend && (!DICT || cdict[nc] >= 0);
             const int lc = nxt ? nc : c;
-            const int nbase = cptr[lc], nL = chunk_len(clen, lc), ncb = ccol[lc];
-            const int2 nwb = cbase[lc];
-            const int nrow = cpos[lc] + lane;
-            const int nblk = USE_DICT && cdict ? cdict[lc] : -1;
+            const int nbase = cptr[lc], nL = chunk_len(clen, lc), npos = cpos[lc];
+            int ncb = 0;
+            int2 nwb = make_int2(0, 0);
             uint32_t ncw[U], ndw = 0;
             int ntab = 0;
-            VT nvv[U];
             if constexpr (DICT) {
-                load_dict(ndw, ntab, nblk, lane, dtab, dword);
-#pragma unroll
-                for (int u = 0; u < U; ++u) nvv[u] = val[nbase + min(u, nL - 1) * 64 + lane];
+                load_dict(ndw, ntab, cdict[lc], lane, dtab, dword);
             } else {
-                load_batch<VT, U>(ncw, nvv, ncb, nbase, 0, nL, lane, col, col16, val);
+                ncb = ccol[lc];
+                nwb = cbase[lc];
+                load_cwords<U>(ncw, ncb, 0, nL, lane, col, col16);
             }
-            int nlen = 0;
-            XT nr, np, nx;
-            // a dictionary chunk's rows all exist; with at most 7 slots their
-            // lengths come with the index words
-            constexpr bool LEN_IN_WORD = DICT && U < 8;
-            if constexpr (LEN_IN_WORD)
-                load_row_nolen<XT, MODE>(nr, np, nx, nrow, r, pin, x);
-            else
-                load_row<XT, MODE>(nlen, nr, np, nx, nrow, nrows, rlen, r, pin, x);
             __builtin_amdgcn_sched_barrier(0);
+            // one wait for all that is in flight (with stores outstanding a
+            // wait for the gathers alone is not possible)
+            __builtin_amdgcn_s_waitcnt(dev::kWaitVmcnt0);
             XT prod[U];
 #pragma unroll
-            for (int u = 0; u < U; ++u) prod[u] = (XT)vv[u] * (PUPD ? pupd(rx[u], px[u], beta) : px[u]);
+            for (int u = 0; u < U; ++u) prod[u] = (XT)cv[u] * (PUPD ? pupd(rx[u], px[u], beta) : px[u]);
             XT sacc = XT(0);
             if constexpr (BAND) {
                 // the products exist before the band bookkeeping branches
@@ -510,112 +522,134 @@ __global__ __launch_bounds__(kBS) __attribute__((amdgpu_waves_per_eu(1, 4))) voi
             // products -- and the gathers with them -- into the store branch
             asm volatile("" : "+v"(sacc));
             if (row < nrows) {
-                q[row] = sacc;
+                st32(q + pos, (uint32_t)lane, sacc);
                 if (CG) {
-                    const XT pr = PUPD ? pupd(rrow, prow, beta) : prow;
-                    if (PUPD) pout[row] = pr;
-                    if (MODE == SPMV_STEP) x[row] = (XT)((double)xrow + alpha * (double)prow);
+                    const XT pr = PUPD ? pupd(ro, po, beta) : po;
+                    if (PUPD) st32(pout + pos, (uint32_t)lane, pr);
+                    if (MODE == SPMV_STEP) st32(x + pos, (uint32_t)lane, (XT)((double)xo + alpha * (double)po));
                     acc = acc + (double)pr * (double)sacc;
                 }
             }
             c = nc;
             have = nxt;
-            cb = ncb;
-            wb = nwb;
-            row = nrow;
-            if constexpr (!LEN_IN_WORD) len = nlen;
-            blk = nblk;
-            rrow = nr;
-            prow = np;
-            xrow = nx;
+            base = nbase;
+            L = nL;
+            pos = npos;
+            row = npos + lane;
             if constexpr (DICT) {
                 dw = ndw;
                 tab = ntab;
-            }
+            } else {
+                cb = ncb;
+                wb = nwb;
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
-                if constexpr (!DICT) cw[u] = ncw[u];
-                vv[u] = nvv[u];
+                for (int u = 0; u < U; ++u) cw[u] = ncw[u];
             }
         };
-        if constexpr (!USE_DICT) {
-            while (c < cend) run_chunk(std::false_type{});
-        } else {
-        while (c < cend) {
-            if (!have) {
-                // a chunk of the other kind (once per wave with the host's order)
-                base = cptr[c];
-                L = chunk_len(clen, c);
-                cb = ccol[c];
-                if (cb >= 0) wb = cbase[c];
-                row = cpos[c] + lane;
-                blk = cdict ? cdict[c] : -1;
-                load_dict(dw, tab, max(blk, 0), lane, dtab, dword);
-                load_batch<VT, U>(cw, vv, cb, base, 0, L, lane, col, col16, val);
-                load_row<XT, MODE>(len, rrow, prow, xrow, row, nrows, rlen, r, pin, x);
-                have = true;
-            }
-            if (blk >= 0) {
-                while (have && c < cend) run_chunk(std::true_type{});
-            } else {
-                while (have && c < cend) run_chunk(std::false_type{});
-            }
-        }
-        }
-    } else {
-        bool have = true;  // cc / vv hold batch 0 of chunk c
-        for (; c < cend; c += W) {
-            if (!have) {
-                base = cptr[c];
-                L = chunk_len(clen, c);
-                cb = ccol[c];
-                if (cb >= 0) wb = cbase[c];
-                row = cpos[c] + lane;
-                if (WIDE) {
-                    blk = cdict[c];
-                    if (blk >= 0) tab = dtab[blk * 64 + lane];
+        if constexpr (USE_DICT) {
+            if (c < cend && blk >= 0) {
+                do
+                    run_chunk(std::true_type{});
+                while (have);
+                // the rest of the wave's chunks: column words
+                if (c < cend) {
+                    base = cptr[c];
+                    L = chunk_len(clen, c);
+                    cb = ccol[c];
+                    wb = cbase[c];
+                    pos = cpos[c];
+                    row = pos + lane;
+                    load_cwords<U>(cw, cb, 0, L, lane, col, col16);
                 }
             }
-            len = row < nrows ? (int)rlen[row] : 0;
+        }
+        while (c < cend) run_chunk(std::false_type{});
+    } else {
+        // Rows of several batches.  The wave walks its chunks batch by batch.
+        // For each batch it issues the gathers (their columns were loaded with
+        // the batch before), the batch's values and the columns of the next
+        // batch -- of this chunk, or the first of the wave's next chunk --, and
+        // waits once for all of them; the rows' lengths and own operands come
+        // with a chunk's first batch.
+        for (; c < cend; c += W) {
+            // the wave's next chunk (chunk c again past the end: its first
+            // batch's columns are loaded and not used)
+            const int nc = c + W;
+            const int lc = nc < cend ? nc : c;
+            const int nbase = cptr[lc], nL = chunk_len(clen, lc), ncb = ccol[lc], npos = cpos[lc];
+            const int2 nwb = cbase[lc];
+            const int nblk = WIDE ? cdict[lc] : -1;
+            const uint32_t t = (uint32_t)min(lane, nrows - 1 - pos);
+            const int l = ld32(rlen + pos, t);
+            len = pos + lane < nrows ? l : 0;
+            XT ro = XT(0), po = XT(0), xo = XT(0);
+            if (CG) po = ld32(pin + pos, t);
+            if (PUPD) ro = ld32(r + pos, t);
+            if (MODE == SPMV_STEP) xo = ld32(x + pos, t);
             XT sacc = XT(0);
             XT btot = XT(0);
             int bnext = -1;
             for (int j0 = 0; j0 < L; j0 += U) {
-                if (!have) {
-                    if (WIDE && blk >= 0)
-                        decode_wide<U>(cc, wide_word(dword, blk, dict_batches, j0 / U, lane), tab, row);
-                    else
-                        load_cols<U>(cc, cb, wb, j0, L, lane, col, col16);
+                if (WIDE && blk >= 0)
+                    decode_wide<U>(cc, wbits, tab, row);
+                else
+                    decode_cols<U>(cc, cw, cb, wb, lane);
+                XT xr[U], xp[U];
 #pragma unroll
-                    for (int u = 0; u < U; ++u) vv[u] = val[base + min(j0 + u, L - 1) * 64 + lane];
+                for (int u = 0; u < U; ++u) {
+                    if (PUPD) xr[u] = ld32(r, (uint32_t)cc[u]);
+                    xp[u] = ld32(pin, (uint32_t)cc[u]);
                 }
-                have = false;
-                XT xx[U];
+                __builtin_amdgcn_sched_barrier(0);
+                VT bv[U];
 #pragma unroll
-                for (int u = 0; u < U; ++u) xx[u] = PUPD ? pupd(r[cc[u]], pin[cc[u]], beta) : pin[cc[u]];
+                for (int u = 0; u < U; ++u) bv[u] = ld32(val + base, (uint32_t)(min(j0 + u, L - 1) * 64 + lane));
+                if (j0 + U < L) {
+                    if (WIDE && blk >= 0)
+                        wbits = wide_word(dword, blk, dict_batches, j0 / U + 1, lane);
+                    else
+                        load_cwords<U>(cw, cb, j0 + U, L, lane, col, col16);
+                } else {
+                    if (WIDE && nblk >= 0) {
+                        tab = ld32(dtab + nblk * 64, (uint32_t)lane);
+                        wbits = wide_word(dword, nblk, dict_batches, 0, lane);
+                    } else {
+                        load_cwords<U>(cw, ncb, 0, nL, lane, col, col16);
+                    }
+                }
+                __builtin_amdgcn_sched_barrier(0);
+                // one wait for all that is in flight (see the one-batch loop)
+                __builtin_amdgcn_s_waitcnt(dev::kWaitVmcnt0);
 #pragma unroll
-                for (int u = 0; u < U; ++u)
+                for (int u = 0; u < U; ++u) {
+                    const XT xx = PUPD ? pupd(xr[u], xp[u], beta) : xp[u];
                     if (j0 + u < len) {
                         if (BAND && cc[u] >= bnext) {
                             btot = btot + sacc;
                             sacc = XT(0);
                             bnext = band_next(cc[u], bm, nbands);
                         }
-                        sacc = sacc + (XT)vv[u] * xx[u];
+                        sacc = sacc + (XT)bv[u] * xx;
                     }
+                }
             }
             if (BAND) sacc = btot + sacc;
-            have = false;
             if (row < nrows) {
-                q[row] = sacc;
+                st32(q + pos, (uint32_t)lane, sacc);
                 if (CG) {
-                    const XT pold = pin[row];
-                    const XT pr = PUPD ? pupd(r[row], pold, beta) : pold;
-                    if (PUPD) pout[row] = pr;
-                    if (MODE == SPMV_STEP) x[row] = (XT)((double)x[row] + alpha * (double)pold);
+                    const XT pr = PUPD ? pupd(ro, po, beta) : po;
+                    if (PUPD) st32(pout + pos, (uint32_t)lane, pr);
+                    if (MODE == SPMV_STEP) st32(x + pos, (uint32_t)lane, (XT)((double)xo + alpha * (double)po));
                     acc = acc + (double)pr * (double)sacc;
                 }
             }
+            base = nbase;
+            L = nL;
+            cb = ncb;
+            wb = nwb;
+            pos = npos;
+            row = npos + lane;
+            blk = nblk;
         }
     }
     if (CG) {

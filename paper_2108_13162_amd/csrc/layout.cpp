@@ -21,6 +21,8 @@ constexpr int kSmallChunks = 16384;
 // Offset dictionary of a chunk: at most kDictOffsets distinct column - row
 // offsets, rows of at most kDictSlots entries (4-bit indices, 8 to a word).
 constexpr int kDictOffsets = 16;
+// SELL storage holds fewer local positions than this (FP64 vectors under 4 GiB).
+constexpr int32_t kSellMaxRows = 1 << 29;
 constexpr int kDictSlots = 8;
 constexpr int kDictMinPerWg = 24;  // chunks per SpMV workgroup for the dictionaries to pay
 // Rows of several load batches: at most 64 offsets (6-bit indices, a batch of
@@ -96,7 +98,8 @@ void build_matrix(const ss_part *p, Layout &L, int32_t tile_nnz, int32_t force, 
         for (int32_t t = c * 64; t < std::min(nl, c * 64 + 64); ++t) m = std::max(m, row_len(t));
         padded += 64 * (int64_t)m;
     }
-    const bool sell_ok = maxlen <= 255 && padded < INT32_MAX;
+    // (the SELL SpMV addresses its vectors through 32-bit byte offsets)
+    const bool sell_ok = maxlen <= 255 && padded < INT32_MAX && nl < kSellMaxRows;
     bool sell = sell_ok && padded <= p->nnz + p->nnz / 4;
     if (force == SS_MAT_SELL && sell_ok) sell = true;
     if (force == SS_MAT_CSR) sell = false;
