@@ -95,6 +95,53 @@ __device__ __forceinline__ double sum_partials_vec(const double *__restrict__ pa
     return v;
 }
 
+// The first round of sum_partials_vec loaded ahead, so that these loads go
+// out with a kernel's first operand loads and share their wait: pairs t,
+// t + kBS, ..., t + (R-1) kBS of thread t.  The loads are unconditional (at
+// the last pair past the end; n >= 2, the grids being multiples of 8) and
+// the pairs past the end are dropped where they are added, so that no use
+// sits next to a load.
+template <int R>
+__device__ __forceinline__ void pre_pairs(double2 (&t)[R], const double *__restrict__ partial, int n)
+{
+    const double2 *p2 = reinterpret_cast<const double2 *>(partial);
+    const int last = (n >> 1) - 1;
+#pragma unroll
+    for (int i = 0; i < R; ++i) t[i] = p2[min(i * kBS + (int)threadIdx.x, last)];
+}
+
+// sum_partials_vec from a preloaded first round: thread t still adds its
+// pairs t, t + kBS, ... in turn (+0 past the end changes nothing), so the
+// bits are the same.
+template <int R>
+__device__ __forceinline__ double sum_pre(const double2 (&t)[R], const double *__restrict__ partial, int n)
+{
+    const double2 *p2 = reinterpret_cast<const double2 *>(partial);
+    const int npair = n >> 1;
+    double v = 0.0;
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+        const bool in = i * kBS + (int)threadIdx.x < npair;
+        v = v + (in ? t[i].x : 0.0);
+        v = v + (in ? t[i].y : 0.0);
+    }
+    for (int base = R * kBS; base < npair; base += 8 * kBS) {
+        double2 u[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const int idx = base + i * kBS + (int)threadIdx.x;
+            u[i] = idx < npair ? p2[idx] : make_double2(0.0, 0.0);
+        }
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            v = v + u[i].x;
+            v = v + u[i].y;
+        }
+    }
+    if ((n & 1) && threadIdx.x == 0) v = v + partial[n - 1];
+    return v;
+}
+
 // Two fixed-order workgroup sums in one pass (each with exactly the order of
 // block_sum_all).  ws: 2 * (kBS/64) + 2 slots.
 __device__ __forceinline__ void block_sum2_all(double &a, double &b, double *ws)
@@ -153,30 +200,42 @@ __device__ __forceinline__ void st32(T *__restrict__ base, uint32_t i, T v)
 // already formed (k_pstep), (p, A p) partials.
 enum { SPMV_PLAIN = 0, SPMV_FIRST = 1, SPMV_STEP = 2, SPMV_PQ = 3 };
 
-// The CG-step prologue: finish (r, r) [and (r, z)] of the previous update,
-// record iteration k+1 (workgroup 0), stopping test on ||r||.  Returns
-// beta = (r, z)_new / (r, z), or sets *stop.  part_b2 = nullptr: no
-// preconditioner, (r, z) = (r, r).
-__device__ __forceinline__ double finish_rr(const double *__restrict__ part_b, const double *__restrict__ part_b2,
-                                            int nb, int slot, DevState *st, double *ws, bool *stop_out)
+// Pairs of partials per thread loaded ahead: of the update partials by the
+// CG-step SpMV (one per kUI * kBS positions: one round up to ~3M positions)
+// and by k_pstep (a streaming kernel that keeps its registers for occupancy,
+// 8 waves per SIMD: ~1M positions, and (r, z) not ahead), of the SpMV
+// partials by the update (one per SpMV workgroup: up to 2048).
+constexpr int kPreRound = 12;
+constexpr int kPreRoundS = 4;
+constexpr int kPreRoundA = 4;
+
+// The state a CG step reads before its stopping test, loaded with the
+// step's first operands (no kernel of the step writes these fields).
+struct StepIn {
+    double rz;    // (r, z) of the slot
+    double stop;  // threshold on ||r||
+    int32_t iter, kmax;
+};
+
+__device__ __forceinline__ StepIn load_step_in(const DevState *st, int slot)
 {
-    double rr_new, rz_new;
-    if (part_b2) {
-        rr_new = sum_partials_vec(part_b, nb);
-        rz_new = sum_partials_vec(part_b2, nb);
-        block_sum2_all(rr_new, rz_new, ws);
-    } else {
-        rr_new = block_sum_all(sum_partials_vec(part_b, nb), ws);
-        rz_new = rr_new;
-    }
-    const double rz_cur = st->rz[slot];
-    const int k_new = st->iter[slot] + 1;
+    return StepIn{st->rz[slot], st->stop, st->iter[slot], st->kmax};
+}
+
+// The CG-step prologue: from the finished (r, r) [and (r, z)] of the
+// previous update, record iteration k+1 (workgroup 0) and take the stopping
+// test on ||r||.  Returns beta = (r, z)_new / (r, z), or sets *stop.
+__device__ __forceinline__ double step_test(double rr_new, double rz_new, StepIn in, int slot, DevState *st,
+                                            bool *stop_out)
+{
+    const double rz_cur = in.rz;
+    const int k_new = in.iter + 1;
     int stop = ST_RUNNING;
     if (!isfinite(rr_new) || !isfinite(rz_new))
         stop = ST_BREAKDOWN;
-    else if (sqrt(rr_new) <= st->stop)
+    else if (sqrt(rr_new) <= in.stop)
         stop = ST_CONVERGED;
-    else if (k_new >= st->kmax)
+    else if (k_new >= in.kmax)
         stop = ST_MAXIT;
     const double beta = rz_new / rz_cur;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -193,6 +252,42 @@ __device__ __forceinline__ double finish_rr(const double *__restrict__ part_b, c
     }
     *stop_out = stop != ST_RUNNING;
     return beta;
+}
+
+// finish (r, r) [and (r, z)] from the update partials, then step_test.
+// part_b2 = nullptr: no preconditioner, (r, z) = (r, r).
+__device__ __forceinline__ double finish_rr(const double *__restrict__ part_b, const double *__restrict__ part_b2,
+                                            int nb, int slot, DevState *st, double *ws, bool *stop_out)
+{
+    double rr_new, rz_new;
+    if (part_b2) {
+        rr_new = sum_partials_vec(part_b, nb);
+        rz_new = sum_partials_vec(part_b2, nb);
+        block_sum2_all(rr_new, rz_new, ws);
+    } else {
+        rr_new = block_sum_all(sum_partials_vec(part_b, nb), ws);
+        rz_new = rr_new;
+    }
+    return step_test(rr_new, rz_new, load_step_in(st, slot), slot, st, stop_out);
+}
+
+// The same from preloaded first rounds of the partials and state.
+template <int R>
+__device__ __forceinline__ double finish_rr_pre(const double2 (&tb)[R], const double2 (&tb2)[R],
+                                                const double *__restrict__ part_b,
+                                                const double *__restrict__ part_b2, int nb, StepIn in, int slot,
+                                                DevState *st, double *ws, bool *stop_out)
+{
+    double rr_new, rz_new;
+    if (part_b2) {
+        rr_new = sum_pre<R>(tb, part_b, nb);
+        rz_new = sum_pre<R>(tb2, part_b2, nb);
+        block_sum2_all(rr_new, rz_new, ws);
+    } else {
+        rr_new = block_sum_all(sum_pre<R>(tb, part_b, nb), ws);
+        rz_new = rr_new;
+    }
+    return step_test(rr_new, rz_new, in, slot, st, stop_out);
 }
 
 // ---- local SpMV, SELL-64 -----------------------------------------------------
@@ -364,8 +459,10 @@ __global__ __launch_bounds__(kBS) __attribute__((amdgpu_waves_per_eu(1, 4))) voi
     __shared__ double ws[2 * (kBS / 64) + 2];
     __shared__ int s_flag;
     if (gate && dev::flag_load(gate) == 0) return;
-    // the status word is read while the first matrix loads are in flight
-    if (CG && threadIdx.x == 0) s_flag = load_status(st);
+    // the status word, the first chunk's columns and (STEP) the first round
+    // of the update partials and the state go out together, behind one wait
+    int flag0 = ST_RUNNING;
+    if (CG && threadIdx.x == 0) flag0 = load_status(st);
     // the wave index is uniform: chunk headers come through the scalar path
     const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
     const int rb = xcd_remap(blockIdx.x, gridDim.x);
@@ -408,17 +505,26 @@ __global__ __launch_bounds__(kBS) __attribute__((amdgpu_waves_per_eu(1, 4))) voi
                 load_cwords<U>(cw, cb, 0, L, lane, col, col16);
         }
     }
+    double2 tb[kPreRound], tb2[kPreRound];
+    StepIn in{};
+    if constexpr (MODE == SPMV_STEP) {
+        pre_pairs<kPreRound>(tb, part_b, nb);
+        if (part_b2) pre_pairs<kPreRound>(tb2, part_b2, nb);
+        in = load_step_in(st, slot);
+    }
     // x_k = x_{k-1} + alpha p_{k-1} is deferred to here.  It is owed whenever
     // the update of this slot ran (alpha != 0), whatever the status shows by
     // now: workgroup 0 may already have recorded this step's stop.
     const double alpha = MODE == SPMV_STEP ? st->alpha[slot] : 0.0;
     bool stop = false;
     if (CG) {
+        if (threadIdx.x == 0) s_flag = flag0;
         __syncthreads();
         stop = s_flag != ST_RUNNING;
     }
     double beta = 0.0;
-    if (MODE == SPMV_STEP && !stop) beta = finish_rr(part_b, part_b2, nb, slot, st, ws, &stop);
+    if (MODE == SPMV_STEP && !stop)
+        beta = finish_rr_pre<kPreRound>(tb, tb2, part_b, part_b2, nb, in, slot, st, ws, &stop);
     if (stop) {
         if (MODE == SPMV_STEP && alpha != 0.0)
             for (int c2 = rb * cpb + w; c2 < cend; c2 += W) {
@@ -677,9 +783,11 @@ __global__ __launch_bounds__(kBS) void k_pstep(int32_t n, const XT *__restrict__
     constexpr int B = kUI * kBS;
     __shared__ double ws[2 * (kBS / 64) + 2];
     __shared__ int s_flag;
-    if (threadIdx.x == 0) s_flag = load_status(st);
+    // the status word, the operands, the first round of the update partials
+    // and the state go out together (as in k_spmv_sell)
+    int flag0 = ST_RUNNING;
+    if (threadIdx.x == 0) flag0 = load_status(st);
     const int b0 = (int)blockIdx.x * B;
-    // operands loaded before beta is known
     XT rv[kUI], pv[kUI], xv[kUI];
 #pragma unroll
     for (int i = 0; i < kUI; ++i) {
@@ -688,12 +796,27 @@ __global__ __launch_bounds__(kBS) void k_pstep(int32_t n, const XT *__restrict__
         pv[i] = pin[c];
         xv[i] = x[c];
     }
+    double2 tb[kPreRoundS];
+    pre_pairs<kPreRoundS>(tb, part_b, nb);
+    const StepIn in = load_step_in(st, slot);
     // the x update is owed whenever this slot's update ran (see k_spmv_sell)
     const double alpha = st->alpha[slot];
+    if (threadIdx.x == 0) s_flag = flag0;
     __syncthreads();
     bool stop = s_flag != ST_RUNNING;
     double beta = 0.0;
-    if (!stop) beta = finish_rr(part_b, part_b2, nb, slot, st, ws, &stop);
+    if (!stop) {
+        // (r, z) of a preconditioned run from the partials as they come
+        double rr_new = sum_pre<kPreRoundS>(tb, part_b, nb), rz_new;
+        if (part_b2) {
+            rz_new = sum_partials_vec(part_b2, nb);
+            block_sum2_all(rr_new, rz_new, ws);
+        } else {
+            rr_new = block_sum_all(rr_new, ws);
+            rz_new = rr_new;
+        }
+        beta = step_test(rr_new, rz_new, in, slot, st, &stop);
+    }
 #pragma unroll
     for (int i = 0; i < kUI; ++i) {
         const int c = b0 + (int)threadIdx.x + i * kBS;
@@ -847,8 +970,10 @@ __global__ __launch_bounds__(kBS) void k_update(int32_t n_loc, int32_t n_own, in
     constexpr int B = kUI * kBS;
     __shared__ double ws[2 * (kBS / 64) + 2];
     __shared__ int s_flag;
-    // the status word is read while the first operand loads are in flight
-    if (threadIdx.x == 0) s_flag = load_status(st);
+    // the status word, the operands of a full interior batch, the first round
+    // of the SpMV partials and (r, z) go out together, behind one wait
+    int flag0 = ST_RUNNING;
+    if (threadIdx.x == 0) flag0 = load_status(st);
     const bool pc = dinv != nullptr;
     const int b0 = (int)blockIdx.x * B;
     // a full batch of interior positions: operands loaded before alpha is known
@@ -864,6 +989,10 @@ __global__ __launch_bounds__(kBS) void k_update(int32_t n_loc, int32_t n_own, in
             dv[i] = pc ? dinv[c] : 1.0;
         }
     }
+    double2 ta[kPreRoundA];
+    pre_pairs<kPreRoundA>(ta, part_a, na);
+    const double rz_cur = st->rz[slot];
+    if (threadIdx.x == 0) s_flag = flag0;
     __syncthreads();
     if (s_flag != ST_RUNNING) {
         // no update this slot: the next step owes no x update
@@ -872,9 +1001,9 @@ __global__ __launch_bounds__(kBS) void k_update(int32_t n_loc, int32_t n_own, in
     }
 
     // finish (p, A p): alpha, or a breakdown when it is not positive
-    const double pAp = block_sum_all(sum_partials_vec(part_a, na), ws);
+    const double pAp = block_sum_all(sum_pre<kPreRoundA>(ta, part_a, na), ws);
     const bool bad = !(pAp > 0.0) || !isfinite(pAp);
-    const double alpha = st->rz[slot] / pAp;
+    const double alpha = rz_cur / pAp;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         st->pAp = pAp;
         st->alpha[slot] = bad ? 0.0 : alpha;
