@@ -110,7 +110,7 @@ inline bool split_step(const Mat &A) { return A.fmt == FMT_SELL && !A.one_batch;
 // workgroup, interface batches first.
 struct Iface {
     int32_t n_loc, n_own, n_if;
-    int32_t grid;                 // workgroups of the update kernels (multiple of 8)
+    int32_t grid;                 // workgroups of the update kernels (one per kUI * kBS positions)
     const int32_t *pos_grp, *copy_ptr, *copy_pos;
     int32_t ngamma;
     const double *dinv;           // Jacobi: 1 / a_ii of every position, or nullptr (no preconditioner)

@@ -97,17 +97,22 @@ __device__ __forceinline__ double sum_partials_vec(const double *__restrict__ pa
 
 // The first round of sum_partials_vec loaded ahead, so that these loads go
 // out with a kernel's first operand loads and share their wait: pairs t,
-// t + kBS, ..., t + (R-1) kBS of thread t.  The loads are unconditional (at
-// the last pair past the end; n >= 2, the grids being multiples of 8) and
-// the pairs past the end are dropped where they are added, so that no use
-// sits next to a load.
+// t + kBS, ..., t + (R-1) kBS of thread t.  The loads are unconditional (past
+// the end they repeat the last pair; with a single partial there is no pair
+// to load) and the pairs past the end are dropped where they are added, so
+// that no use sits next to a load.
 template <int R>
 __device__ __forceinline__ void pre_pairs(double2 (&t)[R], const double *__restrict__ partial, int n)
 {
     const double2 *p2 = reinterpret_cast<const double2 *>(partial);
-    const int last = (n >> 1) - 1;
+    const int npair = n >> 1;
+    if (npair == 0) {
 #pragma unroll
-    for (int i = 0; i < R; ++i) t[i] = p2[min(i * kBS + (int)threadIdx.x, last)];
+        for (int i = 0; i < R; ++i) t[i] = make_double2(0.0, 0.0);
+        return;
+    }
+#pragma unroll
+    for (int i = 0; i < R; ++i) t[i] = p2[min(i * kBS + (int)threadIdx.x, npair - 1)];
 }
 
 // sum_partials_vec from a preloaded first round: thread t still adds its

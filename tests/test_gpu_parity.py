@@ -283,6 +283,37 @@ def test_one_by_one_and_single_subdomain():
     assert r.status == ss.SS_OK and r.iterations == 1 and _np(x)[0] == 0.75
 
 
+@pytest.mark.parametrize("case", ["one_by_one", "poisson9_user5", "random300_user3"])
+def test_tiny_systems_on_the_streaming_path(case):
+    # up to 512 local positions: one update workgroup, so the CG step
+    # finishes (r, r) from a single partial (no pair of partials to load);
+    # the random case has two (a single pair)
+    if case == "one_by_one":
+        A = CSR(1, np.array([0, 1], np.int32), np.array([0], np.int32), np.array([4.0]))
+        part, P = np.zeros(1, np.int32), 1
+    elif case == "poisson9_user5":
+        A = poisson2d(9)
+        part = (np.arange(A.n) * 5 // A.n).astype(np.int32)
+        P = 5
+    else:
+        A = random_spd_csr(300, 6.0, seed=11)
+        part = np.random.default_rng(11).integers(0, 3, A.n).astype(np.int32)
+        P = 3
+    p = ss.ss_partition(A, ss.SS_PART_USER, P, user_part=part)
+    s = _setup(A, p, small_solver=ss.SS_SMALL_OFF)
+    n_loc = s.info()["n_loc"]
+    assert s.path() == ss.SS_PATH_STREAM
+    assert (512 < n_loc <= 1024) if case == "random300_user3" else n_loc <= 512
+    b = uniform_rhs(A.n, 12) if A.n > 1 else np.array([3.0])
+    x = torch.zeros(A.n, dtype=torch.float64, device=DEV)
+    r = ss.ss_cg_solve(s, _t(b), x, tol=1e-12)
+    xo, ro = O.ss_cg(A, O.split(A.rowptr, A.colidx, part, P), b, tol=1e-12)
+    assert r.status == ss.SS_OK and abs(r.iterations - ro.iterations) <= 1
+    assert np.linalg.norm(_np(x) - xo) <= 1e-9 * np.linalg.norm(xo)
+    if case == "one_by_one":
+        assert r.iterations == 1 and _np(x)[0] == 0.75
+
+
 def test_empty_subdomains():
     A = poisson2d(9)
     part = np.zeros(A.n, np.int32)
