@@ -129,12 +129,21 @@ __device__ __forceinline__ void st_row(double *__restrict__ v, int row, const do
     }
 }
 
-// The pair statuses of system s into LDS; true if any pair is running.
+// The pair statuses of system s, in two parts, so that their loads go out
+// with a tile's other first loads and share their wait: pre_status issues
+// them (thread j < NR gets pair j's), publish_status shares them through LDS
+// and returns true if any pair is running.
 template <int NR>
-__device__ __forceinline__ bool load_sys_status(const BState &S, int s, int32_t *sh)
+__device__ __forceinline__ int32_t pre_status(const BState &S, int s)
+{
+    return threadIdx.x < NR ? dev::flag_load(&S.status[s * NR + threadIdx.x]) : BS_RUNNING;
+}
+
+template <int NR>
+__device__ __forceinline__ bool publish_status(int32_t f, int32_t *sh)
 {
     __syncthreads();  // sh may still be read from the previous tile
-    if (threadIdx.x < NR) sh[threadIdx.x] = dev::flag_load(&S.status[s * NR + threadIdx.x]);
+    if (threadIdx.x < NR) sh[threadIdx.x] = f;
     __syncthreads();
     bool any = false;
 #pragma unroll
@@ -147,11 +156,8 @@ __device__ __forceinline__ bool load_sys_status(const BState &S, int s, int32_t 
 // j = t % NR), then the lanes of equal residue, then the waves in order.
 // Every thread receives the NR sums.  ws: kWaves * NR.
 template <int NR>
-__device__ __forceinline__ void sys_sum(const double *__restrict__ part, int g0, int g1, double *ws, double (&out)[NR])
+__device__ __forceinline__ void sys_sum_tail(double v, double *ws, double (&out)[NR])
 {
-    const int lo = g0 * NR, hi = g1 * NR;
-    double v = 0.0;
-    for (int e = lo + (int)threadIdx.x; e < hi; e += kWG) v = v + part[e];
     v = dev::wave_sum_strided<NR>(v);
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     if (lane < NR) ws[w * NR + lane] = v;
@@ -164,6 +170,40 @@ __device__ __forceinline__ void sys_sum(const double *__restrict__ part, int g0,
         out[j] = t;
     }
     __syncthreads();
+}
+
+template <int NR>
+__device__ __forceinline__ void sys_sum(const double *__restrict__ part, int g0, int g1, double *ws, double (&out)[NR])
+{
+    const int lo = g0 * NR, hi = g1 * NR;
+    double v = 0.0;
+    for (int e = lo + (int)threadIdx.x; e < hi; e += kWG) v = v + part[e];
+    sys_sum_tail<NR>(v, ws, out);
+}
+
+// sys_sum with its first kPreSys elements per thread loaded ahead (with a
+// tile's first loads, at the last element past the end) and dropped where
+// they are added when past the end: the same order, so the same bits.
+constexpr int kPreSys = 2;  // one round for systems of up to 128 granules with 4 right-hand sides
+
+template <int NR>
+__device__ __forceinline__ void pre_sys(double (&t)[kPreSys], const double *__restrict__ part, int g0, int g1)
+{
+    const int lo = g0 * NR, hi = g1 * NR;
+#pragma unroll
+    for (int i = 0; i < kPreSys; ++i) t[i] = part[min(lo + (int)threadIdx.x + i * kWG, hi - 1)];
+}
+
+template <int NR>
+__device__ __forceinline__ void sys_sum_pre(const double (&t)[kPreSys], const double *__restrict__ part, int g0,
+                                            int g1, double *ws, double (&out)[NR])
+{
+    const int lo = g0 * NR, hi = g1 * NR;
+    double v = 0.0;
+#pragma unroll
+    for (int i = 0; i < kPreSys; ++i) v = v + (lo + (int)threadIdx.x + i * kWG < hi ? t[i] : 0.0);
+    for (int e = lo + (int)threadIdx.x + kPreSys * kWG; e < hi; e += kWG) v = v + part[e];
+    sys_sum_tail<NR>(v, ws, out);
 }
 
 // Granule partial of per-thread values of right-hand side t % NR (flat
@@ -280,30 +320,46 @@ __device__ __forceinline__ void spmv_tile(const BMat &M, const BTiles &T, const 
             xupd = xupd || al[j] != 0.0;
         }
         const int own0 = M.crow[T.gran_c0[T.tile_g0[t]]], own1 = M.crow[T.gran_c0[T.tile_g0[t + 1]]];
+        // the statuses, the system's (r, r) partials and the pairs' state go
+        // out together, behind one wait
+        const int32_t f = CG ? pre_status<NR>(S, s) : BS_RUNNING;
+        double tp[kPreSys];
+        double rrv[NR], stv[NR];
+        int32_t itv[NR];
+        int kmax = 0;
+        if (MODE == M_STEP) {
+            pre_sys<NR>(tp, part_b, T.sys_g0[s], T.sys_g0[s + 1]);
+            const double *rrc = rr_slot(S, slot);
+            const int32_t *itc = it_slot(S, slot);
+#pragma unroll
+            for (int j = 0; j < NR; ++j) {
+                rrv[j] = rrc[s * NR + j];
+                itv[j] = itc[s * NR + j];
+                stv[j] = S.stop[s * NR + j];
+            }
+            kmax = *S.kmax;
+        }
         if (CG) {
             // (the statuses may already show this step's stops, recorded by
             // the system's first tile: the x update is owed all the same)
-            if (!load_sys_status<NR>(S, s, sh_st)) {
+            if (!publish_status<NR>(f, sh_st)) {
                 if (MODE == M_STEP && xupd) x_update_rows<NR>(x, pin, own0, own1, al);
                 return;
             }
             bool any = false;
             if (MODE == M_STEP) {
                 double rrn[NR];
-                sys_sum<NR>(part_b, T.sys_g0[s], T.sys_g0[s + 1], ws, rrn);
+                sys_sum_pre<NR>(tp, part_b, T.sys_g0[s], T.sys_g0[s + 1], ws, rrn);
                 const bool lead = T.tile_g0[t] == T.sys_g0[s] && threadIdx.x == 0;
-                const int kmax = *S.kmax;
-                const double *rrc = rr_slot(S, slot);
-                const int32_t *itc = it_slot(S, slot);
 #pragma unroll
                 for (int j = 0; j < NR; ++j) {
                     if (sh_st[j] != BS_RUNNING) continue;
                     const int pr = s * NR + j;
-                    const int kn = itc[pr] + 1;
+                    const int kn = itv[j] + 1;
                     int32_t stop = BS_RUNNING;
                     if (!isfinite(rrn[j]))
                         stop = BS_BREAKDOWN;
-                    else if (sqrt(rrn[j]) <= S.stop[pr])
+                    else if (sqrt(rrn[j]) <= stv[j])
                         stop = BS_CONVERGED;
                     else if (kn >= kmax)
                         stop = BS_MAXIT;
@@ -320,7 +376,7 @@ __device__ __forceinline__ void spmv_tile(const BMat &M, const BTiles &T, const 
                         }
                     }
                     if (stop == BS_RUNNING) {
-                        beta[j] = rrn[j] / rrc[pr];
+                        beta[j] = rrn[j] / rrv[j];
                         any = true;
                     }
                 }
@@ -514,13 +570,11 @@ __device__ __forceinline__ void update_tile(const BMat &M, const BTiles &T, cons
     const int jt = threadIdx.x % NR;
     {
         const int s = T.tile_sys[t];
-        if (!load_sys_status<NR>(S, s, sh_st)) {
-            // nothing ran: the next step owes no x update for this system
-            if (T.tile_g0[t] == T.sys_g0[s] && threadIdx.x < NR) S.alpha[s * NR + threadIdx.x] = 0.0;
-            return;
-        }
+        // the statuses, the operands of the first granule, the system's
+        // (p, A p) partials and the pairs' (r, r) go out together, behind one
+        // wait
+        const int32_t f = pre_status<NR>(S, s);
         const int g0 = T.tile_g0[t], g1 = T.tile_g0[t + 1];
-        // operands of the first granule, loaded before alpha is known
         double rv[NI], qv[NI];
         int e0 = M.crow[T.gran_c0[g0]] * NR, e1 = M.crow[T.gran_c0[g0 + 1]] * NR;
         bool full = e1 - e0 == kGranRows * NR;
@@ -532,10 +586,20 @@ __device__ __forceinline__ void update_tile(const BMat &M, const BTiles &T, cons
                 qv[k] = q[e];
             }
         }
-        double pAp[NR];
-        sys_sum<NR>(part_a, T.sys_g0[s], T.sys_g0[s + 1], ws, pAp);
-        const bool lead = T.tile_g0[t] == T.sys_g0[s] && threadIdx.x == 0;
+        double tp[kPreSys];
+        pre_sys<NR>(tp, part_a, T.sys_g0[s], T.sys_g0[s + 1]);
+        double rrv[NR];
         const double *rrc = rr_slot(S, slot);
+#pragma unroll
+        for (int j = 0; j < NR; ++j) rrv[j] = rrc[s * NR + j];
+        if (!publish_status<NR>(f, sh_st)) {
+            // nothing ran: the next step owes no x update for this system
+            if (T.tile_g0[t] == T.sys_g0[s] && threadIdx.x < NR) S.alpha[s * NR + threadIdx.x] = 0.0;
+            return;
+        }
+        double pAp[NR];
+        sys_sum_pre<NR>(tp, part_a, T.sys_g0[s], T.sys_g0[s + 1], ws, pAp);
+        const bool lead = T.tile_g0[t] == T.sys_g0[s] && threadIdx.x == 0;
         bool any = false, run = false;
         double a = 0.0;  // alpha of this thread's right-hand side jt
 #pragma unroll
@@ -549,7 +613,7 @@ __device__ __forceinline__ void update_tile(const BMat &M, const BTiles &T, cons
                         atomicSub(S.nrun, 1);
                     }
                 } else {
-                    al = rrc[pr] / pAp[j];
+                    al = rrv[j] / pAp[j];
                     any = true;
                     if (j == jt) run = true;
                 }
