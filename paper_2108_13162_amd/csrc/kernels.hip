@@ -17,8 +17,9 @@
 // "Finishes" means: every workgroup adds up the previous kernel's
 // per-workgroup partials itself, in one fixed order, so all workgroups obtain
 // bitwise the same scalar without a grid-wide barrier or a separate launch;
-// those loads are issued after the workgroup's first streaming loads and
-// overlap them.  Workgroup 0 records the scalars.  All sums are fixed-order,
+// those loads go out with the workgroup's first operand loads, the status
+// word and the state's scalars, behind one wait.  Workgroup 0 records the
+// scalars.  All sums are fixed-order,
 // hence bitwise reproducible run to run.  Compiled with -ffp-contract=off:
 // products and sums are rounded separately, as the expressions are written.
 #include "kernels.h"
