@@ -320,9 +320,23 @@ def variant_batched(ss, torch, reps: int, tol: float, one_by_one: bool = True) -
     out["persistent_one_launch_ms"] = round(ms_p, 3)
     out["persistent_bitwise_equal"] = bool(torch.equal(x, x_tuned)) and \
         [r.iterations for r in res_p] == [r.iterations for r in res]
-    ss.ss_batch_set_tuning(bt, **chosen)
     print(f"# batched, one persistent launch: {ms_p:.3f} ms, bitwise equal {out['persistent_bitwise_equal']}",
           file=sys.stderr, flush=True)
+    # the tuned chunked launches captured as one graph of the whole solve
+    # (SS_BATCH_GRAPH): the first solve sets the graph's length, the second
+    # builds it, the timed ones are one graph launch each
+    ss.ss_batch_set_tuning(bt, chosen["tile_granules"], chosen["grid"], chosen["unroll"], chosen["check_every"],
+                           ss.SS_BATCH_GRAPH)
+    run()
+    run()
+    ms_g, (res_g, _) = _timed(torch, run, reps)
+    out["graph_one_launch_ms"] = round(ms_g, 3)
+    out["graph_launches_per_solve"] = bt.launches()
+    out["graph_bitwise_equal"] = bool(torch.equal(x, x_tuned)) and \
+        [r.iterations for r in res_g] == [r.iterations for r in res]
+    ss.ss_batch_set_tuning(bt, **chosen)
+    print(f"# batched, one graph launch: {ms_g:.3f} ms, launches {out['graph_launches_per_solve']}, "
+          f"bitwise equal {out['graph_bitwise_equal']}", file=sys.stderr, flush=True)
     if not one_by_one:
         return out
     # one by one: one solver per system (set up outside the timing), every pair solved separately

@@ -425,8 +425,17 @@ typedef struct ss_batch ss_batch;
  *   device-scope release and acquire (an L2 write-back and invalidation on
  *   this multi-XCD device), which makes it slower than the chunked
  *   schedule on large batches; the autotuner times both.  check_every is not
- *   used. */
-enum { SS_BATCH_CHUNKED = 0, SS_BATCH_PERSISTENT = 1 };
+ *   used.
+ * SS_BATCH_GRAPH: the chunked schedule's launches, with the whole solve
+ *   captured as one HIP graph of as many check_every-iteration chunks as the
+ *   previous solve of this batch took (each chunk followed by the rebuild of
+ *   the running list), launched once; the host polls only after it, and a
+ *   solve that needs more iterations continues chunk by chunk (the graph
+ *   grows to that length for the next solve).  The first solve of a batch
+ *   runs chunk by chunk.  Chunks past the end of the solve find no running
+ *   system and return at once.  Results are bitwise those of the chunked
+ *   schedule. */
+enum { SS_BATCH_CHUNKED = 0, SS_BATCH_PERSISTENT = 1, SS_BATCH_GRAPH = 2 };
 
 /* Launch shape of the batched kernels.  It changes timing only: results are
  * bitwise the same for every choice (all partial sums are taken over fixed
@@ -442,7 +451,8 @@ typedef struct {
                               many as are resident at once (persistent)     */
     int32_t unroll;        /* matrix entries loaded per lane before use: 4, 5, 8 */
     int32_t check_every;   /* CG iterations between host polls, even, 2..1024  */
-    int32_t schedule;      /* SS_BATCH_CHUNKED or SS_BATCH_PERSISTENT          */
+    int32_t schedule;      /* SS_BATCH_CHUNKED, SS_BATCH_PERSISTENT or
+                              SS_BATCH_GRAPH                                */
 } ss_batch_tuning;
 
 typedef struct {
@@ -499,6 +509,12 @@ int ss_batch_tune(ss_batch *bt, const double *b_dev, int32_t iters, int32_t forc
  * stored entries of the systems and the device storage incl. padding. */
 int ss_batch_info(const ss_batch *bt, int32_t *nsys, int32_t *nrhs, int64_t *nrows, int64_t *nnz,
                   int64_t *stored);
+
+/* Host-side launches of the last ss_batch_solve: *graphs = launches of the
+ * whole-solve graph (SS_BATCH_GRAPH), *chunks = launches of single-chunk
+ * graphs, *kernels = launches of the persistent kernel (SS_BATCH_PERSISTENT).
+ * Any pointer may be NULL.  Errors: SS_EINVAL (bt NULL). */
+int ss_batch_launches(const ss_batch *bt, int32_t *graphs, int32_t *chunks, int32_t *kernels);
 
 void ss_batch_destroy(ss_batch *bt);
 

@@ -31,7 +31,7 @@ SS_MAT_AUTO, SS_MAT_SELL, SS_MAT_CSR = 0, 1, 2
 SS_PRECOND_NONE, SS_PRECOND_JACOBI = 0, 1
 SS_SMALL_AUTO, SS_SMALL_OFF = 0, 1
 SS_PATH_STREAM, SS_PATH_SMALL = 0, 1
-SS_BATCH_CHUNKED, SS_BATCH_PERSISTENT = 0, 1
+SS_BATCH_CHUNKED, SS_BATCH_PERSISTENT, SS_BATCH_GRAPH = 0, 1, 2
 
 _ALLOC_T = C.CFUNCTYPE(C.c_void_p, C.c_void_p, C.c_size_t)
 _FREE_T = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
@@ -112,6 +112,7 @@ def lib() -> C.CDLL:
         "ss_batch_get_tuning": (C.c_int, [P, P]),
         "ss_batch_tune": (C.c_int, [P, P, i32, i32, P, P, i32, P]),
         "ss_batch_info": (C.c_int, [P, P, P, P, P, P]),
+        "ss_batch_launches": (C.c_int, [P, P, P, P]),
         "ss_batch_destroy": (None, [P]),
         "ss_strerror": (C.c_char_p, [C.c_int]),
         "ss_last_error": (C.c_char_p, []),
@@ -496,6 +497,12 @@ class Batch:
         v = [C.c_int32(), C.c_int32(), C.c_int64(), C.c_int64(), C.c_int64()]
         _check(lib().ss_batch_info(self.h, *[C.byref(t) for t in v]), "ss_batch_info")
         return dict(zip(["nsys", "nrhs", "nrows", "nnz", "stored"], [t.value for t in v]))
+
+    def launches(self) -> dict:
+        """Host-side launches of the last solve (ss_batch_launches)."""
+        v = [C.c_int32(), C.c_int32(), C.c_int32()]
+        _check(lib().ss_batch_launches(self.h, *[C.byref(t) for t in v]), "ss_batch_launches")
+        return dict(zip(["graphs", "chunks", "kernels"], [t.value for t in v]))
 
 
 def _tuning_dict(t: ss_batch_tuning) -> dict:

@@ -1081,7 +1081,8 @@ bool tuning_valid(const ss_batch_tuning &t)
     if (t.grid != 0 && (t.grid < 8 || t.grid > kGridLimit || t.grid % 8 != 0)) return false;
     if (t.unroll != 4 && t.unroll != 5 && t.unroll != 8) return false;
     if (t.check_every < 2 || t.check_every > 1024 || t.check_every % 2 != 0) return false;
-    if (t.schedule != SS_BATCH_CHUNKED && t.schedule != SS_BATCH_PERSISTENT) return false;
+    if (t.schedule != SS_BATCH_CHUNKED && t.schedule != SS_BATCH_PERSISTENT && t.schedule != SS_BATCH_GRAPH)
+        return false;
     return true;
 }
 
@@ -1126,6 +1127,13 @@ struct ss_batch {
     hipGraphExec_t exec = nullptr;
     int32_t graph_pairs = 0;
     bool graph_ok = false;
+    // SS_BATCH_GRAPH: the whole-solve graph of lchunks chunks of lpairs
+    // pairs, and the chunks the longest solve so far took
+    hipGraph_t lgraph = nullptr;
+    hipGraphExec_t lexec = nullptr;
+    int32_t lchunks = 0, lpairs = 0, hint = 0;
+    // host-side launches of the last solve (ss_batch_launches)
+    int32_t n_graph = 0, n_chunk = 0, n_kernel = 0;
 
     BMat bmat() const { return BMat{col, val, cptr, crow, clen, rlen}; }
     BTiles tiles(bool full) const
@@ -1158,6 +1166,16 @@ int upload(ss_batch *b, T **dst, const std::vector<T> &src)
     return SS_OK;
 }
 
+void destroy_long_graph(ss_batch *b)
+{
+    if (b->lexec) (void)hipGraphExecDestroy(b->lexec);
+    if (b->lgraph) (void)hipGraphDestroy(b->lgraph);
+    b->lexec = nullptr;
+    b->lgraph = nullptr;
+    b->lchunks = 0;
+}
+
+// Both graphs (they hold the kernels' launch shape and tiles).
 void destroy_graph(ss_batch *b)
 {
     if (b->exec) (void)hipGraphExecDestroy(b->exec);
@@ -1165,6 +1183,7 @@ void destroy_graph(ss_batch *b)
     b->exec = nullptr;
     b->graph = nullptr;
     b->graph_ok = false;
+    destroy_long_graph(b);
 }
 
 // Uploads the tiles of tuning t (the identity list is the full list).
@@ -1300,6 +1319,7 @@ int ensure_graph(ss_batch *b, int32_t pairs)
 {
     if (b->graph_ok && b->graph_pairs == pairs) return SS_OK;
     destroy_graph(b);
+    b->hint = 0;  // counted in chunks of another length
     SS_HIP(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
     for (int32_t k = 0; k < pairs; ++k) enqueue_pair(b, b->cap, k);
     compact(b, b->cap);
@@ -1309,6 +1329,27 @@ int ensure_graph(ss_batch *b, int32_t pairs)
     SS_HIP(hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0));
     b->graph_pairs = pairs;
     b->graph_ok = true;
+    return SS_OK;
+}
+
+// The whole-solve graph: `chunks` times a chunk of `pairs` pairs and the
+// rebuild of the running list, as the chunk graph runs them one launch at a
+// time.
+int ensure_long_graph(ss_batch *b, int32_t pairs, int32_t chunks)
+{
+    if (b->lexec && b->lchunks == chunks && b->lpairs == pairs) return SS_OK;
+    destroy_long_graph(b);
+    SS_HIP(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
+    for (int32_t c = 0; c < chunks; ++c) {
+        for (int32_t k = 0; k < pairs; ++k) enqueue_pair(b, b->cap, k);
+        compact(b, b->cap);
+    }
+    hipGraph_t g = nullptr;
+    SS_HIP(hipStreamEndCapture(b->cap, &g));
+    b->lgraph = g;
+    SS_HIP(hipGraphInstantiate(&b->lexec, g, nullptr, nullptr, 0));
+    b->lchunks = chunks;
+    b->lpairs = pairs;
     return SS_OK;
 }
 
@@ -1366,25 +1407,46 @@ int iterate_flow(ss_batch *b)
     return SS_OK;
 }
 
-// Iterates until no pair is running; chunks are queued one ahead of the poll.
-int iterate(ss_batch *b)
+// Iterates until no pair is running; chunks are queued one ahead of the
+// poll.  SS_BATCH_GRAPH: the first call of a solve launches the whole-solve
+// graph once (after a first solve has set its length) and goes on chunk by
+// chunk only if pairs still run after it.
+int iterate(ss_batch *b, bool first)
 {
-    if (b->tun.schedule == SS_BATCH_PERSISTENT) return iterate_flow(b);
+    if (b->tun.schedule == SS_BATCH_PERSISTENT) {
+        ++b->n_kernel;
+        return iterate_flow(b);
+    }
     const int32_t chunk = b->tun.check_every;
     int rc = ensure_graph(b, chunk);
     if (rc != SS_OK) return rc;
+    const bool whole = b->tun.schedule == SS_BATCH_GRAPH && first;
+    int32_t done = 0;  // chunks run
+    if (whole && b->hint > 0) {
+        if ((rc = ensure_long_graph(b, chunk, b->hint)) != SS_OK) return rc;
+        SS_HIP(hipGraphLaunch(b->lexec, b->stream));
+        ++b->n_graph;
+        SS_HIP(hipMemcpyAsync(&b->pinned[0], b->nrun, sizeof(int32_t), hipMemcpyDeviceToHost, b->stream));
+        SS_HIP(hipStreamSynchronize(b->stream));
+        if (b->pinned[0] == 0) return SS_OK;
+        done = b->hint;
+    }
     int slot = 0;
     SS_HIP(hipGraphLaunch(b->exec, b->stream));
+    ++b->n_chunk;
     SS_HIP(hipMemcpyAsync(&b->pinned[slot], b->nrun, sizeof(int32_t), hipMemcpyDeviceToHost, b->stream));
     SS_HIP(hipEventRecord(b->ev[slot], b->stream));
     for (;;) {
         const int nxt = slot ^ 1;
         SS_HIP(hipGraphLaunch(b->exec, b->stream));
+        ++b->n_chunk;
         SS_HIP(hipMemcpyAsync(&b->pinned[nxt], b->nrun, sizeof(int32_t), hipMemcpyDeviceToHost, b->stream));
         SS_HIP(hipEventRecord(b->ev[nxt], b->stream));
         SS_HIP(hipEventSynchronize(b->ev[slot]));
+        ++done;
         if (b->pinned[slot] == 0) {
             SS_HIP(hipEventSynchronize(b->ev[nxt]));
+            if (whole) b->hint = std::max(b->hint, done);
             return SS_OK;
         }
         slot = nxt;
@@ -1613,6 +1675,15 @@ int ss_batch_get_tuning(const ss_batch *b, ss_batch_tuning *t)
     return SS_OK;
 }
 
+int ss_batch_launches(const ss_batch *b, int32_t *graphs, int32_t *chunks, int32_t *kernels)
+{
+    if (!b) return fail(SS_EINVAL, "batch is NULL");
+    if (graphs) *graphs = b->n_graph;
+    if (chunks) *chunks = b->n_chunk;
+    if (kernels) *kernels = b->n_kernel;
+    return SS_OK;
+}
+
 int ss_batch_info(const ss_batch *b, int32_t *nsys, int32_t *nrhs, int64_t *nrows, int64_t *nnz, int64_t *stored)
 {
     if (!b) return fail(SS_EINVAL, "batch is NULL");
@@ -1636,10 +1707,11 @@ int ss_batch_solve(ss_batch *b, const double *b_dev, double *x_dev, double tol, 
         return fail(SS_EINVAL, "b and x overlap");
     SS_HIP(hipMemcpyAsync(b->x, x_dev, sizeof(double) * nv, hipMemcpyDeviceToDevice, b->stream));
     int32_t nrun = 0;
+    b->n_graph = b->n_chunk = b->n_kernel = 0;
     int rc = start_pairs(b, b_dev, tol, maxit, &nrun);
     if (rc != SS_OK) return rc;
-    while (nrun > 0) {
-        if ((rc = iterate(b)) != SS_OK) return rc;
+    for (bool first = true; nrun > 0; first = false) {
+        if ((rc = iterate(b, first)) != SS_OK) return rc;
         if ((rc = residual_phase(b, b_dev, tol, false, &nrun)) != SS_OK) return rc;
         if (nrun == 0) break;
         compact(b, b->stream);

@@ -101,7 +101,7 @@ def test_fixed_iterations_match_oracle(small, k):
             assert np.linalg.norm(X[s][:, j] - xo) <= 1e-12 * np.linalg.norm(xo), (s, j)
 
 
-CH, PE = ss.SS_BATCH_CHUNKED, ss.SS_BATCH_PERSISTENT
+CH, PE, GR = ss.SS_BATCH_CHUNKED, ss.SS_BATCH_PERSISTENT, ss.SS_BATCH_GRAPH
 
 
 def test_results_independent_of_launch_shape(small):
@@ -160,7 +160,7 @@ def test_fewer_rhs(nrhs):
             assert np.linalg.norm(X[s][:, j] - xr) <= 1e-9 * np.linalg.norm(xr)
 
 
-@pytest.mark.parametrize("schedule", [0, 1])  # SS_BATCH_CHUNKED, SS_BATCH_PERSISTENT
+@pytest.mark.parametrize("schedule", [0, 1, 2])  # SS_BATCH_CHUNKED, SS_BATCH_PERSISTENT, SS_BATCH_GRAPH
 def test_initial_guess_and_edge_cases(small, schedule):
     S, bt, B = small
     ss.ss_batch_set_tuning(bt, 2, 0, 8, 32, schedule)
@@ -190,10 +190,45 @@ def test_initial_guess_and_edge_cases(small, schedule):
     with pytest.raises(ss.SSError):
         ss.ss_batch_set_tuning(bt, 2, 12, 8, 32)
     with pytest.raises(ss.SSError):
-        ss.ss_batch_set_tuning(bt, 2, 0, 8, 32, 2)  # no such schedule
+        ss.ss_batch_set_tuning(bt, 2, 0, 8, 32, 3)  # no such schedule
     with pytest.raises(ss.SSError):
         ss.ss_batch_setup(S, nrhs=3)
     ss.ss_batch_set_tuning(bt, 2, 0, 8, 32, CH)
+
+
+@pytest.mark.parametrize("shape", [(2, 0, 8, 32), (1, 16, 5, 2), (0, 0, 4, 64)])
+def test_whole_solve_graph(shape):
+    # SS_BATCH_GRAPH: the first solve runs chunk by chunk and sets the graph's
+    # length; the next solves are one graph launch each; a solve that needs
+    # more chunks than the graph holds goes on chunk by chunk.  Every result
+    # bitwise that of the chunked schedule.
+    S = _systems()
+    B = _rhs(S, 4, 31)
+    bt_ch = ss.ss_batch_setup(S, nrhs=4)
+    ss.ss_batch_set_tuning(bt_ch, *shape, CH)
+    Xc, rc, _ = _solve(bt_ch, B)
+    Xc_short, rc_short, _ = _solve(bt_ch, B, maxit=40)
+    flat_c = np.concatenate([x.ravel() for x in Xc])
+    its_c = [r.iterations for r in rc]
+    bt = ss.ss_batch_setup(S, nrhs=4)
+    ss.ss_batch_set_tuning(bt, *shape, GR)
+    # a short first solve: the graph gets the chunks of 40 iterations
+    Xs, rs, summ = _solve(bt, B, maxit=40)
+    assert summ.status == ss.SS_NOT_CONVERGED
+    assert bt.launches()["graphs"] == 0 and bt.launches()["chunks"] > 0
+    assert np.array_equal(np.concatenate([x.ravel() for x in Xs]), np.concatenate([x.ravel() for x in Xc_short]))
+    assert [r.iterations for r in rs] == [r.iterations for r in rc_short]
+    # the full solve outgrows it: one graph launch, then chunk by chunk
+    X1, r1, summ1 = _solve(bt, B)
+    assert summ1.status == ss.SS_OK
+    n1 = bt.launches()
+    assert n1["graphs"] == 1 and n1["chunks"] > 0 and n1["kernels"] == 0
+    assert np.array_equal(np.concatenate([x.ravel() for x in X1]), flat_c) and [r.iterations for r in r1] == its_c
+    # now the graph holds the whole solve: one launch
+    X2, r2, summ2 = _solve(bt, B)
+    n2 = bt.launches()
+    assert summ2.status == ss.SS_OK and n2["graphs"] == 1 and n2["chunks"] == 0
+    assert np.array_equal(np.concatenate([x.ravel() for x in X2]), flat_c) and [r.iterations for r in r2] == its_c
 
 
 def test_matches_one_by_one_gpu_solves(small):
