@@ -318,7 +318,7 @@ __device__ __forceinline__ int chunk_len(const uint8_t *__restrict__ clen, int c
     return (int)((wd >> (8 * (c & 3))) & 0xffu);
 }
 
-// The loads of a one-batch chunk (see k_spmv_sell), addressed from the
+// The loads of a chunk's batch (see k_spmv_sell), addressed from the
 // chunk's wave-uniform bases: its values cv, its first row pos.
 //
 // The column words of slots j0..j0+U-1, the last slot repeated past L; decoded
