@@ -427,14 +427,19 @@ typedef struct ss_batch ss_batch;
  *   schedule on large batches; the autotuner times both.  check_every is not
  *   used.
  * SS_BATCH_GRAPH: the chunked schedule's launches, with the whole solve
- *   captured as one HIP graph of as many check_every-iteration chunks as the
- *   previous solve of this batch took (each chunk followed by the rebuild of
- *   the running list), launched once; the host polls only after it, and a
- *   solve that needs more iterations continues chunk by chunk (the graph
- *   grows to that length for the next solve).  The first solve of a batch
- *   runs chunk by chunk.  Chunks past the end of the solve find no running
- *   system and return at once.  Results are bitwise those of the chunked
- *   schedule. */
+ *   captured as one HIP graph and launched once: as many check_every-
+ *   iteration chunks as the longest solve of this batch so far took before
+ *   its residual check (each chunk followed by the rebuild of the running
+ *   list), the residual check and the restart it may start, as many chunks
+ *   as that solve's restart took, and a last check.  Each check runs only
+ *   once no pair runs any more (else its kernels return at once), and chunks
+ *   past the end find no running system and return at once, so the results
+ *   are bitwise those of the chunked schedule.  The host polls only after
+ *   the graph.  The first solve of a batch runs chunk by chunk and sets the
+ *   lengths; a solve that outruns the graph goes on chunk by chunk, and the
+ *   next one sets the lengths again.  The graph's checks read the solve's
+ *   right-hand sides from a copy that every solve makes (one more vector of
+ *   the batch's size on the device). */
 enum { SS_BATCH_CHUNKED = 0, SS_BATCH_PERSISTENT = 1, SS_BATCH_GRAPH = 2 };
 
 /* Launch shape of the batched kernels.  It changes timing only: results are

@@ -546,8 +546,9 @@ __global__ __launch_bounds__(kWG) void k_bspmv(BMat M, BTiles T, BState S, const
                                                const double *__restrict__ r, double *__restrict__ pout,
                                                double *__restrict__ q, double *__restrict__ x,
                                                double *__restrict__ part_a, const double *__restrict__ part_b,
-                                               int slot)
+                                               int slot, const int32_t *__restrict__ gate)
 {
+    if (gate && *gate == 0) return;
     __shared__ double ws[kWaves * NR];
     __shared__ int32_t sh_st[NR];
     __shared__ __align__(16) double ring[ring_rows<NR>() * NR];
@@ -881,8 +882,10 @@ __global__ __launch_bounds__(64) void k_bflow_reset(int32_t *ctl)
 template <int NR, bool FIRST>
 __global__ __launch_bounds__(kWG) void k_bresid(BMat M, BTiles T, const double *__restrict__ b,
                                                 const double *__restrict__ q, double *__restrict__ r,
-                                                double *__restrict__ part_r, double *__restrict__ part_bb)
+                                                double *__restrict__ part_r, double *__restrict__ part_bb,
+                                                const int32_t *__restrict__ gate)
 {
+    if (gate && *gate == 0) return;
     __shared__ double ws[kWaves * NR];
     const Share sh = list_share(*T.nlist);
     for (int i = sh.i; i < sh.end; i += sh.step) {
@@ -910,8 +913,10 @@ __global__ __launch_bounds__(kWG) void k_bresid(BMat M, BTiles T, const double *
 // from it when still above the tolerance and below the iteration limit).
 template <int NR>
 __global__ __launch_bounds__(kWG) void k_bfinish(BTiles T, BState S, const double *__restrict__ part_r,
-                                                 const double *__restrict__ part_bb, double tol, int first)
+                                                 const double *__restrict__ part_bb, double tol, int first,
+                                                 const int32_t *__restrict__ gate)
 {
+    if (gate && *gate == 0) return;
     __shared__ double ws[kWaves * NR];
     const int s = blockIdx.x;
     const int g0 = T.sys_g0[s], g1 = T.sys_g0[s + 1];
@@ -1011,9 +1016,18 @@ __global__ __launch_bounds__(kWG) void k_binit(BState S, int32_t npairs, int32_t
     dev::flag_store(&S.status[i], BS_RUNNING);
 }
 
-__global__ __launch_bounds__(kWG) void k_bzero_count(int32_t *nrun)
+__global__ __launch_bounds__(kWG) void k_bzero_count(int32_t *nrun, const int32_t *__restrict__ gate)
 {
+    if (gate && *gate == 0) return;
     if (threadIdx.x == 0 && blockIdx.x == 0) *nrun = 0;
+}
+
+// The gate of a residual check inside the whole-solve graph: 1 when no pair
+// runs any more (the check is due), else 0 (the kernels it gates return at
+// once and the pairs go on iterating).
+__global__ void k_bgate(const int32_t *__restrict__ nrun, int32_t *__restrict__ gate)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) *gate = *nrun == 0 ? 1 : 0;
 }
 
 // x_out = x, zero for pairs with b = 0 (every tile of the full list).
@@ -1127,11 +1141,17 @@ struct ss_batch {
     hipGraphExec_t exec = nullptr;
     int32_t graph_pairs = 0;
     bool graph_ok = false;
-    // SS_BATCH_GRAPH: the whole-solve graph of lchunks chunks of lpairs
-    // pairs, and the chunks the longest solve so far took
+    // SS_BATCH_GRAPH: the whole-solve graph (lchunks chunks of lpairs
+    // pairs, a residual check, lchunks2 chunks, a residual check), the
+    // chunks the longest solve so far took before its first residual check
+    // and after it, the gate of the checks and the right-hand sides the
+    // graph's checks read (copied in by every solve)
     hipGraph_t lgraph = nullptr;
     hipGraphExec_t lexec = nullptr;
-    int32_t lchunks = 0, lpairs = 0, hint = 0;
+    int32_t lchunks = 0, lchunks2 = 0, lpairs = 0, hint = 0, hint2 = 0;
+    int32_t *gate = nullptr;
+    double *bcopy = nullptr;
+    const int32_t *cur_gate = nullptr;  // gate passed to the kernels being enqueued
     // host-side launches of the last solve (ss_batch_launches)
     int32_t n_graph = 0, n_chunk = 0, n_kernel = 0;
 
@@ -1215,10 +1235,12 @@ void spmv_t(ss_batch *b, hipStream_t st, bool full, const double *pin, const dou
 {
     if (b->max_halo <= staged_halo(NR))
         hipLaunchKernelGGL((k_bspmv<NR, U, MODE, true>), dim3(b->grid()), dim3(kWG), 0, st, b->bmat(),
-                           b->tiles(full), b->state(), pin, r, pout, q, b->x, b->part_a, b->part_b, slot);
+                           b->tiles(full), b->state(), pin, r, pout, q, b->x, b->part_a, b->part_b, slot,
+                           b->cur_gate);
     else
         hipLaunchKernelGGL((k_bspmv<NR, U, MODE, false>), dim3(b->grid()), dim3(kWG), 0, st, b->bmat(),
-                           b->tiles(full), b->state(), pin, r, pout, q, b->x, b->part_a, b->part_b, slot);
+                           b->tiles(full), b->state(), pin, r, pout, q, b->x, b->part_a, b->part_b, slot,
+                           b->cur_gate);
 }
 
 template <int NR, int MODE>
@@ -1270,33 +1292,40 @@ void compact(ss_batch *b, hipStream_t st)
 }
 
 template <int NR>
-void residual_t(ss_batch *b, const double *b_dev, bool first)
+void residual_t(ss_batch *b, hipStream_t st, const double *b_dev, bool first)
 {
     if (first)
-        hipLaunchKernelGGL((k_bresid<NR, true>), dim3(b->grid()), dim3(kWG), 0, b->stream, b->bmat(), b->tiles(true),
-                           b_dev, b->q, b->r, b->part_b, b->part_c);
+        hipLaunchKernelGGL((k_bresid<NR, true>), dim3(b->grid()), dim3(kWG), 0, st, b->bmat(), b->tiles(true),
+                           b_dev, b->q, b->r, b->part_b, b->part_c, b->cur_gate);
     else
-        hipLaunchKernelGGL((k_bresid<NR, false>), dim3(b->grid()), dim3(kWG), 0, b->stream, b->bmat(),
-                           b->tiles(true), b_dev, b->q, b->r, b->part_b, b->part_c);
+        hipLaunchKernelGGL((k_bresid<NR, false>), dim3(b->grid()), dim3(kWG), 0, st, b->bmat(), b->tiles(true),
+                           b_dev, b->q, b->r, b->part_b, b->part_c, b->cur_gate);
 }
 
 template <int NR>
-void finish_t(ss_batch *b, double tol, bool first)
+void finish_t(ss_batch *b, hipStream_t st, double tol, bool first)
 {
-    hipLaunchKernelGGL(k_bfinish<NR>, dim3(b->nsys), dim3(kWG), 0, b->stream, b->tiles(true), b->state(), b->part_b,
-                       b->part_c, tol, first ? 1 : 0);
+    hipLaunchKernelGGL(k_bfinish<NR>, dim3(b->nsys), dim3(kWG), 0, st, b->tiles(true), b->state(), b->part_b,
+                       b->part_c, tol, first ? 1 : 0, b->cur_gate);
 }
 
 // r = b - A x for every pair, stopping tests; returns the running count.
+// The residual check: q = A x, r = b - q, (r, r) [(b, b)], the stopping
+// test of every pair, the running count; with b->cur_gate set, gated.
+void enqueue_residual(ss_batch *b, hipStream_t st, const double *b_dev, double tol, bool first)
+{
+    spmv<M_PLAIN>(b, st, true, b->x, nullptr, nullptr, b->q, 0);
+    hipLaunchKernelGGL(k_bzero_count, dim3(1), dim3(kWG), 0, st, b->nrun, b->cur_gate);
+    switch (b->nrhs) {
+    case 1: residual_t<1>(b, st, b_dev, first); finish_t<1>(b, st, tol, first); break;
+    case 2: residual_t<2>(b, st, b_dev, first); finish_t<2>(b, st, tol, first); break;
+    default: residual_t<4>(b, st, b_dev, first); finish_t<4>(b, st, tol, first); break;
+    }
+}
+
 int residual_phase(ss_batch *b, const double *b_dev, double tol, bool first, int32_t *nrun)
 {
-    spmv<M_PLAIN>(b, b->stream, true, b->x, nullptr, nullptr, b->q, 0);
-    hipLaunchKernelGGL(k_bzero_count, dim3(1), dim3(kWG), 0, b->stream, b->nrun);
-    switch (b->nrhs) {
-    case 1: residual_t<1>(b, b_dev, first); finish_t<1>(b, tol, first); break;
-    case 2: residual_t<2>(b, b_dev, first); finish_t<2>(b, tol, first); break;
-    default: residual_t<4>(b, b_dev, first); finish_t<4>(b, tol, first); break;
-    }
+    enqueue_residual(b, b->stream, b_dev, tol, first);
     SS_HIP(hipGetLastError());
     SS_HIP(hipMemcpyAsync(&b->pinned[0], b->nrun, sizeof(int32_t), hipMemcpyDeviceToHost, b->stream));
     SS_HIP(hipStreamSynchronize(b->stream));
@@ -1319,7 +1348,7 @@ int ensure_graph(ss_batch *b, int32_t pairs)
 {
     if (b->graph_ok && b->graph_pairs == pairs) return SS_OK;
     destroy_graph(b);
-    b->hint = 0;  // counted in chunks of another length
+    b->hint = b->hint2 = 0;  // counted in chunks of another length
     SS_HIP(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
     for (int32_t k = 0; k < pairs; ++k) enqueue_pair(b, b->cap, k);
     compact(b, b->cap);
@@ -1332,23 +1361,48 @@ int ensure_graph(ss_batch *b, int32_t pairs)
     return SS_OK;
 }
 
+// The residual check of the whole-solve graph, and the restart it may
+// start, as the host runs them between chunk loops: gated on no pair running
+// any more (else every kernel of it returns at once and the chunks that
+// follow go on with the running pairs), reading the solve's right-hand
+// sides from the copy every solve makes.
+void enqueue_check(ss_batch *b, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_bgate, dim3(1), dim3(64), 0, st, b->nrun, b->gate);
+    b->cur_gate = b->gate;
+    enqueue_residual(b, st, b->bcopy, 0.0, false);
+    b->cur_gate = nullptr;
+    compact(b, st);
+    b->cur_gate = b->gate;
+    spmv<M_FIRST>(b, st, false, b->r, b->r, b->p1, b->q, 0);
+    b->cur_gate = nullptr;
+}
+
 // The whole-solve graph: `chunks` times a chunk of `pairs` pairs and the
 // rebuild of the running list, as the chunk graph runs them one launch at a
-// time.
-int ensure_long_graph(ss_batch *b, int32_t pairs, int32_t chunks)
+// time, the residual check, then `chunks2` more chunks and a check when the
+// longest solve so far restarted pairs.
+int ensure_long_graph(ss_batch *b, int32_t pairs, int32_t chunks, int32_t chunks2)
 {
-    if (b->lexec && b->lchunks == chunks && b->lpairs == pairs) return SS_OK;
+    if (b->lexec && b->lchunks == chunks && b->lchunks2 == chunks2 && b->lpairs == pairs) return SS_OK;
     destroy_long_graph(b);
+    int rc;
+    if (!b->gate && (rc = alloc_dev(b, &b->gate, 1)) != SS_OK) return rc;
+    if (!b->bcopy && (rc = alloc_dev(b, &b->bcopy, (size_t)b->nrows * b->nrhs)) != SS_OK) return rc;
     SS_HIP(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
-    for (int32_t c = 0; c < chunks; ++c) {
-        for (int32_t k = 0; k < pairs; ++k) enqueue_pair(b, b->cap, k);
-        compact(b, b->cap);
+    for (int32_t seg = 0; seg < (chunks2 > 0 ? 2 : 1); ++seg) {
+        for (int32_t c = 0; c < (seg == 0 ? chunks : chunks2); ++c) {
+            for (int32_t k = 0; k < pairs; ++k) enqueue_pair(b, b->cap, k);
+            compact(b, b->cap);
+        }
+        enqueue_check(b, b->cap);
     }
     hipGraph_t g = nullptr;
     SS_HIP(hipStreamEndCapture(b->cap, &g));
     b->lgraph = g;
     SS_HIP(hipGraphInstantiate(&b->lexec, g, nullptr, nullptr, 0));
     b->lchunks = chunks;
+    b->lchunks2 = chunks2;
     b->lpairs = pairs;
     return SS_OK;
 }
@@ -1408,11 +1462,10 @@ int iterate_flow(ss_batch *b)
 }
 
 // Iterates until no pair is running; chunks are queued one ahead of the
-// poll.  SS_BATCH_GRAPH: the first call of a solve launches the whole-solve
-// graph once (after a first solve has set its length) and goes on chunk by
-// chunk only if pairs still run after it.
-int iterate(ss_batch *b, bool first)
+// poll.  *chunks: the chunks it took.
+int iterate(ss_batch *b, int32_t *chunks)
 {
+    *chunks = 0;
     if (b->tun.schedule == SS_BATCH_PERSISTENT) {
         ++b->n_kernel;
         return iterate_flow(b);
@@ -1420,17 +1473,7 @@ int iterate(ss_batch *b, bool first)
     const int32_t chunk = b->tun.check_every;
     int rc = ensure_graph(b, chunk);
     if (rc != SS_OK) return rc;
-    const bool whole = b->tun.schedule == SS_BATCH_GRAPH && first;
     int32_t done = 0;  // chunks run
-    if (whole && b->hint > 0) {
-        if ((rc = ensure_long_graph(b, chunk, b->hint)) != SS_OK) return rc;
-        SS_HIP(hipGraphLaunch(b->lexec, b->stream));
-        ++b->n_graph;
-        SS_HIP(hipMemcpyAsync(&b->pinned[0], b->nrun, sizeof(int32_t), hipMemcpyDeviceToHost, b->stream));
-        SS_HIP(hipStreamSynchronize(b->stream));
-        if (b->pinned[0] == 0) return SS_OK;
-        done = b->hint;
-    }
     int slot = 0;
     SS_HIP(hipGraphLaunch(b->exec, b->stream));
     ++b->n_chunk;
@@ -1446,7 +1489,7 @@ int iterate(ss_batch *b, bool first)
         ++done;
         if (b->pinned[slot] == 0) {
             SS_HIP(hipEventSynchronize(b->ev[nxt]));
-            if (whole) b->hint = std::max(b->hint, done);
+            *chunks = done;
             return SS_OK;
         }
         slot = nxt;
@@ -1710,8 +1753,29 @@ int ss_batch_solve(ss_batch *b, const double *b_dev, double *x_dev, double tol, 
     b->n_graph = b->n_chunk = b->n_kernel = 0;
     int rc = start_pairs(b, b_dev, tol, maxit, &nrun);
     if (rc != SS_OK) return rc;
-    for (bool first = true; nrun > 0; first = false) {
-        if ((rc = iterate(b, first)) != SS_OK) return rc;
+    // SS_BATCH_GRAPH: once a solve has set the lengths, the whole solve (its
+    // chunks, residual check, restart chunks, final check) is one graph
+    // launch; a solve that outruns it goes on as below, and the next one
+    // learns the lengths again
+    const bool graph = b->tun.schedule == SS_BATCH_GRAPH;
+    bool learn = graph;
+    if (graph && (rc = ensure_graph(b, b->tun.check_every)) != SS_OK) return rc;
+    if (graph && b->hint > 0 && nrun > 0) {
+        if ((rc = ensure_long_graph(b, b->tun.check_every, b->hint, b->hint2)) != SS_OK) return rc;
+        SS_HIP(hipMemcpyAsync(b->bcopy, b_dev, sizeof(double) * nv, hipMemcpyDeviceToDevice, b->stream));
+        SS_HIP(hipGraphLaunch(b->lexec, b->stream));
+        ++b->n_graph;
+        SS_HIP(hipMemcpyAsync(&b->pinned[0], b->nrun, sizeof(int32_t), hipMemcpyDeviceToHost, b->stream));
+        SS_HIP(hipStreamSynchronize(b->stream));
+        nrun = b->pinned[0];
+        learn = false;
+        if (nrun > 0) b->hint = b->hint2 = 0;
+    }
+    for (int round = 0; nrun > 0; ++round) {
+        int32_t chunks = 0;
+        if ((rc = iterate(b, &chunks)) != SS_OK) return rc;
+        if (learn && round == 0) b->hint = std::max(b->hint, chunks);
+        if (learn && round == 1) b->hint2 = std::max(b->hint2, chunks);
         if ((rc = residual_phase(b, b_dev, tol, false, &nrun)) != SS_OK) return rc;
         if (nrun == 0) break;
         compact(b, b->stream);

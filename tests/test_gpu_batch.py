@@ -224,11 +224,22 @@ def test_whole_solve_graph(shape):
     n1 = bt.launches()
     assert n1["graphs"] == 1 and n1["chunks"] > 0 and n1["kernels"] == 0
     assert np.array_equal(np.concatenate([x.ravel() for x in X1]), flat_c) and [r.iterations for r in r1] == its_c
-    # now the graph holds the whole solve: one launch
+    # the next solve sets the lengths again, chunk by chunk
     X2, r2, summ2 = _solve(bt, B)
-    n2 = bt.launches()
-    assert summ2.status == ss.SS_OK and n2["graphs"] == 1 and n2["chunks"] == 0
+    assert summ2.status == ss.SS_OK and bt.launches()["graphs"] == 0
     assert np.array_equal(np.concatenate([x.ravel() for x in X2]), flat_c) and [r.iterations for r in r2] == its_c
+    # now the graph holds the whole solve, residual checks included: one launch
+    for _ in range(2):
+        X3, r3, summ3 = _solve(bt, B)
+        n3 = bt.launches()
+        assert summ3.status == ss.SS_OK and n3 == {"graphs": 1, "chunks": 0, "kernels": 0}
+        assert np.array_equal(np.concatenate([x.ravel() for x in X3]), flat_c) and [r.iterations for r in r3] == its_c
+    # other right-hand sides through the same graph (the checks read a copy)
+    B2 = _rhs(S, 4, 32)
+    Xc2, rc2, _ = _solve(bt_ch, B2)
+    X4, r4, _ = _solve(bt, B2)
+    assert np.array_equal(np.concatenate([x.ravel() for x in X4]), np.concatenate([x.ravel() for x in Xc2]))
+    assert [r.iterations for r in r4] == [r.iterations for r in rc2]
 
 
 def test_matches_one_by_one_gpu_solves(small):
