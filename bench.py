@@ -259,7 +259,7 @@ def variant_mixed(ss, torch, reps: int, tol: float) -> dict:
     return out
 
 
-def variant_batched(ss, torch, reps: int, tol: float, one_by_one: bool = True) -> dict:
+def variant_batched(ss, torch, reps: int, tol: float, one_by_one: bool = True, whole_graph: bool = True) -> dict:
     import numpy as np
 
     from workloads import config
@@ -323,30 +323,31 @@ def variant_batched(ss, torch, reps: int, tol: float, one_by_one: bool = True) -
         [r.iterations for r in res_p] == [r.iterations for r in res]
     print(f"# batched, one persistent launch: {ms_p:.3f} ms, bitwise equal {out['persistent_bitwise_equal']}",
           file=sys.stderr, flush=True)
-    # the tuned chunked launches captured as one graph of the whole solve
-    # (SS_BATCH_GRAPH): the first solve sets the graph's length, the second
-    # builds it, the timed ones are one graph launch each
-    ss.ss_batch_set_tuning(bt, chosen["tile_granules"], chosen["grid"], chosen["unroll"], chosen["check_every"],
-                           ss.SS_BATCH_GRAPH)
-    run()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    run()
-    torch.cuda.synchronize()
-    out["graph_build_and_solve_ms"] = round((time.perf_counter() - t0) * 1e3, 3)
-    t0 = time.perf_counter()
-    for _ in range(max(reps, 1)):
-        res_g, _ = run()
-    torch.cuda.synchronize()
-    ms_g = (time.perf_counter() - t0) * 1e3 / max(reps, 1)
-    out["graph_one_launch_ms"] = round(ms_g, 3)
-    out["graph_launches_per_solve"] = bt.launches()
-    out["graph_bitwise_equal"] = bool(torch.equal(x, x_tuned)) and \
-        [r.iterations for r in res_g] == [r.iterations for r in res]
+    if whole_graph:
+        # the tuned chunked launches captured as one graph of the whole solve
+        # (SS_BATCH_GRAPH): the first solve sets the graph's length, the second
+        # builds it, the timed ones are one graph launch each
+        ss.ss_batch_set_tuning(bt, chosen["tile_granules"], chosen["grid"], chosen["unroll"], chosen["check_every"],
+                               ss.SS_BATCH_GRAPH)
+        run()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        run()
+        torch.cuda.synchronize()
+        out["graph_build_and_solve_ms"] = round((time.perf_counter() - t0) * 1e3, 3)
+        t0 = time.perf_counter()
+        for _ in range(max(reps, 1)):
+            res_g, _ = run()
+        torch.cuda.synchronize()
+        ms_g = (time.perf_counter() - t0) * 1e3 / max(reps, 1)
+        out["graph_one_launch_ms"] = round(ms_g, 3)
+        out["graph_launches_per_solve"] = bt.launches()
+        out["graph_bitwise_equal"] = bool(torch.equal(x, x_tuned)) and \
+            [r.iterations for r in res_g] == [r.iterations for r in res]
+        print(f"# batched, one graph launch: {ms_g:.3f} ms (first, with the capture: "
+              f"{out['graph_build_and_solve_ms']:.3f} ms), launches {out['graph_launches_per_solve']}, "
+              f"bitwise equal {out['graph_bitwise_equal']}", file=sys.stderr, flush=True)
     ss.ss_batch_set_tuning(bt, **chosen)
-    print(f"# batched, one graph launch: {ms_g:.3f} ms (first, with the capture: "
-          f"{out['graph_build_and_solve_ms']:.3f} ms), launches {out['graph_launches_per_solve']}, "
-          f"bitwise equal {out['graph_bitwise_equal']}", file=sys.stderr, flush=True)
     if not one_by_one:
         return out
     # one by one: one solver per system (set up outside the timing), every pair solved separately
@@ -740,6 +741,9 @@ def main() -> int:
                     help="profiling aid: skip the main measurement, print only the variants")
     ap.add_argument("--no-one-by-one", action="store_true",
                     help="profiling aid: skip the one-by-one half of the batched comparison")
+    ap.add_argument("--no-whole-solve-graph", action="store_true",
+                    help="profiling aid: skip the whole-solve graph half of the batched comparison "
+                         "(its kernels are the chunked launches')")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run plain 1 GiB device copies first (reference for PMC byte counters)")
     args = ap.parse_args()
@@ -768,7 +772,8 @@ def main() -> int:
     if chosen:
         out["variants"] = {}
         for v in chosen:
-            kw = {"one_by_one": not args.no_one_by_one} if v == "batched" else {}
+            kw = {"one_by_one": not args.no_one_by_one,
+                  "whole_graph": not args.no_whole_solve_graph} if v == "batched" else {}
             out["variants"][v] = funcs[v](ss, torch, args.variant_steps, args.tol, **kw)
             torch.cuda.empty_cache()
     if _ORACLE_AT_TOL:
