@@ -19,7 +19,12 @@ build); the GPU solves go through the C-ABI.  Checked per system:
     any x with residual 1e-10 is bounded only by cond(A) 1e-10);
   - with the residual driven to 1e-13, the error <= 1e-9.
 The mixed-precision modes on the 96^3 Q1 system are held to max(1e-9, 10x
-the oracle FP64 CG's error), and their FP32 product is compared bit for bit.
+the oracle FP64 CG's error), their FP32 product is compared bit for bit, and
+their counts (inner iterations within 3, replacements / outer corrections
+within 1) with the oracle's own mixed solves (tests/golden/
+cfg3_mixed_counts.json, written by make_cfg3_mixed.py, which calls only
+oracle/): the FP32 roundings are the same, the FP64 dots are summed in another
+order.
 These need a few minutes of CPU time for the oracle side."""
 import json
 import os
@@ -39,6 +44,8 @@ DEV = "cuda:0"
 
 with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "fullsize_spread.json")) as _f:
     SPREAD = json.load(_f)
+with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "cfg3_mixed_counts.json")) as _f:
+    MIXED = json.load(_f)
 
 
 def _its_range(idx):
@@ -175,3 +182,7 @@ def test_cfg3_mixed_accuracy(cfg3, prec):
           f"error {err:.2e} (oracle FP64 CG {cfg3.err10:.2e})")
     assert r.status == ss.SS_OK and true <= 1e-10, (r, true)
     assert err <= max(1e-9, 10 * cfg3.err10), (err, cfg3.err10)
+    ref = MIXED["ru"] if prec == "SS_FP32_RU" else MIXED["ir"]
+    outer = ref["replacements"] if prec == "SS_FP32_RU" else ref["outer"]
+    assert abs(r.iterations - ref["iterations"]) <= 3, (r.iterations, ref)
+    assert abs(r.outer_iterations - outer) <= 1, (r.outer_iterations, ref)
