@@ -242,6 +242,39 @@ def test_whole_solve_graph(shape):
     assert [r.iterations for r in r4] == [r.iterations for r in rc2]
 
 
+@pytest.mark.parametrize("nrhs", [1, 2])
+def test_whole_solve_graph_fewer_rhs_with_restarts(nrhs):
+    # SS_BATCH_GRAPH with 1 and 2 right-hand sides, to a tolerance near the
+    # attainable floor, so that residual checks restart pairs and the graph's
+    # restart segment runs: bitwise the chunked schedule's results, iteration
+    # and restart counts
+    S = _systems()
+    B = _rhs(S, nrhs, 41)
+    tol = 1e-13
+    bt_ch = ss.ss_batch_setup(S, nrhs=nrhs)
+    ss.ss_batch_set_tuning(bt_ch, 2, 0, 8, 32, CH)
+    Xc, rc, sc = _solve(bt_ch, B, tol=tol)
+    flat_c = np.concatenate([x.ravel() for x in Xc])
+    key_c = [(r.status, r.iterations, r.restarts) for r in rc]
+    assert any(r.restarts > 0 for r in rc), key_c
+    # the graph holds two rounds of chunks (before and after one restart);
+    # a solve whose pairs restart again goes on chunk by chunk after it
+    fits = max(r.restarts for r in rc) <= 1
+    print(f"nrhs {nrhs}: {sum(r.restarts > 0 for r in rc)} pairs restarted, at most {max(r.restarts for r in rc)} times")
+    bt = ss.ss_batch_setup(S, nrhs=nrhs)
+    ss.ss_batch_set_tuning(bt, 2, 0, 8, 32, GR)
+    for k in range(3):
+        X, r, summ = _solve(bt, B, tol=tol)
+        n = bt.launches()
+        if k == 0:
+            assert n["graphs"] == 0  # the first solve sets the lengths
+        elif fits:
+            assert n == {"graphs": 1, "chunks": 0, "kernels": 0}, n
+        assert summ.status == sc.status
+        assert np.array_equal(np.concatenate([x.ravel() for x in X]), flat_c)
+        assert [(q.status, q.iterations, q.restarts) for q in r] == key_c
+
+
 def test_matches_one_by_one_gpu_solves(small):
     S, bt, B = small
     X, res, _ = _solve(bt, B)
