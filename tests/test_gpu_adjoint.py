@@ -50,6 +50,25 @@ def test_gradients_match_fp64_reference_small():
     assert np.linalg.norm(dvals - ref) <= 1e-10 * np.linalg.norm(ref)
 
 
+@pytest.mark.parametrize("opts", [{"precond": ss.SS_PRECOND_JACOBI}, {"small_solver": ss.SS_SMALL_OFF}])
+def test_gradients_through_other_solve_paths(opts):
+    # the same adjoint on a Jacobi-preconditioned solver and on the streaming
+    # kernels (the 8^3 system otherwise takes the one-launch solve): both
+    # solves converge to the same x and lambda, so the same gradients
+    w = config(5, size=8)
+    A = w.A
+    solver = ss.ss_cg_setup(A, ss.partition_workload(w), ss.default_opts(**opts))
+    b, xt = w.b, w.extra["x_target"]
+    _, dvals, db, x = _loss_and_grads(A, solver, b, xt, tol=1e-14)
+    D = A.to_dense()
+    xr, _ = O.chol_solve(D, b)
+    lam, _ = O.chol_solve(D, xr - xt)
+    ref = O.grad_vals(A, lam, xr)
+    assert np.linalg.norm(x - xr) <= 1e-12 * np.linalg.norm(xr)
+    assert np.linalg.norm(db - lam) <= 1e-10 * np.linalg.norm(lam)
+    assert np.linalg.norm(dvals - ref) <= 1e-10 * np.linalg.norm(ref)
+
+
 def test_gradients_full_size_central_fd():
     # 64^3 smoothed-GRF diffusion, 8 boxes: loss 0.5 ||x - x_t||^2
     w = config(5)
