@@ -35,6 +35,10 @@ def test_c_client_solves(tmp_path):
     print(r.stdout, r.stderr)
     assert r.returncode == 0, (r.stdout, r.stderr)
     assert "iterations=" in r.stdout
+    # the product, the allocation-free solve and a batch solved as one graph
+    # launch, from C
+    assert "noalloc: iterations=" in r.stdout and "identical=1" in r.stdout
+    assert "batch: graphs=1 chunks=0 kernels=0" in r.stdout
     # a caller's allocator returning blocks off a 256-byte boundary is refused
     # cleanly, every block handed back
     assert "misaligned allocator: out of memory, blocks left 0" in r.stdout
