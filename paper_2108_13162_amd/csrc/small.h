@@ -13,9 +13,10 @@ namespace ss {
 // ---- one-launch solve of a small system (small.hip) --------------------------
 // One workgroup of kSmallThreads threads runs the whole CG (M = I, FP64):
 // each thread owns `rows` rows (t, t + kSmallThreads, ...) of the
-// block-diagonal matrix, their `width` (5 or 7) value slots and column
-// positions held in registers; x, r, p, the interface products and the
-// interface copy lists live in LDS.
+// block-diagonal matrix, their `width` (5 or 7) value slots, column
+// positions and r held in registers (the largest kernels, 6 rows of 5 and 5
+// of 7, spill 52 and 92 bytes a thread); x, p, the interface products and
+// the interface copy lists live in LDS.
 constexpr int kSmallThreads = 768;
 
 struct SmallMat {
@@ -29,7 +30,7 @@ struct SmallMat {
 
 inline size_t small_lds_bytes(int32_t n_loc, int32_t n_if, int32_t ngamma, int32_t n_copies)
 {
-    return sizeof(double) * (3 * (size_t)n_loc + (size_t)n_if + 2 * (kSmallThreads / 64) + 256) +
+    return sizeof(double) * (2 * (size_t)n_loc + (size_t)n_if + 2 * (kSmallThreads / 64) + 256) +
            sizeof(int32_t) * ((size_t)n_if + (size_t)ngamma + 1 + (size_t)n_copies);
 }
 // Rows per thread of the kernel for `rows_needed` rows of `width` slots, 0
